@@ -1,0 +1,79 @@
+"""ctypes binding of libmbc (include/mbc.h): argument marshalling only.
+
+Every step of the contraction runs in the library; this module only converts
+Python/torch arguments to pointers and sizes and raises on a non-zero status.
+Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libmbc.so")
+
+MBC_OK = 0
+OPS = {"proton": 0, "neutron": 1, "DI": 2, "DII": 3, "HE3_I": 4, "HE3_II": 5}
+SIGNS = {"exact": 0, "r2": 1}
+F64, F32C = 0, 1
+C128, C64 = 0, 1
+
+
+class MbcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmbc status {status}: {msg}")
+        self.status = status
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("snk_spin", ctypes.c_int32), ("src_spin", ctypes.c_int32),
+                ("sign_mode", ctypes.c_int32), ("symmetrise", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("n_corr", ctypes.c_int32), ("n_u", ctypes.c_int32),
+                ("n_d", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+                ("alg_flops_per_site", ctypes.c_double), ("exec_flops_per_site", ctypes.c_double),
+                ("in_bytes_per_site", ctypes.c_double)]
+
+
+_lib = None
+
+# exported symbols and their signatures: (name, restype, argtypes)
+_P, _I32, _I64, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = [
+    ("mbc_last_error", ctypes.c_char_p, []),
+    ("mbc_version", ctypes.c_char_p, []),
+    ("mbc_build_index_set", _I32, [ctypes.POINTER(OpDesc), _I32, ctypes.POINTER(_P)]),
+    ("mbc_index_set_dims", _I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                  ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    ("mbc_index_set_export", _I32, [_P] + [_P] * 8),
+    ("mbc_index_set_free", None, [_P]),
+    ("mbc_plan_create", _I32, [_P, _I32, _P, ctypes.POINTER(_P)]),
+    ("mbc_plan_get_stats", _I32, [_P, ctypes.POINTER(PlanStats)]),
+    ("mbc_plan_workspace_bytes", _I32, [_P, _I32, _I64, _I32, ctypes.POINTER(_SZ)]),
+    ("mbc_plan_destroy", None, [_P]),
+    ("mbc_contract", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
+    ("mbc_contract_backward", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    ("mbc_debug_eval_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, ctypes.POINTER(PlanStats)]),
+]
+
+
+def lib():
+    """The loaded library; raises if libmbc.so has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2201_04269_amd.build` (there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != MBC_OK:
+        raise MbcError(status, lib().mbc_last_error().decode())

@@ -1,0 +1,180 @@
+"""Python API over libmbc: index sets, plans, contract, backward, autograd.
+
+PyTorch provides device memory and the current stream only; every step of the
+correlator evaluation runs in libmbc's HIP kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+
+def _op_descs(ops):
+    arr = (B.OpDesc * len(ops))()
+    for i, od in enumerate(ops):
+        arr[i].op = B.OPS[od["op"]]
+        arr[i].snk_spin = int(od.get("snk_spin", 0))
+        arr[i].src_spin = int(od.get("src_spin", od.get("snk_spin", 0)))
+        arr[i].sign_mode = B.SIGNS[od.get("sign_mode", "exact")]
+        arr[i].symmetrise = 1 if od.get("symmetrise", True) else 0
+    return arr
+
+
+class IndexSet:
+    """Index set I and exact weights of a batch of correlators (host, integer).
+
+    ``ops``: list of dicts with keys op ("proton", "neutron", "DI", "DII",
+    "HE3_I", "HE3_II"), snk_spin, src_spin, sign_mode ("exact"/"r2"),
+    symmetrise (bool).  Mirrors mbc_build_index_set.
+    """
+
+    def __init__(self, ops):
+        self.ops = [dict(o) for o in ops]
+        h = ctypes.c_void_p()
+        descs = _op_descs(self.ops)
+        B.check(B.lib().mbc_build_index_set(descs, len(self.ops), ctypes.byref(h)))
+        self._h = h
+        nu, nd, nc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nnz = ctypes.c_int64()
+        B.check(B.lib().mbc_index_set_dims(h, ctypes.byref(nu), ctypes.byref(nd), ctypes.byref(nnz),
+                                           ctypes.byref(nc)))
+        self.n_u, self.n_d, self.nnz, self.n_corr = nu.value, nd.value, nnz.value, nc.value
+        self._export = None
+
+    def export(self):
+        """dict of numpy arrays: snk_u, src_u, snk_d, src_d, corr_id, w_re, w_im, w_den."""
+        if self._export is None:
+            n, nu, nd = self.nnz, self.n_u, self.n_d
+            out = dict(snk_u=np.zeros((n, nu), np.int32), src_u=np.zeros((n, nu), np.int32),
+                       snk_d=np.zeros((n, nd), np.int32), src_d=np.zeros((n, nd), np.int32),
+                       corr_id=np.zeros(n, np.int32), w_re=np.zeros(n, np.int64),
+                       w_im=np.zeros(n, np.int64), w_den=np.zeros(self.n_corr, np.int64))
+            ptr = [out[k].ctypes.data_as(ctypes.c_void_p) for k in
+                   ("snk_u", "src_u", "snk_d", "src_d", "corr_id", "w_re", "w_im", "w_den")]
+            B.check(B.lib().mbc_index_set_export(self._h, *ptr))
+            self._export = out
+        return self._export
+
+    def weights(self):
+        """Exact weights as complex128 (num / den)."""
+        e = self.export()
+        den = e["w_den"][e["corr_id"]].astype(float)
+        return (e["w_re"].astype(float) + 1j * e["w_im"].astype(float)) / den
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            B.lib().mbc_index_set_free(h)
+            self._h = None
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Compiled evaluation schedule of an index set, resident on the device."""
+
+    def __init__(self, iset, precision="f64", stream=None):
+        self.iset = iset
+        self.precision = precision
+        prec = {"f64": B.F64, "f32c": B.F32C}[precision]
+        h = ctypes.c_void_p()
+        B.check(B.lib().mbc_plan_create(iset._h, prec, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        st = B.PlanStats()
+        B.check(B.lib().mbc_plan_get_stats(h, ctypes.byref(st)))
+        self.stats = {k: getattr(st, k) for k, _ in B.PlanStats._fields_}
+
+    @property
+    def n_corr(self):
+        return self.iset.n_corr
+
+    def workspace_bytes(self, T, V, backward=False):
+        n = ctypes.c_size_t()
+        B.check(B.lib().mbc_plan_workspace_bytes(self._h, int(T), int(V), 1 if backward else 0,
+                                                 ctypes.byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            B.lib().mbc_plan_destroy(h)
+            self._h = None
+
+
+def _check_S(S_u, S_d):
+    for S in (S_u, S_d):
+        if not (S.is_cuda and S.is_contiguous() and S.dim() == 4 and S.shape[-2:] == (12, 12)):
+            raise ValueError("S must be a contiguous CUDA tensor [T, V, 12, 12]")
+        if S.dtype not in (torch.complex128, torch.complex64):
+            raise ValueError("S must be complex128 or complex64")
+    if S_u.shape != S_d.shape or S_u.dtype != S_d.dtype:
+        raise ValueError("S_u and S_d must have the same shape and dtype")
+    return B.C128 if S_u.dtype == torch.complex128 else B.C64
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def contract(plan, S_u, S_d, W=None, stream=None):
+    """C[c, t] (complex128 [n_corr, T]) of eq. 1 for propagators [T, V, 12, 12]."""
+    dt = _check_S(S_u, S_d)
+    T, V = S_u.shape[:2]
+    if W is not None:
+        if W.dtype != torch.complex128 or not W.is_cuda or W.numel() != plan.iset.nnz:
+            raise ValueError("W must be a CUDA complex128 tensor of nnz entries")
+        W = W.contiguous()
+    C = torch.empty((plan.n_corr, T), dtype=torch.complex128, device=S_u.device)
+    nbytes = plan.workspace_bytes(T, V)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=S_u.device)
+    B.check(B.lib().mbc_contract(plan._h, _ptr(S_u), _ptr(S_d), dt, int(T), int(V), _ptr(W), _ptr(C),
+                                 _ptr(ws), ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+    return C
+
+
+def contract_backward(plan, S_u, S_d, W, grad_C, need_W=True, need_S=True, stream=None):
+    """(grad_W, grad_S_u, grad_S_d) of mbc_contract_backward (None where not requested)."""
+    dt = _check_S(S_u, S_d)
+    T, V = S_u.shape[:2]
+    grad_C = grad_C.to(torch.complex128).contiguous()
+    gW = torch.empty(plan.iset.nnz, dtype=torch.complex128, device=S_u.device) if need_W else None
+    gSu = torch.empty_like(S_u) if need_S else None
+    gSd = torch.empty_like(S_d) if need_S else None
+    nbytes = plan.workspace_bytes(T, V, backward=True)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=S_u.device)
+    if W is not None:
+        W = W.contiguous()
+    B.check(B.lib().mbc_contract_backward(plan._h, _ptr(S_u), _ptr(S_d), dt, int(T), int(V), _ptr(W),
+                                          _ptr(grad_C), _ptr(gW), _ptr(gSu), _ptr(gSd), _ptr(ws),
+                                          ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+    return gW, gSu, gSd
+
+
+class Contract(torch.autograd.Function):
+    """C = Contract.apply(S_u, S_d, W, plan): differentiable in S_u, S_d and W.
+
+    The backward is libmbc's adjoint kernels (Jacobi's formula through the
+    Laplace recursion for dS, per-entry site sums for dW), with every minor
+    recomputed rather than stored.
+    """
+
+    @staticmethod
+    def forward(ctx, S_u, S_d, W, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(S_u, S_d, W)
+        return contract(plan, S_u, S_d, W)
+
+    @staticmethod
+    def backward(ctx, grad_C):
+        S_u, S_d, W = ctx.saved_tensors
+        need_S = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        need_W = ctx.needs_input_grad[2]
+        gW, gSu, gSd = contract_backward(ctx.plan, S_u, S_d, W, grad_C, need_W=need_W, need_S=need_S)
+        return (gSu if ctx.needs_input_grad[0] else None,
+                gSd if ctx.needs_input_grad[1] else None,
+                gW if need_W else None, None)

@@ -1,0 +1,316 @@
+// C ABI of libmbc (see include/mbc.h): argument validation, error reporting,
+// plan upload and the orchestration of the device kernels.
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+#include <exception>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/mbc_debug.h"
+#include "kernels.hpp"
+#include "mbc_internal.hpp"
+
+namespace mbc {
+
+mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, const double* S_d, int T,
+                      int64_t V, const double* W, double* C, mbc_plan_stats* stats);
+
+namespace {
+thread_local std::string g_err;
+
+mbc_status fail(mbc_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+mbc_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return MBC_ERR_HIP;
+}
+
+#define MBC_HIP(call)                                 \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+template <typename F>
+mbc_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(MBC_ERR_NOMEM, "host allocation failed");
+  } catch (const std::domain_error& e) {
+    return fail(MBC_ERR_UNSUPPORTED, e.what());
+  } catch (const std::invalid_argument& e) {
+    return fail(MBC_ERR_INVALID, e.what());
+  } catch (const std::exception& e) {
+    return fail(MBC_ERR_INTERNAL, e.what());
+  } catch (...) {
+    return fail(MBC_ERR_INTERNAL, "unknown exception");
+  }
+}
+
+// True if p is device memory (or managed) accessible from the current device.
+bool is_device_ptr(const void* p) {
+  if (p == nullptr) return false;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <typename T>
+mbc_status upload(const std::vector<T>& v, T** out, hipStream_t st) {
+  *out = nullptr;
+  if (v.empty()) return MBC_OK;
+  MBC_HIP(hipMalloc(reinterpret_cast<void**>(out), v.size() * sizeof(T)));
+  MBC_HIP(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return MBC_OK;
+}
+
+void free_device(PlanDevice& d) {
+  void* ptrs[] = {d.corr, d.tiles, d.ops, d.meta, d.src_cu, d.src_cd, d.tabs, d.perm, d.w_exact};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  d = PlanDevice();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct FwdWorkspace {
+  size_t w_plan = 0, partial = 0, total = 0;
+};
+
+FwdWorkspace fwd_workspace(const PlanHost& h, const Launch& L, bool user_w) {
+  FwdWorkspace w;
+  const size_t csz = h.precision == MBC_F64 ? 16 : 8;
+  w.w_plan = user_w ? align256(size_t(h.nnz) * csz) : 0;
+  w.partial = align256(size_t(h.n_tiles) * size_t(L.T) * size_t(L.nc) * 16);
+  w.total = w.w_plan + w.partial;
+  return w;
+}
+
+mbc_status check_common(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
+                        int32_t T, int64_t V) {
+  if (!p) return fail(MBC_ERR_INVALID, "plan is NULL");
+  if (T <= 0) return fail(MBC_ERR_INVALID, "T must be positive");
+  if (V <= 0) return fail(MBC_ERR_INVALID, "sites_per_t must be positive");
+  if (s_dtype != MBC_C128 && s_dtype != MBC_C64) return fail(MBC_ERR_INVALID, "unknown s_dtype");
+  if (!is_device_ptr(S_u) || !is_device_ptr(S_d))
+    return fail(MBC_ERR_INVALID, "S_u and S_d must be device pointers");
+  if (!aligned16(S_u) || !aligned16(S_d)) return fail(MBC_ERR_INVALID, "S_u/S_d must be 16-byte aligned");
+  return MBC_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace mbc
+
+using namespace mbc;
+
+extern "C" {
+
+const char* mbc_last_error(void) { return g_err.c_str(); }
+
+const char* mbc_version(void) { return "mbc 0.1 (gfx950)"; }
+
+mbc_status mbc_build_index_set(const mbc_op_desc* ops, int32_t n_corr, mbc_index_set** out) {
+  if (!ops || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (n_corr < 1) return fail(MBC_ERR_INVALID, "n_corr must be >= 1");
+  *out = nullptr;
+  return guarded([&]() {
+    auto* s = new mbc_index_set();
+    try {
+      build_index_set(ops, n_corr, &s->s);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_index_set_dims(const mbc_index_set* s, int32_t* n_u, int32_t* n_d, int64_t* nnz,
+                              int32_t* n_corr) {
+  if (!s) return fail(MBC_ERR_INVALID, "index set is NULL");
+  if (n_u) *n_u = s->s.n_u;
+  if (n_d) *n_d = s->s.n_d;
+  if (nnz) *nnz = int64_t(s->s.entries.size());
+  if (n_corr) *n_corr = s->s.n_corr;
+  return MBC_OK;
+}
+
+mbc_status mbc_index_set_export(const mbc_index_set* s, int32_t* snk_u, int32_t* src_u, int32_t* snk_d,
+                                int32_t* src_d, int32_t* corr_id, int64_t* w_num_re, int64_t* w_num_im,
+                                int64_t* w_den) {
+  if (!s) return fail(MBC_ERR_INVALID, "index set is NULL");
+  const int nu = s->s.n_u, nd = s->s.n_d;
+  int64_t k = 0;
+  for (const Entry& e : s->s.entries) {
+    for (int i = 0; i < nu; ++i) {
+      if (snk_u) snk_u[k * nu + i] = e.ru.v[i];
+      if (src_u) src_u[k * nu + i] = e.cu.v[i];
+    }
+    for (int i = 0; i < nd; ++i) {
+      if (snk_d) snk_d[k * nd + i] = e.rd.v[i];
+      if (src_d) src_d[k * nd + i] = e.cd.v[i];
+    }
+    if (corr_id) corr_id[k] = e.corr;
+    if (w_num_re) w_num_re[k] = e.w_re;
+    if (w_num_im) w_num_im[k] = e.w_im;
+    ++k;
+  }
+  if (w_den)
+    for (int c = 0; c < s->s.n_corr; ++c) w_den[c] = s->s.w_den[c];
+  return MBC_OK;
+}
+
+void mbc_index_set_free(mbc_index_set* s) { delete s; }
+
+mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stream, mbc_plan** out) {
+  if (!s || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (precision != MBC_F64 && precision != MBC_F32C) return fail(MBC_ERR_INVALID, "unknown precision");
+  *out = nullptr;
+  return guarded([&]() -> mbc_status {
+    auto* p = new mbc_plan();
+    mbc_status st = MBC_OK;
+    try {
+      compile_plan(s->s, precision, &p->h);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return hip_fail(hipGetLastError(), "hipGetDevice");
+    }
+    const PlanHost& h = p->h;
+    std::vector<float> wf;
+    if ((st = upload(h.corr, &p->d.corr, hs)) != MBC_OK ||
+        (st = upload(h.tiles, &p->d.tiles, hs)) != MBC_OK ||
+        (st = upload(h.ops, &p->d.ops, hs)) != MBC_OK || (st = upload(h.meta, &p->d.meta, hs)) != MBC_OK ||
+        (st = upload(h.src_cu, &p->d.src_cu, hs)) != MBC_OK ||
+        (st = upload(h.src_cd, &p->d.src_cd, hs)) != MBC_OK ||
+        (st = upload(h.tabs, &p->d.tabs, hs)) != MBC_OK || (st = upload(h.perm, &p->d.perm, hs)) != MBC_OK) {
+      free_device(p->d);
+      delete p;
+      return st;
+    }
+    if (h.precision == MBC_F64) {
+      double* w = nullptr;
+      st = upload(h.w_exact, &w, hs);
+      p->d.w_exact = w;
+    } else {
+      wf.assign(h.w_exact.begin(), h.w_exact.end());
+      float* w = nullptr;
+      st = upload(wf, &w, hs);
+      p->d.w_exact = w;
+    }
+    hipError_t e = hipStreamSynchronize(hs);
+    if (st == MBC_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    if (st != MBC_OK) {
+      free_device(p->d);
+      delete p;
+      return st;
+    }
+    *out = p;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out) {
+  if (!p || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  out->nnz = p->h.nnz;
+  out->n_corr = p->h.n_corr;
+  out->n_u = p->h.n_u;
+  out->n_d = p->h.n_d;
+  out->precision = p->h.precision;
+  out->n_tiles = p->h.n_tiles;
+  out->threads = p->h.threads;
+  out->lds_bytes = p->h.lds_bytes;
+  out->alg_flops_per_site = p->h.alg_flops_per_site;
+  out->exec_flops_per_site = p->h.exec_flops_per_site;
+  out->in_bytes_per_site = 2.0 * 144.0 * 16.0;
+  return MBC_OK;
+}
+
+mbc_status mbc_plan_workspace_bytes(const mbc_plan* p, int32_t T, int64_t sites_per_t, int32_t backward,
+                                    size_t* bytes) {
+  if (!p || !bytes) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (T <= 0 || sites_per_t <= 0) return fail(MBC_ERR_INVALID, "T and sites_per_t must be positive");
+  if (backward) return fail(MBC_ERR_UNSUPPORTED, "backward not available in this build");
+  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+  *bytes = fwd_workspace(p->h, L, true).total;
+  return MBC_OK;
+}
+
+void mbc_plan_destroy(mbc_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  free_device(p->d);
+  delete p;
+}
+
+mbc_status mbc_contract(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype, int32_t T,
+                        int64_t sites_per_t, const double* W, double* C, void* workspace, size_t ws_bytes,
+                        void* stream) {
+  mbc_status st = check_common(p, S_u, S_d, s_dtype, T, sites_per_t);
+  if (st != MBC_OK) return st;
+  if (!is_device_ptr(C)) return fail(MBC_ERR_INVALID, "C must be a device pointer");
+  if (W && !is_device_ptr(W)) return fail(MBC_ERR_INVALID, "W must be a device pointer or NULL");
+  if (W && !aligned16(W)) return fail(MBC_ERR_INVALID, "W must be 16-byte aligned");
+  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+  const FwdWorkspace ws = fwd_workspace(p->h, L, W != nullptr);
+  if (ws.total > 0 && (!workspace || !is_device_ptr(workspace)))
+    return fail(MBC_ERR_INVALID, "workspace must be a device pointer");
+  if (ws_bytes < ws.total) return fail(MBC_ERR_INVALID, "workspace too small");
+  if (!aligned16(workspace)) return fail(MBC_ERR_INVALID, "workspace must be 16-byte aligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
+  char* wsb = static_cast<char*>(workspace);
+  const void* W_plan = p->d.w_exact;
+  if (W) {
+    MBC_HIP(launch_gather_w(p, W, wsb, hs));
+    W_plan = wsb;
+  }
+  double* partial = reinterpret_cast<double*>(wsb + ws.w_plan);
+  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, hs));
+  MBC_HIP(launch_reduce(p, L, partial, C, hs));
+  return MBC_OK;
+}
+
+mbc_status mbc_contract_backward(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
+                                 int32_t T, int64_t sites_per_t, const double* W, const double* grad_C,
+                                 double* grad_W, void* grad_S_u, void* grad_S_d, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+  (void)W; (void)grad_C; (void)grad_W; (void)grad_S_u; (void)grad_S_d; (void)workspace; (void)ws_bytes;
+  (void)stream;
+  mbc_status st = check_common(p, S_u, S_d, s_dtype, T, sites_per_t);
+  if (st != MBC_OK) return st;
+  return fail(MBC_ERR_UNSUPPORTED, "backward not available in this build");
+}
+
+mbc_status mbc_debug_eval_host(const mbc_index_set* s, int32_t precision, const double* S_u,
+                               const double* S_d, int32_t T, int64_t sites_per_t, const double* W,
+                               double* C, mbc_plan_stats* stats) {
+  if (!s || !S_u || !S_d || !C) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (T <= 0 || sites_per_t <= 0) return fail(MBC_ERR_INVALID, "T and sites_per_t must be positive");
+  if (precision != MBC_F64 && precision != MBC_F32C) return fail(MBC_ERR_INVALID, "unknown precision");
+  return guarded([&]() { return debug_eval(s, precision, S_u, S_d, T, sites_per_t, W, C, stats); });
+}
+
+}  // extern "C"

@@ -1,0 +1,413 @@
+// HIP kernels for gfx950 (CDNA4): forward correlator contraction, weight
+// gather, and the per-timeslice FP64 reduction.
+//
+// Forward kernel (one workgroup = one tile of sink keys x one chunk of sites
+// of one timeslice):
+//   1. stage the tile's row program, per-sink-key metadata and weights W in
+//      LDS once;
+//   2. for each site of the chunk: load S_u(x), S_d(x) (12x12 complex each)
+//      into LDS, then build the tile's compound-matrix rows level by level
+//      with the Laplace expansion along the first row (every thread takes
+//      (row, column-subset) work items of the level; one barrier per level);
+//   3. factor-tree leaves: each thread owns source keys s and, for every sink
+//      key b of the tile, accumulates L_s += W[b,s] Dd[r_d(b), c_d(s)]; at the
+//      end of a run of equal u-tuples it adds Du[r_u, c_u(s)] L_s to its
+//      compensated (TwoSum) accumulator;
+//   4. after the chunk, a fixed-order FP64 workgroup reduction writes the
+//      chunk's partial sum for the tile.
+// No MFMA: the work is gathers and small-determinant recursions, not a dense
+// contraction.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace mbc {
+
+namespace {
+
+constexpr int kNT = 256;  // threads per workgroup
+
+template <typename R>
+struct cx;
+template <>
+struct cx<double> {
+  using T = double2;
+};
+template <>
+struct cx<float> {
+  using T = float2;
+};
+
+template <typename C>
+__device__ __forceinline__ C cmake(decltype(C::x) a, decltype(C::x) b) {
+  C r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+
+// acc + a*b and acc - a*b (complex, FMA-contracted)
+template <typename C>
+__device__ __forceinline__ C cmac(C a, C b, C acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+template <typename C>
+__device__ __forceinline__ C cmsub(C a, C b, C acc) {
+  acc.x = fma(-a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(-a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = fma(a.x, b.x, -a.y * b.y);
+  r.y = fma(a.x, b.y, a.y * b.x);
+  return r;
+}
+
+// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no reassociation).
+template <typename R>
+__device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
+  s = a + b;
+  R bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated complex accumulator.
+template <typename R>
+struct CompAcc {
+  R hx = 0, lx = 0, hy = 0, ly = 0;
+  __device__ __forceinline__ void add(R x, R y) {
+    R s, e;
+    two_sum(hx, x, s, e);
+    hx = s;
+    lx += e;
+    two_sum(hy, y, s, e);
+    hy = s;
+    ly += e;
+  }
+};
+
+template <typename C>
+__device__ __forceinline__ C load_site(const void* base, int c64, int64_t idx) {
+  C r;
+  if (c64) {
+    const float2 v = reinterpret_cast<const float2*>(base)[idx];
+    r.x = v.x;
+    r.y = v.y;
+  } else {
+    const double2 v = reinterpret_cast<const double2*>(base)[idx];
+    r.x = v.x;
+    r.y = v.y;
+  }
+  return r;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block id mod 8).  Map
+// them so that each XCD receives a contiguous range of logical ids, which
+// keeps all tiles of a chunk of sites (same propagators) in one L2.
+__device__ __forceinline__ int xcd_linear(int bid, int nb) {
+  const int per = nb / 8, rem = nb % 8;
+  const int xcd = bid % 8, loc = bid / 8;
+  return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+}
+
+struct FwdArgs {
+  const int32_t* corr;
+  const int32_t* tiles;
+  const int32_t* ops;
+  const int32_t* meta;
+  const int32_t* src_cu;
+  const int32_t* src_cd;
+  const uint16_t* tabs;
+  const void* W;     // plan-ordered weights, plan precision
+  const void* S_u;
+  const void* S_d;
+  int s_c64;
+  int n_tiles;
+  int T;
+  int64_t V;
+  int chunk;
+  int nc;
+  double* partial;   // [n_tiles][T][nc][2]
+};
+
+// Builds the rows of one level phase: items are (row op, column subset) pairs.
+template <typename C>
+__device__ __forceinline__ void row_phase(const int32_t* sOps, int oa, int ob, const C* sS,
+                                          C* sR, const uint16_t* __restrict__ tabs) {
+  const int32_t* last = sOps + (ob - 1) * kOpInts;
+  const int items = last[7] + last[6];
+  for (int w = threadIdx.x; w < items; w += kNT) {
+    int o = oa;
+    while (o + 1 < ob && sOps[(o + 1) * kOpInts + 7] <= w) ++o;
+    const int32_t* op = sOps + o * kOpInts;
+    const int f = op[0], k = op[1], r0 = op[2], in = op[3], out = op[4], toff = op[5];
+    const int i = w - op[7];
+    const C* Sf = sS + 144 * f;
+    const C* srow = Sf + 12 * r0;
+    C val;
+    if (k == 1) {
+      val = srow[tabs[toff + i]];
+    } else {
+      const uint16_t* tb = tabs + toff + i * k;
+      const C* inr = (k == 2) ? (Sf + 12 * in) : (sR + in);
+      val = cmake<C>(0, 0);
+      for (int j = 0; j < k; ++j) {
+        const int e = tb[j];
+        const C x = srow[e & 15];
+        const C y = inr[e >> 4];
+        val = (j & 1) ? cmsub(x, y, val) : cmac(x, y, val);
+      }
+    }
+    sR[out + i] = val;
+  }
+}
+
+template <typename R, int MAXS>
+__global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
+  using C = typename cx<R>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
+  const int tile = lin % a.n_tiles;
+  const int tc = lin / a.n_tiles;  // t * nc + chunk
+  const int32_t* tr = a.tiles + tile * kTileInts;
+  const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nops = tr[4];
+  const int meta0 = tr[5], row_units = tr[6], nph = tr[7];
+  const int32_t* cr = a.corr + corr * kCorrInts;
+  const int n_src = cr[0], src_off = cr[1];
+
+  C* sS = reinterpret_cast<C*>(smem);
+  C* sW = sS + 288;
+  C* sR = sW + B * n_src;
+  int32_t* sOps = reinterpret_cast<int32_t*>(sR + row_units);
+  int32_t* sMeta = sOps + nops * kOpInts;
+
+  for (int i = tid; i < nops * kOpInts; i += kNT) sOps[i] = a.ops[op0 * kOpInts + i];
+  for (int i = tid; i < B * kMetaInts; i += kNT) sMeta[i] = a.meta[meta0 * kMetaInts + i];
+  const C* Wg = reinterpret_cast<const C*>(a.W) + w_off;
+  for (int i = tid; i < B * n_src; i += kNT) sW[i] = Wg[i];
+
+  int cu[MAXS], cd[MAXS];
+#pragma unroll
+  for (int m = 0; m < MAXS; ++m) {
+    const int s = tid + kNT * m;
+    cu[m] = s < n_src ? a.src_cu[src_off + s] : 0;
+    cd[m] = s < n_src ? a.src_cd[src_off + s] : 0;
+  }
+
+  const int t = tc / a.nc, ch = tc % a.nc;
+  const int64_t v0 = int64_t(ch) * a.chunk;
+  const int64_t v1 = (v0 + a.chunk < a.V) ? v0 + a.chunk : a.V;
+  CompAcc<R> acc;
+
+  for (int64_t v = v0; v < v1; ++v) {
+    __syncthreads();  // previous site's rows are no longer read
+    const int64_t site = int64_t(t) * a.V + v;
+    for (int i = tid; i < 288; i += kNT) {
+      const void* base = i < 144 ? a.S_u : a.S_d;
+      sS[i] = load_site<C>(base, a.s_c64, site * 144 + (i % 144));
+    }
+    __syncthreads();
+    for (int ph = 0; ph < nph; ++ph) {
+      row_phase<C>(sOps, tr[8 + ph], tr[9 + ph], sS, sR, a.tabs);
+      __syncthreads();
+    }
+    C L[MAXS];
+#pragma unroll
+    for (int m = 0; m < MAXS; ++m) L[m] = cmake<C>(0, 0);
+    for (int b = 0; b < B; ++b) {
+      const int32_t* mb = sMeta + b * kMetaInts;
+      const C* Wb = sW + b * n_src;
+      const C* Dd = sR + mb[1];
+#pragma unroll
+      for (int m = 0; m < MAXS; ++m) {
+        const int s = tid + kNT * m;
+        if (s < n_src) L[m] = cmac(Wb[s], Dd[cd[m]], L[m]);
+      }
+      if (mb[2]) {
+        const C* Du = sR + mb[0];
+#pragma unroll
+        for (int m = 0; m < MAXS; ++m) {
+          const int s = tid + kNT * m;
+          if (s < n_src) {
+            const C p = cmul(Du[cu[m]], L[m]);
+            acc.add(p.x, p.y);
+          }
+          L[m] = cmake<C>(0, 0);
+        }
+      }
+    }
+  }
+
+  // fixed-order FP64 reduction over the workgroup
+  double rx = double(acc.hx) + double(acc.lx);
+  double ry = double(acc.hy) + double(acc.ly);
+  for (int off = 32; off > 0; off >>= 1) {
+    rx += __shfl_xor(rx, off);
+    ry += __shfl_xor(ry, off);
+  }
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane == 0) {
+    red[2 * wave] = rx;
+    red[2 * wave + 1] = ry;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sx = 0, sy = 0;
+    for (int w = 0; w < kNT / 64; ++w) {
+      sx += red[2 * w];
+      sy += red[2 * w + 1];
+    }
+    double* out = a.partial + 2 * ((int64_t(tile) * a.T + t) * a.nc + ch);
+    out[0] = sx;
+    out[1] = sy;
+  }
+}
+
+template <typename R>
+__global__ void gather_w_kernel(const double2* __restrict__ Wu, const int64_t* __restrict__ perm,
+                                typename cx<R>::T* __restrict__ Wp, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 v = Wu[perm[i]];
+    typename cx<R>::T r;
+    r.x = R(v.x);
+    r.y = R(v.y);
+    Wp[i] = r;
+  }
+}
+
+// One workgroup per (correlator, timeslice): strided per-thread compensated
+// sums in a fixed order, then a fixed-order tree.
+__global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__ corr, int T, int nc,
+                                                     const double* __restrict__ partial,
+                                                     double* __restrict__ C) {
+  const int c = blockIdx.x / T, t = blockIdx.x % T;
+  const int32_t* cr = corr + c * kCorrInts;
+  const int tb = cr[3], te = cr[4];
+  const int64_t n = int64_t(te - tb) * nc;
+  CompAcc<double> acc;
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    const int64_t tile = tb + j / nc, ch = j % nc;
+    const double* p = partial + 2 * ((tile * T + t) * nc + ch);
+    acc.add(p[0], p[1]);
+  }
+  __shared__ double sx[256], sy[256];
+  sx[threadIdx.x] = acc.hx + acc.lx;
+  sy[threadIdx.x] = acc.hy + acc.ly;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s) {
+      sx[threadIdx.x] += sx[threadIdx.x + s];
+      sy[threadIdx.x] += sy[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    C[2 * (int64_t(c) * T + t)] = sx[0];
+    C[2 * (int64_t(c) * T + t) + 1] = sy[0];
+  }
+}
+
+template <typename R, int MAXS>
+hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  auto k = fwd_kernel<R, MAXS>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(nblocks), dim3(kNT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  const int ms = p->h.maxs;
+  if (ms <= 1) return launch_fwd_t<R, 1>(p, a, nblocks, lds, st);
+  if (ms <= 2) return launch_fwd_t<R, 2>(p, a, nblocks, lds, st);
+  if (ms <= 4) return launch_fwd_t<R, 4>(p, a, nblocks, lds, st);
+  if (ms <= 8) return launch_fwd_t<R, 8>(p, a, nblocks, lds, st);
+  if (ms <= 16) return launch_fwd_t<R, 16>(p, a, nblocks, lds, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+Launch forward_launch_shape(const PlanHost& h, int T, int64_t V) {
+  Launch L;
+  L.T = T;
+  L.V = V;
+  // about 16k workgroups in flight over the grid, at least 1 site each
+  const double target = 16384.0;
+  const double total = double(T) * double(V) * std::max(1, h.n_tiles);
+  int64_t chunk = int64_t(total / target);
+  if (chunk < 1) chunk = 1;
+  if (chunk > V) chunk = V;
+  L.chunk = int(chunk);
+  L.nc = int((V + chunk - 1) / chunk);
+  return L;
+}
+
+hipError_t launch_gather_w(const mbc_plan* p, const double* W_user, void* W_plan, hipStream_t st) {
+  const int64_t n = p->h.nnz;
+  if (n == 0) return hipSuccess;
+  const int nb = int((n + 255) / 256);
+  if (p->h.precision == MBC_F64)
+    hipLaunchKernelGGL(gather_w_kernel<double>, dim3(nb), dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(W_user), p->d.perm,
+                       reinterpret_cast<double2*>(W_plan), n);
+  else
+    hipLaunchKernelGGL(gather_w_kernel<float>, dim3(nb), dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(W_user), p->d.perm,
+                       reinterpret_cast<float2*>(W_plan), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64,
+                          const Launch& L, const void* W_plan, double* partial, hipStream_t st) {
+  if (p->h.n_tiles == 0) return hipSuccess;
+  FwdArgs a;
+  a.corr = p->d.corr;
+  a.tiles = p->d.tiles;
+  a.ops = p->d.ops;
+  a.meta = p->d.meta;
+  a.src_cu = p->d.src_cu;
+  a.src_cd = p->d.src_cd;
+  a.tabs = p->d.tabs;
+  a.W = W_plan;
+  a.S_u = S_u;
+  a.S_d = S_d;
+  a.s_c64 = s_c64;
+  a.n_tiles = p->h.n_tiles;
+  a.T = L.T;
+  a.V = L.V;
+  a.chunk = L.chunk;
+  a.nc = L.nc;
+  a.partial = partial;
+  const int64_t nb = int64_t(p->h.n_tiles) * L.T * L.nc;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = size_t(p->h.lds_bytes);
+  if (p->h.precision == MBC_F64) return launch_fwd_r<double>(p, a, int(nb), lds, st);
+  return launch_fwd_r<float>(p, a, int(nb), lds, st);
+}
+
+hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
+                         hipStream_t st) {
+  const int nb = p->h.n_corr * L.T;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, st, p->d.corr, L.T, L.nc, partial, C);
+  return hipGetLastError();
+}
+
+}  // namespace mbc

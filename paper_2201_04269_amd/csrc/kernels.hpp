@@ -1,0 +1,30 @@
+// Host-side launchers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "mbc_internal.hpp"
+
+namespace mbc {
+
+struct Launch {
+  int T = 0;
+  int64_t V = 0;     // sites per timeslice
+  int chunk = 1;     // sites per workgroup (one timeslice)
+  int nc = 1;        // chunks per timeslice
+};
+
+Launch forward_launch_shape(const PlanHost& h, int T, int64_t V);
+
+// W_plan[i] = W_user[perm[i]] in the plan's precision.
+hipError_t launch_gather_w(const mbc_plan* p, const double* W_user, void* W_plan, hipStream_t st);
+
+// Per-tile, per-chunk partial sums of the correlator: partial[tile][T][nc] complex128.
+hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64,
+                          const Launch& L, const void* W_plan, double* partial, hipStream_t st);
+
+// C[corr][t] = fixed-order FP64 sum of the partials of the correlator's tiles.
+hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
+                         hipStream_t st);
+
+}  // namespace mbc

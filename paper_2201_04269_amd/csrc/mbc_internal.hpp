@@ -1,0 +1,113 @@
+// Internal structures shared by the host-side builder/planner and the HIP
+// kernels.  Nothing here is part of the public ABI (include/mbc.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mbc.h"
+
+namespace mbc {
+
+constexpr int kMaxQuarks = 6;  // per flavour
+
+// A sorted (canonical) or written-order (raw) tuple of quark indices.
+struct Key {
+  uint8_t n = 0;
+  uint8_t v[kMaxQuarks] = {0, 0, 0, 0, 0, 0};
+};
+bool operator<(const Key& a, const Key& b);
+bool operator==(const Key& a, const Key& b);
+
+struct Entry {
+  Key ru, cu, rd, cd;  // sink u, source u, sink d, source d
+  int64_t w_re = 0, w_im = 0;
+  int32_t corr = 0;
+};
+
+struct IndexSet {
+  int n_u = 0, n_d = 0, n_corr = 0;
+  bool canonical = true;
+  std::vector<Entry> entries;         // grouped by correlator
+  std::vector<int64_t> corr_begin;    // [n_corr + 1]
+  std::vector<int64_t> w_den;         // [n_corr]
+};
+
+void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
+
+// ---------------------------------------------------------------------------
+// Plan layout (all int32 unless noted), mirrored to the device.
+//
+// Correlator record (kCorrInts ints):
+//   [0] n_src        source keys (c_u, c_d) of the correlator
+//   [1] src_off      offset into src_cu / src_cd
+//   [2] n_snk        sink keys
+//   [3] tile_begin   first tile of the correlator; [4] tile_end
+//   [5] entry_begin  first index-set entry of the correlator
+//   [8 + 2*(6*f + k-1)]     ncol[f][k]   columns (k-subsets) at level k, flavour f
+//   [8 + 2*(6*f + k-1) + 1] tab_off[f][k] offset of the level's column table
+// Column table of level k >= 2: ncol*k uint16 entries (sub << 4) | col, the k
+//   terms of the expansion along the first row; col = C_j, sub = index of
+//   C \ C_j in level k-1 (for k = 2: the remaining column number itself).
+//   Level 1: ncol entries, the column numbers.
+// Tile record (kTileInts ints):
+//   [0] corr [1] B (sink keys) [2] w_off (complex units into the plan-ordered W)
+//   [3] op_begin [4] n_ops [5] meta_off [6] row_lds (complex units of row slots)
+//   [7] n_phases [8 .. 8+kMaxPhases] phase boundaries (op indices, relative)
+//   [16] snk_begin (index of the tile's first sink key in plan order)
+// Row op (kOpInts ints): flav, level, r0, in, out, tab_off, ncol, item_begin
+//   in: the S row r1 for level 2, the parent row's slot for level >= 3.
+//   out: slot (complex offset inside the row area).
+// Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
+// ---------------------------------------------------------------------------
+constexpr int kCorrInts = 40;
+constexpr int kTileInts = 20;
+constexpr int kOpInts = 8;
+constexpr int kMetaInts = 4;
+constexpr int kMaxPhases = 7;
+
+struct PlanHost {
+  int n_u = 0, n_d = 0, n_corr = 0, precision = MBC_F64;
+  int64_t nnz = 0;
+  int threads = 256;
+  int maxs = 1;          // max source keys per thread
+  int max_b = 0;         // max sink keys per tile
+  int max_ops = 0;       // max row ops per tile
+  int64_t lds_bytes = 0; // dynamic LDS of the forward kernel
+  int n_tiles = 0;
+  std::vector<int32_t> corr, tiles, ops, meta, src_cu, src_cd;
+  std::vector<uint16_t> tabs;
+  std::vector<int64_t> perm;      // plan-ordered W slot -> index-set entry
+  std::vector<double> w_exact;    // plan-ordered exact W (re, im)
+  double alg_flops_per_site = 0, exec_flops_per_site = 0;
+};
+
+// Compiles a plan; throws std::invalid_argument / std::runtime_error.
+void compile_plan(const IndexSet& s, int precision, PlanHost* out);
+
+struct PlanDevice {
+  int32_t* corr = nullptr;
+  int32_t* tiles = nullptr;
+  int32_t* ops = nullptr;
+  int32_t* meta = nullptr;
+  int32_t* src_cu = nullptr;
+  int32_t* src_cd = nullptr;
+  uint16_t* tabs = nullptr;
+  int64_t* perm = nullptr;
+  void* w_exact = nullptr;  // plan precision complex
+};
+
+void set_error(const std::string& msg);
+
+}  // namespace mbc
+
+struct mbc_index_set {
+  mbc::IndexSet s;
+};
+
+struct mbc_plan {
+  mbc::PlanHost h;
+  mbc::PlanDevice d;
+  int device = 0;
+};
