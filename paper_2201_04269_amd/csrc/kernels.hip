@@ -140,41 +140,140 @@ struct FwdArgs {
   double* partial;   // [n_tiles][T][nc][2]
 };
 
-// Builds the rows of one level phase: items are (row op, column subset) pairs.
-template <typename C>
-__device__ __forceinline__ void row_phase(const int32_t* sOps, int oa, int ob, const C* sS,
-                                          C* sR, const uint16_t* __restrict__ tabs) {
-  const int32_t* last = sOps + (ob - 1) * kOpInts;
-  const int items = last[7] + last[6];
-  for (int w = threadIdx.x; w < items; w += kNT) {
-    int o = oa;
-    while (o + 1 < ob && sOps[(o + 1) * kOpInts + 7] <= w) ++o;
-    const int32_t* op = sOps + o * kOpInts;
-    const int f = op[0], k = op[1], r0 = op[2], in = op[3], out = op[4], toff = op[5];
-    const int i = w - op[7];
-    const C* Sf = sS + 144 * f;
-    const C* srow = Sf + 12 * r0;
-    C val;
-    if (k == 1) {
-      val = srow[tabs[toff + i]];
+// Column-subset table entries of one (flavour, level) for the columns this
+// thread owns, kept in registers for the whole tile.  With ncol <= NT the
+// workgroup runs G = NT / ncol row ops of the level side by side (thread t
+// takes column t % ncol of op group t / ncol); otherwise each thread takes
+// columns t, t + NT, ... of one op at a time.
+template <int K, int QMAX>
+struct LevelTab {
+  int ncol = 0, G = 1, g = 0, i0 = 0;
+  int e[QMAX][K > 0 ? K : 1];
+
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
+    ncol = cr[8 + 2 * (6 * f + K - 1)];
+    const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
+    const int t = threadIdx.x;
+    if (ncol > 0 && ncol <= kNT) {
+      G = kNT / ncol;
+      g = t / ncol;
+      i0 = t % ncol;
     } else {
-      const uint16_t* tb = tabs + toff + i * k;
-      const C* inr = (k == 2) ? (Sf + 12 * in) : (sR + in);
-      val = cmake<C>(0, 0);
-      for (int j = 0; j < k; ++j) {
-        const int e = tb[j];
-        const C x = srow[e & 15];
-        const C y = inr[e >> 4];
-        val = (j & 1) ? cmsub(x, y, val) : cmac(x, y, val);
-      }
+      G = 1;
+      g = 0;
+      i0 = t;
     }
-    sR[out + i] = val;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int i = i0 + q * kNT;
+#pragma unroll
+      for (int j = 0; j < K; ++j) e[q][j] = (i < ncol && g < G) ? int(tabs[toff + i * (K == 1 ? 1 : K) + (K == 1 ? 0 : j)]) : 0;
+    }
+  }
+};
+
+template <int K, typename C>
+__device__ __forceinline__ C minor_entry(const int* e, const C* srow, const C* inr) {
+  if constexpr (K == 1) {
+    return srow[e[0]];
+  } else {
+    C val = cmake<C>(0, 0);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const C x = srow[e[j] & 15];
+      const C y = inr[e[j] >> 4];
+      val = (j & 1) ? cmsub(x, y, val) : cmac(x, y, val);
+    }
+    return val;
   }
 }
 
-template <typename R, int MAXS>
+// One (flavour, level) phase: rows of the tile's ops [o0, o0 + nops).
+// Two ops are processed per trip so that their LDS loads overlap.
+template <int K, int QMAX, typename C>
+__device__ __forceinline__ void level_phase(const LevelTab<K, QMAX>& tb, const int4* sOps, int o0, int nops,
+                                            const C* Sf, C* sR) {
+  if (tb.g >= tb.G) return;
+  for (int jb = tb.g; jb < nops; jb += 2 * tb.G) {
+    const int j2 = jb + tb.G;
+    const int4 opa = sOps[o0 + jb];
+    const int4 opb = sOps[o0 + (j2 < nops ? j2 : jb)];
+    const C* sa = Sf + 12 * opa.x;
+    const C* sb = Sf + 12 * opb.x;
+    const C* ia = (K == 2) ? (Sf + 12 * opa.y) : (sR + opa.y);
+    const C* ib = (K == 2) ? (Sf + 12 * opb.y) : (sR + opb.y);
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int i = tb.i0 + q * kNT;
+      if (i < tb.ncol) {
+        const C va = minor_entry<K>(tb.e[q], sa, ia);
+        const C vb = minor_entry<K>(tb.e[q], sb, ib);
+        sR[opa.z + i] = va;
+        if (j2 < nops) sR[opb.z + i] = vb;
+      }
+    }
+  }
+}
+
+template <int NF, int QMAX>
+struct FlavTabs {
+  LevelTab<1, QMAX> l1;
+  LevelTab<2, QMAX> l2;
+  LevelTab<3, QMAX> l3;
+  LevelTab<4, QMAX> l4;
+  LevelTab<5, QMAX> l5;
+  LevelTab<6, QMAX> l6;
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
+    if constexpr (NF == 1) l1.load(cr, f, tabs);
+    if constexpr (NF >= 2) l2.load(cr, f, tabs);
+    if constexpr (NF >= 3) l3.load(cr, f, tabs);
+    if constexpr (NF >= 4) l4.load(cr, f, tabs);
+    if constexpr (NF >= 5) l5.load(cr, f, tabs);
+    if constexpr (NF >= 6) l6.load(cr, f, tabs);
+  }
+};
+
+template <int K, int NF, int QMAX, typename C>
+__device__ __forceinline__ void run_level(const FlavTabs<NF, QMAX>& ft, const int32_t* tr, int f,
+                                          const int4* sOps, const C* Sf, C* sR) {
+  const int o0 = tr[20 + 2 * (7 * f + K)], n = tr[21 + 2 * (7 * f + K)];
+  if constexpr (K == 1) level_phase<1>(ft.l1, sOps, o0, n, Sf, sR);
+  if constexpr (K == 2) level_phase<2>(ft.l2, sOps, o0, n, Sf, sR);
+  if constexpr (K == 3) level_phase<3>(ft.l3, sOps, o0, n, Sf, sR);
+  if constexpr (K == 4) level_phase<4>(ft.l4, sOps, o0, n, Sf, sR);
+  if constexpr (K == 5) level_phase<5>(ft.l5, sOps, o0, n, Sf, sR);
+  if constexpr (K == 6) level_phase<6>(ft.l6, sOps, o0, n, Sf, sR);
+}
+
+// All levels of one site, one barrier after each level.  During the top
+// level the next site's propagators (prefetched in registers) are stored in
+// the other S buffer.
+template <int K, int KMAX, int NU, int ND, int QMAX, typename C>
+__device__ __forceinline__ void site_levels(const FlavTabs<NU, QMAX>& tu, const FlavTabs<ND, QMAX>& td,
+                                            const int32_t* tr, const int4* sOps, const C* sS, C* sR,
+                                            C* sSnext, const C* pre, bool have_next) {
+  if constexpr (K <= KMAX) {
+    if constexpr (K <= NU && (K >= 2 || NU == 1)) run_level<K>(tu, tr, 0, sOps, sS, sR);
+    if constexpr (K <= ND && (K >= 2 || ND == 1)) run_level<K>(td, tr, 1, sOps, sS + 144, sR);
+    if constexpr (K == KMAX) {
+      if (have_next) {
+        sSnext[threadIdx.x] = pre[0];
+        if (threadIdx.x < 288 - kNT) sSnext[kNT + threadIdx.x] = pre[1];
+      }
+    }
+    __syncthreads();
+    site_levels<K + 1, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSnext, pre, have_next);
+  }
+}
+
+template <typename R, int NU, int ND, int MAXS, int QMAX>
 __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   using C = typename cx<R>::T;
+  constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
+  constexpr int KMAX = NU > ND ? NU : ND;
+  // With both flavours' top level above 2, the first level of the next site
+  // writes no slot the leaves read, so the leaves need no closing barrier.
+  constexpr bool kOverlapLeaves = (NU >= 3 && ND >= 3);
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
@@ -182,20 +281,27 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   const int tc = lin / a.n_tiles;  // t * nc + chunk
   const int32_t* tr = a.tiles + tile * kTileInts;
   const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nops = tr[4];
-  const int meta0 = tr[5], row_units = tr[6], nph = tr[7];
+  const int meta0 = tr[5], row_units = tr[6];
   const int32_t* cr = a.corr + corr * kCorrInts;
   const int n_src = cr[0], src_off = cr[1];
 
-  C* sS = reinterpret_cast<C*>(smem);
-  C* sW = sS + 288;
+  C* sS0 = reinterpret_cast<C*>(smem);
+  C* sW = sS0 + 576;
   C* sR = sW + B * n_src;
-  int32_t* sOps = reinterpret_cast<int32_t*>(sR + row_units);
-  int32_t* sMeta = sOps + nops * kOpInts;
+  int4* sOps = reinterpret_cast<int4*>(sR + row_units);
 
-  for (int i = tid; i < nops * kOpInts; i += kNT) sOps[i] = a.ops[op0 * kOpInts + i];
-  for (int i = tid; i < B * kMetaInts; i += kNT) sMeta[i] = a.meta[meta0 * kMetaInts + i];
+  for (int i = tid; i < nops; i += kNT) {
+    const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
+    sOps[i] = make_int4(op[2], op[3], op[4], 0);
+  }
   const C* Wg = reinterpret_cast<const C*>(a.W) + w_off;
   for (int i = tid; i < B * n_src; i += kNT) sW[i] = Wg[i];
+  const int4* meta = reinterpret_cast<const int4*>(a.meta) + meta0;
+
+  FlavTabs<NU, QMAX> tu;
+  FlavTabs<ND, QMAX> td;
+  tu.load(cr, 0, a.tabs);
+  td.load(cr, 1, a.tabs);
 
   int cu[MAXS], cd[MAXS];
 #pragma unroll
@@ -210,32 +316,39 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   const int64_t v1 = (v0 + a.chunk < a.V) ? v0 + a.chunk : a.V;
   CompAcc<R> acc;
 
-  for (int64_t v = v0; v < v1; ++v) {
-    __syncthreads();  // previous site's rows are no longer read
+  // propagators of site v: thread i holds entries i and i + NT (< 288)
+  auto fetch = [&](int64_t v, C* pre) {
     const int64_t site = int64_t(t) * a.V + v;
-    for (int i = tid; i < 288; i += kNT) {
-      const void* base = i < 144 ? a.S_u : a.S_d;
-      sS[i] = load_site<C>(base, a.s_c64, site * 144 + (i % 144));
-    }
-    __syncthreads();
-    for (int ph = 0; ph < nph; ++ph) {
-      row_phase<C>(sOps, tr[8 + ph], tr[9 + ph], sS, sR, a.tabs);
-      __syncthreads();
-    }
+    pre[0] = load_site<C>(tid < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (tid % 144));
+    if (tid < 288 - kNT) pre[1] = load_site<C>(a.S_d, a.s_c64, site * 144 + (kNT + tid - 144));
+  };
+  C pre[2];
+  fetch(v0, pre);
+  sS0[tid] = pre[0];
+  if (tid < 288 - kNT) sS0[kNT + tid] = pre[1];
+  __syncthreads();
+
+  for (int64_t v = v0; v < v1; ++v) {
+    const int buf = int((v - v0) & 1);
+    C* sS = sS0 + 288 * buf;
+    C* sSn = sS0 + 288 * (buf ^ 1);
+    const bool have_next = v + 1 < v1;
+    if (have_next) fetch(v + 1, pre);
+    site_levels<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
     C L[MAXS];
 #pragma unroll
     for (int m = 0; m < MAXS; ++m) L[m] = cmake<C>(0, 0);
     for (int b = 0; b < B; ++b) {
-      const int32_t* mb = sMeta + b * kMetaInts;
+      const int4 mb = meta[b];
       const C* Wb = sW + b * n_src;
-      const C* Dd = sR + mb[1];
+      const C* Dd = sR + mb.y;
 #pragma unroll
       for (int m = 0; m < MAXS; ++m) {
         const int s = tid + kNT * m;
         if (s < n_src) L[m] = cmac(Wb[s], Dd[cd[m]], L[m]);
       }
-      if (mb[2]) {
-        const C* Du = sR + mb[0];
+      if (mb.z) {
+        const C* Du = sR + mb.x;
 #pragma unroll
         for (int m = 0; m < MAXS; ++m) {
           const int s = tid + kNT * m;
@@ -247,6 +360,7 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
         }
       }
     }
+    if constexpr (!kOverlapLeaves) __syncthreads();
   }
 
   // fixed-order FP64 reduction over the workgroup
@@ -321,9 +435,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__
   }
 }
 
-template <typename R, int MAXS>
-hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
-  auto k = fwd_kernel<R, MAXS>;
+template <typename R, int NU, int ND, int MAXS, int QMAX>
+hipError_t launch_fwd_t(const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  auto k = fwd_kernel<R, NU, ND, MAXS, QMAX>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
@@ -331,15 +445,15 @@ hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t
   return hipGetLastError();
 }
 
+// Instantiated shapes: proton (2,1), neutron (1,2), dinucleon (3,3), 3He (5,4).
 template <typename R>
 hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
-  const int ms = p->h.maxs;
-  if (ms <= 1) return launch_fwd_t<R, 1>(p, a, nblocks, lds, st);
-  if (ms <= 2) return launch_fwd_t<R, 2>(p, a, nblocks, lds, st);
-  if (ms <= 4) return launch_fwd_t<R, 4>(p, a, nblocks, lds, st);
-  if (ms <= 8) return launch_fwd_t<R, 8>(p, a, nblocks, lds, st);
-  if (ms <= 16) return launch_fwd_t<R, 16>(p, a, nblocks, lds, st);
-  return hipErrorInvalidValue;
+  const int nu = p->h.n_u, nd = p->h.n_d, ms = p->h.maxs, qm = p->h.qmax;
+  if (nu == 2 && nd == 1 && ms <= 1 && qm <= 1) return launch_fwd_t<R, 2, 1, 1, 1>(a, nblocks, lds, st);
+  if (nu == 1 && nd == 2 && ms <= 1 && qm <= 1) return launch_fwd_t<R, 1, 2, 1, 1>(a, nblocks, lds, st);
+  if (nu == 3 && nd == 3 && ms <= 4 && qm <= 1) return launch_fwd_t<R, 3, 3, 4, 1>(a, nblocks, lds, st);
+  if (nu == 5 && nd == 4 && ms <= 8 && qm <= 2) return launch_fwd_t<R, 5, 4, 8, 2>(a, nblocks, lds, st);
+  return hipErrorNotSupported;
 }
 
 }  // namespace

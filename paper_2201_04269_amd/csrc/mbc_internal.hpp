@@ -56,13 +56,15 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   [3] op_begin [4] n_ops [5] meta_off [6] row_lds (complex units of row slots)
 //   [7] n_phases [8 .. 8+kMaxPhases] phase boundaries (op indices, relative)
 //   [16] snk_begin (index of the tile's first sink key in plan order)
+//   [20 + 2*(7f + k)], [21 + 2*(7f + k)]: first op (relative) and number of
+//   ops of flavour f at level k; ops are ordered by (level, flavour).
 // Row op (kOpInts ints): flav, level, r0, in, out, tab_off, ncol, item_begin
 //   in: the S row r1 for level 2, the parent row's slot for level >= 3.
 //   out: slot (complex offset inside the row area).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
 // ---------------------------------------------------------------------------
 constexpr int kCorrInts = 40;
-constexpr int kTileInts = 20;
+constexpr int kTileInts = 48;
 constexpr int kOpInts = 8;
 constexpr int kMetaInts = 4;
 constexpr int kMaxPhases = 7;
@@ -74,6 +76,7 @@ struct PlanHost {
   int maxs = 1;          // max source keys per thread
   int max_b = 0;         // max sink keys per tile
   int max_ops = 0;       // max row ops per tile
+  int qmax = 1;          // max column subsets per thread at one level
   int64_t lds_bytes = 0; // dynamic LDS of the forward kernel
   int n_tiles = 0;
   std::vector<int32_t> corr, tiles, ops, meta, src_cu, src_cd;

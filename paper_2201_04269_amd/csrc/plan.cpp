@@ -205,6 +205,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
       P.src_cd.push_back(lev[1].index[nf[1]].at(k.second));
     }
     P.maxs = std::max(P.maxs, (n_src + P.threads - 1) / P.threads);
+    for (int f = 0; f < 2; ++f)
+      for (int k = 1; k <= nf[f]; ++k) P.qmax = std::max(P.qmax, (ncol(f, k) + P.threads - 1) / P.threads);
 
     // algorithmic flops (global minor DAG + leaves + (r_u, c_u) groups)
     {
@@ -234,9 +236,9 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
         add_chain(0, snk[i].first, &rows);
         add_chain(1, snk[i].second, &rows);
       }
-      int64_t units = 288 + int64_t(sk.size()) * n_src;
+      int64_t units = 576 + int64_t(sk.size()) * n_src;
       for (auto& r : rows) units += ncol(r.f, r.k);
-      return units * csz + int64_t(rows.size()) * kOpInts * 4 + int64_t(sk.size()) * kMetaInts * 4;
+      return units * csz + int64_t(rows.size()) * 16;
     };
     // greedy tiling over whole runs (a run longer than a tile is split)
     std::vector<std::vector<int>> tiles;
@@ -276,8 +278,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
         slot[r] = units;
         units += ncol(r.f, r.k);
       }
-      const int64_t lds = int64_t(288 + int64_t(B) * n_src + units) * csz +
-                          int64_t(rowset.size()) * kOpInts * 4 + int64_t(B) * kMetaInts * 4;
+      // double-buffered S, the tile's weights, row slots, staged (r0, in, out) ops
+      const int64_t lds = int64_t(576 + int64_t(B) * n_src + units) * csz + int64_t(rowset.size()) * 16;
       if (lds > 160 * 1024) throw std::runtime_error("a tile exceeds the 160 KiB local memory of a CU");
       P.lds_bytes = std::max(P.lds_bytes, lds);
       std::vector<int32_t> tr(kTileInts, 0);
@@ -301,6 +303,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
         if (r.k == 2) in = r.t.v[1];
         if (r.k >= 3) in = slot.at({r.f, r.k - 1, tail(r.t, r.k - 1)});
         const int nc = ncol(r.f, r.k);
+        if (tr[21 + 2 * (7 * r.f + r.k)] == 0) tr[20 + 2 * (7 * r.f + r.k)] = n_ops;
+        ++tr[21 + 2 * (7 * r.f + r.k)];
         const int32_t op[kOpInts] = {r.f, r.k, r.t.v[0], in, slot.at(r), tab_off_fk[r.f][r.k], nc, item};
         P.ops.insert(P.ops.end(), op, op + kOpInts);
         item += nc;
