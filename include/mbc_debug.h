@@ -27,6 +27,16 @@ mbc_status mbc_debug_eval_host(const mbc_index_set* s, int32_t precision, const 
                                const double* S_d, int32_t T, int64_t sites_per_t, const double* W,
                                double* C, mbc_plan_stats* stats);
 
+/* Gradients of eq. 1 (PyTorch's complex convention, as mbc_contract_backward)
+ * computed on the host by walking the backward schedule: the leaf adjoints of
+ * the determinant rows and the reverse sweep of the Laplace recursion for
+ * grad_S, the per-entry sums over sites for grad_W.  All arrays are host
+ * complex128; grad_W [nnz], grad_S_u/grad_S_d like S; any output may be NULL. */
+mbc_status mbc_debug_backward_host(const mbc_index_set* s, int32_t precision, const double* S_u,
+                                   const double* S_d, int32_t T, int64_t sites_per_t, const double* W,
+                                   const double* grad_C, double* grad_W, double* grad_S_u,
+                                   double* grad_S_d);
+
 #ifdef __cplusplus
 }
 #endif

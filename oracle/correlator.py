@@ -211,3 +211,58 @@ def gradients(S_u, S_d, iset, grad_C, want=("W", "S_u", "S_d"), batch=4):
     if "S_d" in want:
         out["S_d"] = gSd.reshape(T, V, 12, 12)
     return out
+
+
+def _perm_cofactors(S, rows, cols):
+    """Permanents of every (n-1)x(n-1) minor: [..., m, n, n] (no signs)."""
+    n = rows.shape[1]
+    shape = S.shape[:-2] + (rows.shape[0], n, n)
+    cof = np.empty(shape, dtype=S.dtype)
+    if n == 1:
+        cof[...] = 1.0
+        return cof
+    for i in range(n):
+        ri = np.delete(rows, i, axis=1)
+        for j in range(n):
+            cj = np.delete(cols, j, axis=1)
+            cof[..., i, j] = _permanents(_submatrices(S, ri, cj))
+    return cof
+
+
+def gradient_abs_scales(S_u, S_d, iset, grad_C, batch=4):
+    """Sum of |Wick terms| of every gradient entry (scales for tolerances).
+
+    The same sums as ``gradients`` with |W|, |grad_C| and |S| and every sign
+    +, i.e. determinants replaced by permanents: each entry is the sum of the
+    magnitudes of the quark-level terms that make up that gradient entry.
+    Returns a dict like ``gradients`` (real arrays).
+    """
+    p = _prep(iset)
+    T, V = S_u.shape[:2]
+    ns = T * V
+    Su = np.abs(S_u.reshape(ns, 12, 12))
+    Sd = np.abs(S_d.reshape(ns, 12, 12))
+    t_of = np.repeat(np.arange(T), V)
+    aW = np.abs(p.W)
+    ag = np.abs(grad_C)
+    gW = np.zeros(iset.nnz)
+    gSu = np.zeros((ns, 144))
+    gSd = np.zeros((ns, 144))
+    for sl in _site_batches(ns, batch):
+        Pu = _permanents(_submatrices(Su[sl], p.ru, p.cu))[:, p.inv_u]
+        Pd = _permanents(_submatrices(Sd[sl], p.rd, p.cd))[:, p.inv_d]
+        g = ag[p.corr][:, t_of[sl]].T
+        gW += np.sum(g * Pu * Pd, axis=0)
+        for name, S, rows, cols, inv, other, acc, n in (
+                ("u", Su, p.ru, p.cu, p.inv_u, Pd, gSu, iset.nu), ("d", Sd, p.rd, p.cd, p.inv_d, Pu, gSd, iset.nd)):
+            cof = _perm_cofactors(S[sl], rows, cols)[:, inv]
+            coef = g * aW[None, :] * other
+            snk = iset.snk_u if name == "u" else iset.snk_d
+            src = iset.src_u if name == "u" else iset.src_d
+            for i in range(n):
+                for j in range(n):
+                    flat = snk[:, i] * 12 + src[:, j]
+                    contrib = coef * cof[:, :, i, j]
+                    for bi, x in enumerate(range(sl.start, sl.stop)):
+                        np.add.at(acc[x], flat, contrib[bi])
+    return {"W": gW, "S_u": gSu.reshape(T, V, 12, 12), "S_d": gSd.reshape(T, V, 12, 12)}

@@ -55,6 +55,7 @@ SIGNATURES = [
     ("mbc_contract", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
     ("mbc_contract_backward", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("mbc_debug_eval_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, ctypes.POINTER(PlanStats)]),
+    ("mbc_debug_backward_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, _P, _P, _P]),
 ]
 
 

@@ -16,6 +16,9 @@ namespace mbc {
 
 mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, const double* S_d, int T,
                       int64_t V, const double* W, double* C, mbc_plan_stats* stats);
+mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S_u, const double* S_d, int T,
+                          int64_t V, const double* W, const double* grad_C, double* grad_W, double* grad_Su,
+                          double* grad_Sd);
 
 namespace {
 thread_local std::string g_err;
@@ -77,7 +80,8 @@ mbc_status upload(const std::vector<T>& v, T** out, hipStream_t st) {
 }
 
 void free_device(PlanDevice& d) {
-  void* ptrs[] = {d.corr, d.tiles, d.ops, d.meta, d.src_cu, d.src_cd, d.tabs, d.perm, d.w_exact};
+  void* ptrs[] = {d.corr,  d.tiles,   d.ops,  d.meta,   d.src_cu,  d.src_cd, d.tabs,
+                  d.perm,  d.w_exact, d.b_tiles, d.b_ops, d.b_meta, d.b_extra, d.btab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = PlanDevice();
@@ -94,6 +98,19 @@ FwdWorkspace fwd_workspace(const PlanHost& h, const Launch& L, bool user_w) {
   const size_t csz = h.precision == MBC_F64 ? 16 : 8;
   w.w_plan = user_w ? align256(size_t(h.nnz) * csz) : 0;
   w.partial = align256(size_t(h.n_tiles) * size_t(L.T) * size_t(L.nc) * 16);
+  w.total = w.w_plan + w.partial;
+  return w;
+}
+
+struct BwdWorkspace {
+  size_t w_plan = 0, partial = 0, total = 0;
+};
+
+BwdWorkspace bwd_workspace(const PlanHost& h, const Launch& L, bool user_w) {
+  BwdWorkspace w;
+  const size_t csz = h.precision == MBC_F64 ? 16 : 8;
+  w.w_plan = user_w ? align256(size_t(h.nnz) * csz) : 0;
+  w.partial = align256(size_t(L.T) * size_t(L.nc) * size_t(h.nnz) * 16);
   w.total = w.w_plan + w.partial;
   return w;
 }
@@ -203,7 +220,10 @@ mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stre
         (st = upload(h.ops, &p->d.ops, hs)) != MBC_OK || (st = upload(h.meta, &p->d.meta, hs)) != MBC_OK ||
         (st = upload(h.src_cu, &p->d.src_cu, hs)) != MBC_OK ||
         (st = upload(h.src_cd, &p->d.src_cd, hs)) != MBC_OK ||
-        (st = upload(h.tabs, &p->d.tabs, hs)) != MBC_OK || (st = upload(h.perm, &p->d.perm, hs)) != MBC_OK) {
+        (st = upload(h.tabs, &p->d.tabs, hs)) != MBC_OK || (st = upload(h.perm, &p->d.perm, hs)) != MBC_OK ||
+        (st = upload(h.b_tiles, &p->d.b_tiles, hs)) != MBC_OK ||
+        (st = upload(h.b_ops, &p->d.b_ops, hs)) != MBC_OK || (st = upload(h.b_meta, &p->d.b_meta, hs)) != MBC_OK ||
+        (st = upload(h.b_extra, &p->d.b_extra, hs)) != MBC_OK || (st = upload(h.btab, &p->d.btab, hs)) != MBC_OK) {
       free_device(p->d);
       delete p;
       return st;
@@ -250,9 +270,13 @@ mbc_status mbc_plan_workspace_bytes(const mbc_plan* p, int32_t T, int64_t sites_
                                     size_t* bytes) {
   if (!p || !bytes) return fail(MBC_ERR_INVALID, "NULL argument");
   if (T <= 0 || sites_per_t <= 0) return fail(MBC_ERR_INVALID, "T and sites_per_t must be positive");
-  if (backward) return fail(MBC_ERR_UNSUPPORTED, "backward not available in this build");
-  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
-  *bytes = fwd_workspace(p->h, L, true).total;
+  if (backward) {
+    const Launch L = backward_dw_launch_shape(p->h, T, sites_per_t);
+    *bytes = bwd_workspace(p->h, L, true).total;
+  } else {
+    const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+    *bytes = fwd_workspace(p->h, L, true).total;
+  }
   return MBC_OK;
 }
 
@@ -297,11 +321,51 @@ mbc_status mbc_contract_backward(const mbc_plan* p, const void* S_u, const void*
                                  int32_t T, int64_t sites_per_t, const double* W, const double* grad_C,
                                  double* grad_W, void* grad_S_u, void* grad_S_d, void* workspace,
                                  size_t ws_bytes, void* stream) {
-  (void)W; (void)grad_C; (void)grad_W; (void)grad_S_u; (void)grad_S_d; (void)workspace; (void)ws_bytes;
-  (void)stream;
   mbc_status st = check_common(p, S_u, S_d, s_dtype, T, sites_per_t);
   if (st != MBC_OK) return st;
-  return fail(MBC_ERR_UNSUPPORTED, "backward not available in this build");
+  if (!is_device_ptr(grad_C) || !aligned16(grad_C)) return fail(MBC_ERR_INVALID, "grad_C must be an aligned device pointer");
+  if (W && (!is_device_ptr(W) || !aligned16(W))) return fail(MBC_ERR_INVALID, "W must be an aligned device pointer or NULL");
+  if (grad_W && (!is_device_ptr(grad_W) || !aligned16(grad_W)))
+    return fail(MBC_ERR_INVALID, "grad_W must be an aligned device pointer or NULL");
+  for (void* g : {grad_S_u, grad_S_d})
+    if (g && (!is_device_ptr(g) || !aligned16(g)))
+      return fail(MBC_ERR_INVALID, "grad_S_u/grad_S_d must be aligned device pointers or NULL");
+  const Launch L = backward_dw_launch_shape(p->h, T, sites_per_t);
+  const BwdWorkspace ws = bwd_workspace(p->h, L, W != nullptr);
+  const size_t need = (grad_W ? ws.total : ws.w_plan);
+  if (need > 0 && (!workspace || !is_device_ptr(workspace)))
+    return fail(MBC_ERR_INVALID, "workspace must be a device pointer");
+  if (ws_bytes < need) return fail(MBC_ERR_INVALID, "workspace too small");
+  if (workspace && !aligned16(workspace)) return fail(MBC_ERR_INVALID, "workspace must be 16-byte aligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
+  char* wsb = static_cast<char*>(workspace);
+  const void* W_plan = p->d.w_exact;
+  if (W) {
+    MBC_HIP(launch_gather_w(p, W, wsb, hs));
+    W_plan = wsb;
+  }
+  const int s_c64 = s_dtype == MBC_C64;
+  if (grad_W) {
+    if (p->h.nnz == 0) {
+      // nothing to write
+    } else {
+      double* partial = reinterpret_cast<double*>(wsb + ws.w_plan);
+      MBC_HIP(launch_backward_dw(p, S_u, S_d, s_c64, L, W_plan, grad_C, partial, grad_W, hs));
+    }
+  }
+  if (grad_S_u || grad_S_d) {
+    const size_t bytes = size_t(T) * size_t(sites_per_t) * 144 * (s_c64 ? 8 : 16);
+    if (p->h.b_n_tiles == 0) {
+      if (grad_S_u) MBC_HIP(hipMemsetAsync(grad_S_u, 0, bytes, hs));
+      if (grad_S_d) MBC_HIP(hipMemsetAsync(grad_S_d, 0, bytes, hs));
+    } else {
+      MBC_HIP(launch_backward_ds(p, S_u, S_d, s_c64, T, sites_per_t, W_plan, grad_C, grad_S_u, grad_S_d, hs));
+    }
+  }
+  return MBC_OK;
 }
 
 mbc_status mbc_debug_eval_host(const mbc_index_set* s, int32_t precision, const double* S_u,
@@ -311,6 +375,18 @@ mbc_status mbc_debug_eval_host(const mbc_index_set* s, int32_t precision, const 
   if (T <= 0 || sites_per_t <= 0) return fail(MBC_ERR_INVALID, "T and sites_per_t must be positive");
   if (precision != MBC_F64 && precision != MBC_F32C) return fail(MBC_ERR_INVALID, "unknown precision");
   return guarded([&]() { return debug_eval(s, precision, S_u, S_d, T, sites_per_t, W, C, stats); });
+}
+
+mbc_status mbc_debug_backward_host(const mbc_index_set* s, int32_t precision, const double* S_u,
+                                   const double* S_d, int32_t T, int64_t sites_per_t, const double* W,
+                                   const double* grad_C, double* grad_W, double* grad_S_u,
+                                   double* grad_S_d) {
+  if (!s || !S_u || !S_d || !grad_C) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (T <= 0 || sites_per_t <= 0) return fail(MBC_ERR_INVALID, "T and sites_per_t must be positive");
+  if (precision != MBC_F64 && precision != MBC_F32C) return fail(MBC_ERR_INVALID, "unknown precision");
+  return guarded([&]() {
+    return debug_backward(s, precision, S_u, S_d, T, sites_per_t, W, grad_C, grad_W, grad_S_u, grad_S_d);
+  });
 }
 
 }  // extern "C"

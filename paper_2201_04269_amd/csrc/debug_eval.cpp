@@ -90,4 +90,193 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
   }
   return MBC_OK;
 }
+
+// Backward walk: gradients in PyTorch's convention (see mbc_contract_backward),
+// through the backward tiling exactly as the dS and dW kernels traverse it.
+mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S_u, const double* S_d, int T,
+                          int64_t V, const double* W, const double* grad_C, double* grad_W, double* grad_Su,
+                          double* grad_Sd) {
+  using cd = std::complex<double>;
+  PlanHost h;
+  compile_plan(s->s, precision, &h);
+  std::vector<cd> Wp(size_t(h.nnz));
+  for (int64_t i = 0; i < h.nnz; ++i)
+    Wp[i] = W ? cd(W[2 * h.perm[i]], W[2 * h.perm[i] + 1]) : cd(h.w_exact[2 * i], h.w_exact[2 * i + 1]);
+  std::vector<cd> gW(size_t(h.nnz), cd(0, 0));
+  const int nS = 2 * 144;
+  std::vector<cd> S(nS), R, A, part, adj1, Sbar(size_t(T) * V * nS, cd(0, 0));
+  for (int tile = 0; tile < h.b_n_tiles; ++tile) {
+    const int32_t* tr = &h.b_tiles[size_t(tile) * kTileInts];
+    const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], meta0 = tr[5], units = tr[6];
+    const int nreal = tr[17], nvirt = tr[18];
+    const int32_t* cr = &h.corr[size_t(corr) * kCorrInts];
+    const int n_src = cr[0], src_off = cr[1];
+    const int nf[2] = {h.n_u, h.n_d};
+    const int32_t* ex = &h.b_extra[size_t(tr[19])];
+    const int n_runs = ex[0], n_dg = ex[1];
+    const int32_t* runs = ex + 2;
+    const int32_t* dgs = runs + 3 * n_runs;
+    const int32_t* child = dgs + 2 * n_dg;
+    auto op = [&](int o) { return &h.b_ops[size_t(op0 + o) * kOpInts]; };
+    auto metab = [&](int b) { return &h.b_meta[size_t(meta0 + b) * kMetaInts]; };
+    R.assign(size_t(units), cd(0, 0));
+    A.assign(size_t(units), cd(0, 0));
+    for (int t = 0; t < T; ++t) {
+      const cd gbar = std::conj(cd(grad_C[2 * (size_t(corr) * T + t)], grad_C[2 * (size_t(corr) * T + t) + 1]));
+      std::vector<cd> Q(size_t(B) * n_src, cd(0, 0));
+      for (int64_t v = 0; v < V; ++v) {
+        const int64_t site = int64_t(t) * V + v;
+        for (int i = 0; i < 144; ++i) {
+          S[i] = cd(S_u[2 * (site * 144 + i)], S_u[2 * (site * 144 + i) + 1]);
+          S[144 + i] = cd(S_d[2 * (site * 144 + i)], S_d[2 * (site * 144 + i) + 1]);
+        }
+        // forward rows (real ops, level order)
+        for (int o = 0; o < nreal; ++o) {
+          const int32_t* p = op(o);
+          const int f = p[0], k = p[1], r0 = p[2], in = p[3], outs = p[4];
+          const int nc = cr[8 + 2 * (6 * f + k - 1)], toff = cr[8 + 2 * (6 * f + k - 1) + 1];
+          const cd* Sf = &S[144 * f];
+          for (int i = 0; i < nc; ++i) {
+            cd val(0, 0);
+            if (k == 1) {
+              val = Sf[12 * r0 + h.tabs[toff + i]];
+            } else {
+              for (int j = 0; j < k; ++j) {
+                const int e = h.tabs[toff + i * k + j];
+                const cd x = Sf[12 * r0 + (e & 15)];
+                const cd y = (k == 2) ? Sf[12 * in + (e >> 4)] : R[in + (e >> 4)];
+                val += (j & 1) ? -x * y : x * y;
+              }
+            }
+            R[outs + i] = val;
+          }
+        }
+        // dW: per-entry products summed over the sites of the timeslice
+        for (int b = 0; b < B; ++b) {
+          const int32_t* mb = metab(b);
+          for (int sidx = 0; sidx < n_src; ++sidx)
+            Q[size_t(b) * n_src + sidx] += R[mb[0] + h.src_cu[src_off + sidx]] * R[mb[1] + h.src_cd[src_off + sidx]];
+        }
+        // leaf adjoints of the top rows (holomorphic, seeded with conj(grad_C))
+        const int ncu = cr[8 + 2 * (6 * 0 + nf[0] - 1)], ncd = cr[8 + 2 * (6 * 1 + nf[1] - 1)];
+        const int32_t* csru = &h.btab[size_t(cr[64])];
+        const int32_t* csrd = &h.btab[size_t(cr[65])];
+        for (int r = 0; r < n_runs; ++r) {
+          const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
+          for (int c = 0; c < ncu; ++c) {
+            cd sum(0, 0);
+            for (int q = csru[c]; q < csru[c + 1]; ++q) {
+              const int sidx = csru[q];
+              for (int b = b0; b < b1; ++b)
+                sum += Wp[size_t(w_off) + size_t(b) * n_src + sidx] * R[metab(b)[1] + h.src_cd[src_off + sidx]];
+            }
+            A[us + c] = gbar * sum;
+          }
+        }
+        for (int g = 0; g < n_dg; ++g) {
+          const int ds = dgs[2 * g], mask = dgs[2 * g + 1];
+          for (int c = 0; c < ncd; ++c) {
+            cd sum(0, 0);
+            for (int q = csrd[c]; q < csrd[c + 1]; ++q) {
+              const int sidx = csrd[q];
+              for (int b = 0; b < B; ++b)
+                if (mask & (1 << b))
+                  sum += Wp[size_t(w_off) + size_t(b) * n_src + sidx] * R[metab(b)[0] + h.src_cu[src_off + sidx]];
+            }
+            A[ds + c] = gbar * sum;
+          }
+        }
+        // reverse sweep, top level down
+        part.assign(size_t(nreal) * 12, cd(0, 0));
+        adj1.assign(size_t(nvirt) * 12, cd(0, 0));
+        const int kmax = std::max(nf[0], nf[1]);
+        for (int k = kmax; k >= 1; --k) {
+          for (int o = 0; o < nreal; ++o) {  // (ii) S-bar parts of the level-k rows
+            const int32_t* p = op(o);
+            if (p[1] != k) continue;
+            const int f = p[0];
+            const int32_t* jl = &h.btab[size_t(cr[40 + 6 * f + k - 1])];
+            const cd* Sf = &S[144 * f];
+            for (int j = 0; j < 12; ++j) {
+              cd sum(0, 0);
+              for (int q = jl[j]; q < jl[j + 1]; ++q) {
+                const int e = jl[q], C = e & 4095;
+                if (k == 1) {
+                  sum += A[p[4] + C];
+                } else {
+                  const int sub = (e >> 12) & 4095, pos = e >> 24;
+                  const cd y = (k == 2) ? Sf[12 * p[3] + sub] : R[p[3] + sub];
+                  sum += (pos & 1) ? -A[p[4] + C] * y : A[p[4] + C] * y;
+                }
+              }
+              part[size_t(o) * 12 + j] = sum;
+            }
+          }
+          if (k == 1) continue;
+          // (i) adjoints of the parents (level k-1 rows, or S rows for k = 2)
+          for (int o = 0; o < nreal + nvirt; ++o) {
+            const int32_t* p = op(o);
+            const bool virt = p[7] != 0;
+            if (virt ? (k != 2) : (p[1] != k - 1)) continue;
+            if (p[6] == 0) continue;  // a top row: its adjoint came from the leaves
+            const int f = p[0];
+            const int ncp = cr[8 + 2 * (6 * f + k - 2)];
+            const int32_t* sup = &h.btab[size_t(cr[52 + 6 * f + k - 2])];
+            const int toff1 = cr[8 + 2 * (6 * f + 0) + 1];
+            const cd* Sf = &S[144 * f];
+            for (int c = 0; c < ncp; ++c) {
+              cd sum(0, 0);
+              for (int ci = 0; ci < p[6]; ++ci) {
+                const int32_t* ch = op(child[p[5] + ci]);
+                for (int q = sup[c]; q < sup[c + 1]; ++q) {
+                  const int e = sup[q], C = e & 4095, j = (e >> 12) & 15, pos = e >> 16;
+                  const cd term = A[ch[4] + C] * Sf[12 * ch[2] + j];
+                  sum += (pos & 1) ? -term : term;
+                }
+              }
+              if (virt)
+                adj1[size_t(p[4]) + h.tabs[toff1 + c]] = sum;
+              else
+                A[p[4] + c] = sum;
+            }
+          }
+        }
+        cd* sb = &Sbar[size_t(site) * nS];
+        for (int f = 0; f < 2; ++f)
+          for (int a = 0; a < 12; ++a)
+            for (int bb = 0; bb < 12; ++bb) {
+              cd sum(0, 0);
+              for (int o = 0; o < nreal + nvirt; ++o) {
+                const int32_t* p = op(o);
+                if (p[0] != f || p[2] != a) continue;
+                sum += p[7] ? adj1[size_t(p[4]) + bb] : part[size_t(o) * 12 + bb];
+              }
+              sb[144 * f + 12 * a + bb] += sum;
+            }
+      }
+      const cd g(grad_C[2 * (size_t(corr) * T + t)], grad_C[2 * (size_t(corr) * T + t) + 1]);
+      for (int b = 0; b < B; ++b)
+        for (int sidx = 0; sidx < n_src; ++sidx)
+          gW[size_t(w_off) + size_t(b) * n_src + sidx] += g * std::conj(Q[size_t(b) * n_src + sidx]);
+    }
+  }
+  if (grad_W)
+    for (int64_t i = 0; i < h.nnz; ++i) {
+      grad_W[2 * h.perm[i]] = gW[i].real();
+      grad_W[2 * h.perm[i] + 1] = gW[i].imag();
+    }
+  for (int64_t site = 0; site < int64_t(T) * V; ++site)
+    for (int i = 0; i < 144; ++i) {
+      const cd u = std::conj(Sbar[size_t(site) * nS + i]), d = std::conj(Sbar[size_t(site) * nS + 144 + i]);
+      if (grad_Su) {
+        grad_Su[2 * (site * 144 + i)] = u.real();
+        grad_Su[2 * (site * 144 + i) + 1] = u.imag();
+      }
+      if (grad_Sd) {
+        grad_Sd[2 * (site * 144 + i)] = d.real();
+        grad_Sd[2 * (site * 144 + i) + 1] = d.imag();
+      }
+    }
+  return MBC_OK;
+}
 }  // namespace mbc

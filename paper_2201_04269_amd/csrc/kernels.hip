@@ -21,104 +21,14 @@
 
 #include <cstdint>
 
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace mbc {
 
 namespace {
 
-constexpr int kNT = 256;  // threads per workgroup
-
-template <typename R>
-struct cx;
-template <>
-struct cx<double> {
-  using T = double2;
-};
-template <>
-struct cx<float> {
-  using T = float2;
-};
-
-template <typename C>
-__device__ __forceinline__ C cmake(decltype(C::x) a, decltype(C::x) b) {
-  C r;
-  r.x = a;
-  r.y = b;
-  return r;
-}
-
-// acc + a*b and acc - a*b (complex, FMA-contracted)
-template <typename C>
-__device__ __forceinline__ C cmac(C a, C b, C acc) {
-  acc.x = fma(a.x, b.x, acc.x);
-  acc.x = fma(-a.y, b.y, acc.x);
-  acc.y = fma(a.x, b.y, acc.y);
-  acc.y = fma(a.y, b.x, acc.y);
-  return acc;
-}
-template <typename C>
-__device__ __forceinline__ C cmsub(C a, C b, C acc) {
-  acc.x = fma(-a.x, b.x, acc.x);
-  acc.x = fma(a.y, b.y, acc.x);
-  acc.y = fma(-a.x, b.y, acc.y);
-  acc.y = fma(-a.y, b.x, acc.y);
-  return acc;
-}
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-  C r;
-  r.x = fma(a.x, b.x, -a.y * b.y);
-  r.y = fma(a.x, b.y, a.y * b.x);
-  return r;
-}
-
-// Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no reassociation).
-template <typename R>
-__device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
-  s = a + b;
-  R bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-// Compensated complex accumulator.
-template <typename R>
-struct CompAcc {
-  R hx = 0, lx = 0, hy = 0, ly = 0;
-  __device__ __forceinline__ void add(R x, R y) {
-    R s, e;
-    two_sum(hx, x, s, e);
-    hx = s;
-    lx += e;
-    two_sum(hy, y, s, e);
-    hy = s;
-    ly += e;
-  }
-};
-
-template <typename C>
-__device__ __forceinline__ C load_site(const void* base, int c64, int64_t idx) {
-  C r;
-  if (c64) {
-    const float2 v = reinterpret_cast<const float2*>(base)[idx];
-    r.x = v.x;
-    r.y = v.y;
-  } else {
-    const double2 v = reinterpret_cast<const double2*>(base)[idx];
-    r.x = v.x;
-    r.y = v.y;
-  }
-  return r;
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs (block id mod 8).  Map
-// them so that each XCD receives a contiguous range of logical ids, which
-// keeps all tiles of a chunk of sites (same propagators) in one L2.
-__device__ __forceinline__ int xcd_linear(int bid, int nb) {
-  const int per = nb / 8, rem = nb % 8;
-  const int xcd = bid % 8, loc = bid / 8;
-  return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
-}
+using namespace dev;
 
 struct FwdArgs {
   const int32_t* corr;
@@ -139,111 +49,6 @@ struct FwdArgs {
   int nc;
   double* partial;   // [n_tiles][T][nc][2]
 };
-
-// Column-subset table entries of one (flavour, level) for the columns this
-// thread owns, kept in registers for the whole tile.  With ncol <= NT the
-// workgroup runs G = NT / ncol row ops of the level side by side (thread t
-// takes column t % ncol of op group t / ncol); otherwise each thread takes
-// columns t, t + NT, ... of one op at a time.
-template <int K, int QMAX>
-struct LevelTab {
-  int ncol = 0, G = 1, g = 0, i0 = 0;
-  int e[QMAX][K > 0 ? K : 1];
-
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
-    ncol = cr[8 + 2 * (6 * f + K - 1)];
-    const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
-    const int t = threadIdx.x;
-    if (ncol > 0 && ncol <= kNT) {
-      G = kNT / ncol;
-      g = t / ncol;
-      i0 = t % ncol;
-    } else {
-      G = 1;
-      g = 0;
-      i0 = t;
-    }
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int i = i0 + q * kNT;
-#pragma unroll
-      for (int j = 0; j < K; ++j) e[q][j] = (i < ncol && g < G) ? int(tabs[toff + i * (K == 1 ? 1 : K) + (K == 1 ? 0 : j)]) : 0;
-    }
-  }
-};
-
-template <int K, typename C>
-__device__ __forceinline__ C minor_entry(const int* e, const C* srow, const C* inr) {
-  if constexpr (K == 1) {
-    return srow[e[0]];
-  } else {
-    C val = cmake<C>(0, 0);
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const C x = srow[e[j] & 15];
-      const C y = inr[e[j] >> 4];
-      val = (j & 1) ? cmsub(x, y, val) : cmac(x, y, val);
-    }
-    return val;
-  }
-}
-
-// One (flavour, level) phase: rows of the tile's ops [o0, o0 + nops).
-// Two ops are processed per trip so that their LDS loads overlap.
-template <int K, int QMAX, typename C>
-__device__ __forceinline__ void level_phase(const LevelTab<K, QMAX>& tb, const int4* sOps, int o0, int nops,
-                                            const C* Sf, C* sR) {
-  if (tb.g >= tb.G) return;
-  for (int jb = tb.g; jb < nops; jb += 2 * tb.G) {
-    const int j2 = jb + tb.G;
-    const int4 opa = sOps[o0 + jb];
-    const int4 opb = sOps[o0 + (j2 < nops ? j2 : jb)];
-    const C* sa = Sf + 12 * opa.x;
-    const C* sb = Sf + 12 * opb.x;
-    const C* ia = (K == 2) ? (Sf + 12 * opa.y) : (sR + opa.y);
-    const C* ib = (K == 2) ? (Sf + 12 * opb.y) : (sR + opb.y);
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int i = tb.i0 + q * kNT;
-      if (i < tb.ncol) {
-        const C va = minor_entry<K>(tb.e[q], sa, ia);
-        const C vb = minor_entry<K>(tb.e[q], sb, ib);
-        sR[opa.z + i] = va;
-        if (j2 < nops) sR[opb.z + i] = vb;
-      }
-    }
-  }
-}
-
-template <int NF, int QMAX>
-struct FlavTabs {
-  LevelTab<1, QMAX> l1;
-  LevelTab<2, QMAX> l2;
-  LevelTab<3, QMAX> l3;
-  LevelTab<4, QMAX> l4;
-  LevelTab<5, QMAX> l5;
-  LevelTab<6, QMAX> l6;
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
-    if constexpr (NF == 1) l1.load(cr, f, tabs);
-    if constexpr (NF >= 2) l2.load(cr, f, tabs);
-    if constexpr (NF >= 3) l3.load(cr, f, tabs);
-    if constexpr (NF >= 4) l4.load(cr, f, tabs);
-    if constexpr (NF >= 5) l5.load(cr, f, tabs);
-    if constexpr (NF >= 6) l6.load(cr, f, tabs);
-  }
-};
-
-template <int K, int NF, int QMAX, typename C>
-__device__ __forceinline__ void run_level(const FlavTabs<NF, QMAX>& ft, const int32_t* tr, int f,
-                                          const int4* sOps, const C* Sf, C* sR) {
-  const int o0 = tr[20 + 2 * (7 * f + K)], n = tr[21 + 2 * (7 * f + K)];
-  if constexpr (K == 1) level_phase<1>(ft.l1, sOps, o0, n, Sf, sR);
-  if constexpr (K == 2) level_phase<2>(ft.l2, sOps, o0, n, Sf, sR);
-  if constexpr (K == 3) level_phase<3>(ft.l3, sOps, o0, n, Sf, sR);
-  if constexpr (K == 4) level_phase<4>(ft.l4, sOps, o0, n, Sf, sR);
-  if constexpr (K == 5) level_phase<5>(ft.l5, sOps, o0, n, Sf, sR);
-  if constexpr (K == 6) level_phase<6>(ft.l6, sOps, o0, n, Sf, sR);
-}
 
 // All levels of one site, one barrier after each level.  During the top
 // level the next site's propagators (prefetched in registers) are stored in
@@ -288,7 +93,7 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   C* sS0 = reinterpret_cast<C*>(smem);
   C* sW = sS0 + 576;
   C* sR = sW + B * n_src;
-  int4* sOps = reinterpret_cast<int4*>(sR + row_units);
+  int4* sOps = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(sR + row_units) + 15) & ~uintptr_t(15));
 
   for (int i = tid; i < nops; i += kNT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;

@@ -27,4 +27,14 @@ hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, i
 hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
                          hipStream_t st);
 
+// Backward: dW (tile-major over timeslice chunks, then a fixed-order sum over
+// chunks into grad_W in index-set order) and dS (one workgroup per site).
+Launch backward_dw_launch_shape(const PlanHost& h, int T, int64_t V);
+hipError_t launch_backward_dw(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64, const Launch& L,
+                              const void* W_plan, const double* grad_C, double* partial, double* grad_W,
+                              hipStream_t st);
+hipError_t launch_backward_ds(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64, int T, int64_t V,
+                              const void* W_plan, const double* grad_C, void* grad_S_u, void* grad_S_d,
+                              hipStream_t st);
+
 }  // namespace mbc

@@ -45,8 +45,21 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   [2] n_snk        sink keys
 //   [3] tile_begin   first tile of the correlator; [4] tile_end
 //   [5] entry_begin  first index-set entry of the correlator
+//   [6] btile_begin [7] btile_end   tiles of the backward tiling
 //   [8 + 2*(6*f + k-1)]     ncol[f][k]   columns (k-subsets) at level k, flavour f
 //   [8 + 2*(6*f + k-1) + 1] tab_off[f][k] offset of the level's column table
+//   [40 + 6*f + k-1]  offset in btab of the level-k "j-lists": 13 relative
+//                     pointers then entries C | sub << 12 | pos << 24, the
+//                     columns C of level k that contain column j at position
+//                     pos, with sub = index of C \ {j} (level k-1; for k = 2
+//                     the remaining column number); for k = 1: C | col << 12
+//   [52 + 6*f + k-1]  offset in btab of the level-k "superset lists" (parents
+//                     of level k+1): ncol[f][k] + 1 relative pointers, then
+//                     entries C | j << 12 | pos << 16 for every column C of
+//                     level k+1 that is C' + {j}, j at position pos of C
+//   [64] csr_u_off [65] csr_d_off  offsets in btab of: ncol_top + 1 relative
+//                     pointers, then the source keys s with that top column
+//   [66] w_base       plan-ordered W offset of the correlator's first entry
 // Column table of level k >= 2: ncol*k uint16 entries (sub << 4) | col, the k
 //   terms of the expansion along the first row; col = C_j, sub = index of
 //   C \ C_j in level k-1 (for k = 2: the remaining column number itself).
@@ -56,14 +69,21 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   [3] op_begin [4] n_ops [5] meta_off [6] row_lds (complex units of row slots)
 //   [7] n_phases [8 .. 8+kMaxPhases] phase boundaries (op indices, relative)
 //   [16] snk_begin (index of the tile's first sink key in plan order)
+//   [17] virt_begin [18] n_virt  (backward tiles) level-1 parent records
+//   [19] extra_off   (backward tiles) offset in b_extra of: n_runs, n_dgroups,
+//        then runs (u_slot, b_begin, b_end), d-groups (d_slot, b mask), then
+//        the children lists of the ops
 //   [20 + 2*(7f + k)], [21 + 2*(7f + k)]: first op (relative) and number of
 //   ops of flavour f at level k; ops are ordered by (level, flavour).
 // Row op (kOpInts ints): flav, level, r0, in, out, tab_off, ncol, item_begin
 //   in: the S row r1 for level 2, the parent row's slot for level >= 3.
 //   out: slot (complex offset inside the row area).
+// Backward row op: flav, level, r0, in, out, child_begin, n_children, virtual
+//   (virtual = a level-1 parent standing for S row r0: out = 12 * its index
+//   in the tile's level-1 adjoint rows).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
 // ---------------------------------------------------------------------------
-constexpr int kCorrInts = 40;
+constexpr int kCorrInts = 72;
 constexpr int kTileInts = 48;
 constexpr int kOpInts = 8;
 constexpr int kMetaInts = 4;
@@ -80,6 +100,11 @@ struct PlanHost {
   int64_t lds_bytes = 0; // dynamic LDS of the forward kernel
   int n_tiles = 0;
   std::vector<int32_t> corr, tiles, ops, meta, src_cu, src_cd;
+  // backward tiling (smaller tiles: adjoint rows need their own slots)
+  int b_n_tiles = 0, b_max_ops = 0, b_max_b = 0;
+  int64_t b_lds_ds = 0, b_lds_dw = 0;  // dS kernel, dW kernel
+  std::vector<int32_t> b_tiles, b_ops, b_meta, b_extra, btab;
+  int maxc_top = 0;      // max top-level columns over correlators and flavours
   std::vector<uint16_t> tabs;
   std::vector<int64_t> perm;      // plan-ordered W slot -> index-set entry
   std::vector<double> w_exact;    // plan-ordered exact W (re, im)
@@ -99,6 +124,11 @@ struct PlanDevice {
   uint16_t* tabs = nullptr;
   int64_t* perm = nullptr;
   void* w_exact = nullptr;  // plan precision complex
+  int32_t* b_tiles = nullptr;
+  int32_t* b_ops = nullptr;
+  int32_t* b_meta = nullptr;
+  int32_t* b_extra = nullptr;
+  int32_t* btab = nullptr;
 };
 
 void set_error(const std::string& msg);

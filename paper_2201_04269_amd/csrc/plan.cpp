@@ -106,6 +106,317 @@ void add_chain(int f, const Key& top, std::set<RowId>* rows) {
 
 }  // namespace
 
+namespace {
+
+// Everything about one correlator the tilings need.
+struct CorrCtx {
+  int c = 0, n_src = 0, n_snk = 0;
+  int nf[2] = {0, 0};
+  std::vector<std::pair<Key, Key>> snk, src;  // sink keys in plan order; source keys
+  Levels lev[2];
+  int tab_off[2][kMaxQuarks + 1] = {};
+  int64_t w_base = 0;
+  int ncol(int f, int k) const { return int(lev[f].cols[k].size()); }
+};
+
+struct TileSetOut {
+  std::vector<int32_t>* tiles;
+  std::vector<int32_t>* ops;
+  std::vector<int32_t>* meta;
+  std::vector<int32_t>* extra;  // backward only
+  int* n_tiles;
+  int* max_ops;
+  int* max_b;
+  double* exec;                 // forward flop count (forward tiling only)
+};
+
+// LDS model of a tile: complex units of (S, W, rows) plus bytes of staged records.
+struct LdsModel {
+  bool backward;
+  int csz;
+  int64_t operator()(int B, int n_src, int64_t row_units, int n_ops, int n_virt, int64_t n_child) const {
+    if (!backward) {
+      int64_t bytes = (576 + int64_t(B) * n_src + row_units) * csz;
+      return ((bytes + 15) & ~int64_t(15)) + int64_t(n_ops) * 16;
+    }
+    // dS kernel: S, W, rows, adjoint rows, level-1 adjoints, per-op j-partials,
+    // S-bar accumulators (16 B each), staged op records and child lists
+    const int64_t ds = (288 + int64_t(B) * n_src + 2 * row_units + 12 * int64_t(n_virt) + 12 * int64_t(n_ops)) * csz +
+                       288 * 16 + int64_t(n_ops + n_virt) * 32 + n_child * 4 + 64 * 4;
+    return ds;
+  }
+};
+
+void rows_of(const CorrCtx& X, const std::vector<int>& sk, std::set<RowId>* rows) {
+  for (int i : sk) {
+    add_chain(0, X.snk[i].first, rows);
+    add_chain(1, X.snk[i].second, rows);
+  }
+}
+
+int64_t tile_lds(const CorrCtx& X, const std::vector<int>& sk, const LdsModel& m) {
+  std::set<RowId> rows;
+  rows_of(X, sk, &rows);
+  int64_t units = 0;
+  int n_virt = 0;
+  std::set<std::pair<int, int>> v1;
+  for (auto& r : rows) {
+    units += X.ncol(r.f, r.k);
+    if (r.k == 2) v1.insert({r.f, r.t.v[1]});
+  }
+  n_virt = int(v1.size());
+  return m(int(sk.size()), X.n_src, units, int(rows.size()), n_virt, int64_t(rows.size()));
+}
+
+// Greedy tiling of the sink keys (plan order) into groups of whole runs of
+// equal u-tuples under an LDS budget; a run longer than a tile is split.
+std::vector<std::vector<int>> make_tiles(const CorrCtx& X, int64_t budget, int max_b, const LdsModel& m) {
+  std::vector<std::vector<int>> tiles;
+  std::vector<int> cur;
+  for (int i = 0; i < X.n_snk;) {
+    int j = i + 1;
+    while (j < X.n_snk && X.snk[j].first == X.snk[i].first) ++j;
+    std::vector<int> trial = cur;
+    for (int q = i; q < j; ++q) trial.push_back(q);
+    if (!cur.empty() && (int(trial.size()) > max_b || tile_lds(X, trial, m) > budget)) {
+      tiles.push_back(cur);
+      cur.clear();
+    }
+    for (int q = i; q < j; ++q) {
+      std::vector<int> t2 = cur;
+      t2.push_back(q);
+      if (!cur.empty() && (int(t2.size()) > max_b || tile_lds(X, t2, m) > budget)) {
+        tiles.push_back(cur);
+        cur.clear();
+      }
+      cur.push_back(q);
+    }
+    i = j;
+  }
+  if (!cur.empty()) tiles.push_back(cur);
+  return tiles;
+}
+
+// Emits the records of one tiling.  Returns the largest LDS of a tile.
+int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles, const LdsModel& m,
+                   TileSetOut& o) {
+  int64_t max_lds = 0;
+  for (auto& sk : tiles) {
+    const int B = int(sk.size());
+    std::set<RowId> rowset;
+    rows_of(X, sk, &rowset);
+    std::map<RowId, int> slot;
+    int units = 0;
+    for (auto& r : rowset) {
+      slot[r] = units;
+      units += X.ncol(r.f, r.k);
+    }
+    std::vector<int32_t> tr(kTileInts, 0);
+    tr[0] = X.c;
+    tr[1] = B;
+    tr[2] = int32_t(X.w_base + int64_t(sk[0]) * X.n_src);
+    tr[3] = int32_t(o.ops->size() / kOpInts);
+    tr[5] = int32_t(o.meta->size() / kMetaInts);
+    tr[6] = units;
+    tr[16] = sk[0];
+    std::vector<RowId> order(rowset.begin(), rowset.end());
+    std::map<RowId, int> op_index;
+    int n_ops = 0, phase = -1, cur_level = 0, item = 0;
+    for (auto& r : order) {
+      if (r.k != cur_level) {
+        ++phase;
+        if (phase >= kMaxPhases) throw std::runtime_error("too many phases");
+        tr[8 + phase] = n_ops;
+        cur_level = r.k;
+        item = 0;
+      }
+      if (tr[21 + 2 * (7 * r.f + r.k)] == 0) tr[20 + 2 * (7 * r.f + r.k)] = n_ops;
+      ++tr[21 + 2 * (7 * r.f + r.k)];
+      op_index[r] = n_ops;
+      item += X.ncol(r.f, r.k);
+      ++n_ops;
+      if (r.k >= 2 && o.exec) *o.exec += double(X.ncol(r.f, r.k)) * (8.0 * r.k - 2.0);
+    }
+    tr[4] = n_ops;
+    tr[7] = phase + 1;
+    tr[8 + phase + 1] = n_ops;
+    // level-1 parents (S rows) of the level-2 rows, and children lists
+    std::vector<std::pair<int, int>> virt;  // (f, r1)
+    std::map<std::pair<int, int>, int> virt_index;
+    for (auto& r : order)
+      if (r.k == 2 && !virt_index.count({r.f, r.t.v[1]})) {
+        virt_index[{r.f, r.t.v[1]}] = int(virt.size());
+        virt.push_back({r.f, r.t.v[1]});
+      }
+    std::vector<std::vector<int>> children(size_t(n_ops) + virt.size());
+    for (auto& r : order) {
+      if (r.k == 2) children[n_ops + virt_index.at({r.f, r.t.v[1]})].push_back(op_index.at(r));
+      if (r.k >= 3) children[op_index.at({r.f, r.k - 1, tail(r.t, r.k - 1)})].push_back(op_index.at(r));
+    }
+    const bool bwd = o.extra != nullptr;
+    int64_t child_total = 0;
+    int item_begin = 0;
+    cur_level = 0;
+    for (auto& r : order) {
+      if (r.k != cur_level) {
+        cur_level = r.k;
+        item_begin = 0;
+      }
+      int in = 0;
+      if (r.k == 2) in = r.t.v[1];
+      if (r.k >= 3) in = slot.at({r.f, r.k - 1, tail(r.t, r.k - 1)});
+      const int nc = X.ncol(r.f, r.k);
+      const int oi = op_index.at(r);
+      int32_t op[kOpInts] = {r.f, r.k, r.t.v[0], in, slot.at(r), X.tab_off[r.f][r.k], nc, item_begin};
+      if (bwd) {
+        op[5] = int32_t(child_total);
+        op[6] = int32_t(children[oi].size());
+        op[7] = 0;
+        child_total += int64_t(children[oi].size());
+      }
+      o.ops->insert(o.ops->end(), op, op + kOpInts);
+      item_begin += nc;
+    }
+    if (bwd) {
+      tr[17] = n_ops;
+      tr[18] = int32_t(virt.size());
+      for (size_t v = 0; v < virt.size(); ++v) {
+        const auto& ch = children[n_ops + v];
+        const int32_t op[kOpInts] = {virt[v].first, 1, virt[v].second, 0, int32_t(12 * v),
+                                     int32_t(child_total), int32_t(ch.size()), 1};
+        child_total += int64_t(ch.size());
+        o.ops->insert(o.ops->end(), op, op + kOpInts);
+      }
+      tr[4] = n_ops + int32_t(virt.size());
+    }
+    // per sink key metadata
+    for (int b = 0; b < B; ++b) {
+      const int i = sk[b];
+      const bool run_end = (b + 1 == B) || !(X.snk[sk[b + 1]].first == X.snk[i].first);
+      const int u_slot = slot.at({0, X.nf[0], X.snk[i].first});
+      const int d_slot = slot.at({1, X.nf[1], X.snk[i].second});
+      const int32_t mm[kMetaInts] = {u_slot, d_slot, run_end ? 1 : 0, i};
+      o.meta->insert(o.meta->end(), mm, mm + kMetaInts);
+      if (o.exec) *o.exec += 8.0 * X.n_src + (run_end ? 8.0 * X.n_src : 0.0);
+    }
+    if (bwd) {
+      tr[19] = int32_t(o.extra->size());
+      std::vector<int32_t> runs, dgs;
+      std::map<int, int> dmask;
+      for (int b = 0; b < B;) {
+        int e = b + 1;
+        while (e < B && X.snk[sk[e]].first == X.snk[sk[b]].first) ++e;
+        runs.insert(runs.end(), {slot.at({0, X.nf[0], X.snk[sk[b]].first}), b, e});
+        b = e;
+      }
+      for (int b = 0; b < B; ++b) dmask[slot.at({1, X.nf[1], X.snk[sk[b]].second})] |= (1 << b);
+      for (auto& kv : dmask) dgs.insert(dgs.end(), {kv.first, kv.second});
+      o.extra->push_back(int32_t(runs.size() / 3));
+      o.extra->push_back(int32_t(dgs.size() / 2));
+      o.extra->insert(o.extra->end(), runs.begin(), runs.end());
+      o.extra->insert(o.extra->end(), dgs.begin(), dgs.end());
+      for (auto& ch : children) o.extra->insert(o.extra->end(), ch.begin(), ch.end());
+    }
+    int64_t lds = m(B, X.n_src, units, n_ops, bwd ? int(virt.size()) : 0, child_total);
+    if (bwd) {
+      const int nv = int(virt.size());
+      const int64_t ex_len = int64_t(o.extra->size()) - tr[19];
+      tr[15] = int32_t(ex_len);
+      // dS kernel layout: S, W, rows, adjoint rows, level-1 adjoints, per-row
+      // S-bar partials (complex, rounded up to 16 B), then int4 op records
+      // (real ops; all ops twice) and the extra ints
+      int64_t cunits = 288 + int64_t(B) * X.n_src + 2 * int64_t(units) + 12 * int64_t(nv) + 12 * int64_t(n_ops);
+      int64_t bytes = cunits * m.csz;
+      bytes = (bytes + 15) & ~int64_t(15);
+      lds = bytes + int64_t(n_ops + 2 * (n_ops + nv)) * 16 + ex_len * 4;
+    }
+    if (lds > 160 * 1024) throw std::runtime_error("a tile exceeds the 160 KiB local memory of a CU");
+    max_lds = std::max(max_lds, lds);
+    *o.max_ops = std::max(*o.max_ops, int(tr[4]));
+    *o.max_b = std::max(*o.max_b, B);
+    o.tiles->insert(o.tiles->end(), tr.begin(), tr.end());
+    ++*o.n_tiles;
+  }
+  return max_lds;
+}
+
+// Backward tables of one correlator (see the correlator record layout).
+void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) {
+  for (int f = 0; f < 2; ++f) {
+    for (int k = 1; k <= X.nf[f]; ++k) {
+      const auto& cols = X.lev[f].cols[k];
+      // j-lists of level k
+      cr[40 + 6 * f + k - 1] = int32_t(btab.size());
+      std::vector<std::vector<int32_t>> jl(12);
+      for (size_t i = 0; i < cols.size(); ++i) {
+        const Key& C = cols[i];
+        for (int pos = 0; pos < k; ++pos) {
+          int32_t e;
+          if (k == 1) {
+            e = int32_t(i) | (int32_t(C.v[0]) << 12);
+          } else {
+            const Key rest = drop(C, pos);
+            const int sub = (k == 2) ? rest.v[0] : X.lev[f].index[k - 1].at(rest);
+            e = int32_t(i) | (sub << 12) | (pos << 24);
+          }
+          jl[C.v[pos]].push_back(e);
+        }
+      }
+      const size_t base = btab.size();
+      btab.resize(base + 13);
+      int32_t acc = 13;
+      for (int j = 0; j < 12; ++j) {
+        btab[base + j] = acc;
+        acc += int32_t(jl[j].size());
+      }
+      btab[base + 12] = acc;
+      for (int j = 0; j < 12; ++j) btab.insert(btab.end(), jl[j].begin(), jl[j].end());
+      // superset lists: parents at level k, children at level k + 1
+      if (k < X.nf[f]) {
+        cr[52 + 6 * f + k - 1] = int32_t(btab.size());
+        std::vector<std::vector<int32_t>> sup(cols.size());
+        const auto& up = X.lev[f].cols[k + 1];
+        for (size_t i = 0; i < up.size(); ++i)
+          for (int pos = 0; pos < k + 1; ++pos) {
+            const Key rest = drop(up[i], pos);
+            const int pi = X.lev[f].index[k].at(rest);
+            sup[pi].push_back(int32_t(i) | (int32_t(up[i].v[pos]) << 12) | (pos << 16));
+          }
+        const size_t b2 = btab.size();
+        btab.resize(b2 + cols.size() + 1);
+        int32_t a2 = int32_t(cols.size() + 1);
+        for (size_t i = 0; i < cols.size(); ++i) {
+          btab[b2 + i] = a2;
+          a2 += int32_t(sup[i].size());
+        }
+        btab[b2 + cols.size()] = a2;
+        for (auto& v : sup) btab.insert(btab.end(), v.begin(), v.end());
+      }
+    }
+  }
+  // source keys grouped by their top u column and by their top d column
+  for (int f = 0; f < 2; ++f) {
+    const int ntop = X.ncol(f, X.nf[f]);
+    std::vector<std::vector<int32_t>> lists(ntop);
+    for (int s = 0; s < X.n_src; ++s) {
+      const Key& col = f == 0 ? X.src[s].first : X.src[s].second;
+      lists[X.lev[f].index[X.nf[f]].at(col)].push_back(s);
+    }
+    cr[64 + f] = int32_t(btab.size());
+    const size_t b3 = btab.size();
+    btab.resize(b3 + ntop + 1);
+    int32_t a3 = ntop + 1;
+    for (int i = 0; i < ntop; ++i) {
+      btab[b3 + i] = a3;
+      a3 += int32_t(lists[i].size());
+    }
+    btab[b3 + ntop] = a3;
+    for (auto& v : lists) btab.insert(btab.end(), v.begin(), v.end());
+  }
+}
+
+}  // namespace
+
 void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   if (!s.canonical) throw std::invalid_argument("plans need a canonical (symmetrised) index set");
   if (s.n_corr < 1) throw std::invalid_argument("empty batch of correlators");
@@ -120,66 +431,81 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.nnz = int64_t(s.entries.size());
   P.threads = 256;
   const int csz = precision == MBC_F64 ? 16 : 8;
-  // local-memory budget per workgroup for the S, W and row areas
+  // local-memory budgets per workgroup (forward; backward dS kernel)
   const int64_t budget = precision == MBC_F64 ? 76 * 1024 : 52 * 1024;
+  const int64_t bbudget = precision == MBC_F64 ? 100 * 1024 : 64 * 1024;
   const int kMaxB = 16;
+  const LdsModel fwd_model{false, csz}, bwd_model{true, csz};
   P.corr.assign(size_t(s.n_corr) * kCorrInts, 0);
   P.w_exact.assign(size_t(2 * P.nnz), 0.0);
   P.perm.assign(size_t(P.nnz), 0);
   int64_t w_pos = 0;
   double alg = 0, exec = 0;
-  const int nf[2] = {s.n_u, s.n_d};
+  TileSetOut fo{&P.tiles, &P.ops, &P.meta, nullptr, &P.n_tiles, &P.max_ops, &P.max_b, &exec};
+  TileSetOut bo{&P.b_tiles, &P.b_ops, &P.b_meta, &P.b_extra, &P.b_n_tiles, &P.b_max_ops, &P.b_max_b, nullptr};
 
   for (int c = 0; c < s.n_corr; ++c) {
     int32_t* cr = &P.corr[size_t(c) * kCorrInts];
     const int64_t e0 = s.corr_begin[c], e1 = s.corr_begin[c + 1];
-    cr[3] = P.n_tiles;
+    cr[3] = cr[4] = P.n_tiles;
+    cr[6] = cr[7] = P.b_n_tiles;
     cr[5] = int32_t(e0);
-    if (e0 == e1) {  // empty correlator: C = 0, no tiles
-      cr[4] = P.n_tiles;
-      cr[1] = int32_t(P.src_cu.size());
-      continue;
-    }
-    // sink and source keys
+    cr[66] = int32_t(w_pos);
+    cr[1] = int32_t(P.src_cu.size());
+    if (e0 == e1) continue;  // empty correlator: C = 0, no tiles
+    CorrCtx X;
+    X.c = c;
+    X.nf[0] = s.n_u;
+    X.nf[1] = s.n_d;
+    X.w_base = w_pos;
     std::map<std::pair<Key, Key>, int> snk_id, src_id;
     for (int64_t e = e0; e < e1; ++e) {
       snk_id.emplace(std::make_pair(s.entries[e].ru, s.entries[e].rd), 0);
       src_id.emplace(std::make_pair(s.entries[e].cu, s.entries[e].cd), 0);
     }
-    const int n_snk = int(snk_id.size()), n_src = int(src_id.size());
-    if (int64_t(n_snk) * n_src != e1 - e0)
+    X.n_snk = int(snk_id.size());
+    X.n_src = int(src_id.size());
+    if (int64_t(X.n_snk) * X.n_src != e1 - e0)
       throw std::domain_error("index set of a correlator is not a Cartesian product of sink and source keys");
-    std::vector<std::pair<Key, Key>> snk, src;
-    for (auto& kv : snk_id) snk.push_back(kv.first);
-    for (auto& kv : src_id) src.push_back(kv.first);
+    for (auto& kv : snk_id) X.snk.push_back(kv.first);
+    for (auto& kv : src_id) X.src.push_back(kv.first);
     // plan order of sink keys: by reversed u-tuple, then d-tuple
-    std::sort(snk.begin(), snk.end(), [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
+    std::sort(X.snk.begin(), X.snk.end(), [](const std::pair<Key, Key>& a, const std::pair<Key, Key>& b) {
       if (!(a.first == b.first)) return rev_less(a.first, b.first);
       return a.second < b.second;
     });
-    for (int i = 0; i < n_snk; ++i) snk_id[snk[i]] = i;
-    for (int i = 0; i < n_src; ++i) src_id[src[i]] = i;
-    // entry of (sink i, source j)
-    std::vector<int64_t> ent(size_t(n_snk) * n_src, -1);
+    for (int i = 0; i < X.n_snk; ++i) snk_id[X.snk[i]] = i;
+    for (int i = 0; i < X.n_src; ++i) src_id[X.src[i]] = i;
+    std::vector<int64_t> ent(size_t(X.n_snk) * X.n_src, -1);
     for (int64_t e = e0; e < e1; ++e) {
       const int i = snk_id[{s.entries[e].ru, s.entries[e].rd}];
       const int j = src_id[{s.entries[e].cu, s.entries[e].cd}];
-      int64_t& slot = ent[size_t(i) * n_src + j];
-      if (slot >= 0) throw std::domain_error("duplicate index-set entry");
-      slot = e;
+      int64_t& sl = ent[size_t(i) * X.n_src + j];
+      if (sl >= 0) throw std::domain_error("duplicate index-set entry");
+      sl = e;
     }
+    // plan-ordered weights: [sink key in plan order][source key]
+    for (int i = 0; i < X.n_snk; ++i)
+      for (int j = 0; j < X.n_src; ++j) {
+        const int64_t e = ent[size_t(i) * X.n_src + j];
+        P.perm[size_t(w_pos)] = e;
+        const double den = double(s.w_den[c]);
+        P.w_exact[size_t(2 * w_pos)] = double(s.entries[e].w_re) / den;
+        P.w_exact[size_t(2 * w_pos + 1)] = double(s.entries[e].w_im) / den;
+        ++w_pos;
+      }
     // column levels per flavour: all k-subsets of the source tuples
     std::vector<Key> top_cols[2];
-    for (auto& k : src) {
+    for (auto& k : X.src) {
       top_cols[0].push_back(k.first);
       top_cols[1].push_back(k.second);
     }
-    Levels lev[2] = {column_levels(top_cols[0], nf[0]), column_levels(top_cols[1], nf[1])};
-    int tab_off_fk[2][kMaxQuarks + 1] = {};
+    X.lev[0] = column_levels(top_cols[0], X.nf[0]);
+    X.lev[1] = column_levels(top_cols[1], X.nf[1]);
     for (int f = 0; f < 2; ++f)
-      for (int k = 1; k <= nf[f]; ++k) {
-        const auto& cols = lev[f].cols[k];
-        tab_off_fk[f][k] = int(P.tabs.size());
+      for (int k = 1; k <= X.nf[f]; ++k) {
+        const auto& cols = X.lev[f].cols[k];
+        X.tab_off[f][k] = int(P.tabs.size());
         cr[8 + 2 * (6 * f + k - 1)] = int32_t(cols.size());
         cr[8 + 2 * (6 * f + k - 1) + 1] = int32_t(P.tabs.size());
         for (const Key& C : cols) {
@@ -189,159 +515,57 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
           }
           for (int j = 0; j < k; ++j) {
             const Key rest = drop(C, j);
-            const int sub = (k == 2) ? rest.v[0] : lev[f].index[k - 1].at(rest);
+            const int sub = (k == 2) ? rest.v[0] : X.lev[f].index[k - 1].at(rest);
             if (sub >= 4096) throw std::runtime_error("column list too long");
             P.tabs.push_back(uint16_t((sub << 4) | C.v[j]));
           }
         }
       }
-    auto ncol = [&](int f, int k) { return int(lev[f].cols[k].size()); };
-    // source keys -> top-level column indices
-    cr[0] = n_src;
-    cr[1] = int32_t(P.src_cu.size());
-    cr[2] = n_snk;
-    for (auto& k : src) {
-      P.src_cu.push_back(lev[0].index[nf[0]].at(k.first));
-      P.src_cd.push_back(lev[1].index[nf[1]].at(k.second));
+    cr[0] = X.n_src;
+    cr[2] = X.n_snk;
+    for (auto& k : X.src) {
+      P.src_cu.push_back(X.lev[0].index[X.nf[0]].at(k.first));
+      P.src_cd.push_back(X.lev[1].index[X.nf[1]].at(k.second));
     }
-    P.maxs = std::max(P.maxs, (n_src + P.threads - 1) / P.threads);
-    for (int f = 0; f < 2; ++f)
-      for (int k = 1; k <= nf[f]; ++k) P.qmax = std::max(P.qmax, (ncol(f, k) + P.threads - 1) / P.threads);
+    P.maxs = std::max(P.maxs, (X.n_src + P.threads - 1) / P.threads);
+    for (int f = 0; f < 2; ++f) {
+      P.maxc_top = std::max(P.maxc_top, X.ncol(f, X.nf[f]));
+      for (int k = 1; k <= X.nf[f]; ++k) P.qmax = std::max(P.qmax, (X.ncol(f, k) + P.threads - 1) / P.threads);
+    }
+    backward_tables(X, cr, P.btab);
 
     // algorithmic flops (global minor DAG + leaves + (r_u, c_u) groups)
+    for (int f = 0; f < 2; ++f)
+      for (int k = 2; k <= X.nf[f]; ++k) {
+        std::set<Key> suf;
+        for (auto& kk : X.snk) suf.insert(tail(f == 0 ? kk.first : kk.second, k));
+        alg += double(suf.size()) * X.ncol(f, k) * (8.0 * k - 2.0);
+      }
     {
-      for (int f = 0; f < 2; ++f)
-        for (int k = 2; k <= nf[f]; ++k) {
-          std::set<Key> suf;
-          for (auto& kk : snk) suf.insert(tail(f == 0 ? kk.first : kk.second, k));
-          alg += double(suf.size()) * ncol(f, k) * (8.0 * k - 2.0);
-        }
       std::set<Key> ru, cu;
-      for (auto& kk : snk) ru.insert(kk.first);
-      for (auto& kk : src) cu.insert(kk.first);
-      alg += 8.0 * double(n_snk) * n_src + 8.0 * double(ru.size()) * cu.size();
+      for (auto& kk : X.snk) ru.insert(kk.first);
+      for (auto& kk : X.src) cu.insert(kk.first);
+      alg += 8.0 * double(X.n_snk) * X.n_src + 8.0 * double(ru.size()) * cu.size();
     }
 
-    // runs of equal u-tuples
-    std::vector<std::pair<int, int>> runs;  // [begin, end)
-    for (int i = 0; i < n_snk;) {
-      int j = i + 1;
-      while (j < n_snk && snk[j].first == snk[i].first) ++j;
-      runs.push_back({i, j});
-      i = j;
-    }
-    auto tile_lds = [&](const std::vector<int>& sk) {
-      std::set<RowId> rows;
-      for (int i : sk) {
-        add_chain(0, snk[i].first, &rows);
-        add_chain(1, snk[i].second, &rows);
-      }
-      int64_t units = 576 + int64_t(sk.size()) * n_src;
-      for (auto& r : rows) units += ncol(r.f, r.k);
-      return units * csz + int64_t(rows.size()) * 16;
-    };
-    // greedy tiling over whole runs (a run longer than a tile is split)
-    std::vector<std::vector<int>> tiles;
-    std::vector<int> cur;
-    for (auto& rn : runs) {
-      std::vector<int> run;
-      for (int i = rn.first; i < rn.second; ++i) run.push_back(i);
-      std::vector<int> trial = cur;
-      trial.insert(trial.end(), run.begin(), run.end());
-      if (!cur.empty() && (int(trial.size()) > kMaxB || tile_lds(trial) > budget)) {
-        tiles.push_back(cur);
-        cur.clear();
-      }
-      for (int i : run) {
-        std::vector<int> t2 = cur;
-        t2.push_back(i);
-        if (!cur.empty() && (int(t2.size()) > kMaxB || tile_lds(t2) > budget)) {
-          tiles.push_back(cur);
-          cur.clear();
-        }
-        cur.push_back(i);
-      }
-    }
-    if (!cur.empty()) tiles.push_back(cur);
-
-    for (auto& sk : tiles) {
-      const int B = int(sk.size());
-      std::set<RowId> rowset;
-      for (int i : sk) {
-        add_chain(0, snk[i].first, &rowset);
-        add_chain(1, snk[i].second, &rowset);
-      }
-      // slots in (level, flavour, tuple) order; phases = levels
-      std::map<RowId, int> slot;
-      int units = 0;
-      for (auto& r : rowset) {
-        slot[r] = units;
-        units += ncol(r.f, r.k);
-      }
-      // double-buffered S, the tile's weights, row slots, staged (r0, in, out) ops
-      const int64_t lds = int64_t(576 + int64_t(B) * n_src + units) * csz + int64_t(rowset.size()) * 16;
-      if (lds > 160 * 1024) throw std::runtime_error("a tile exceeds the 160 KiB local memory of a CU");
-      P.lds_bytes = std::max(P.lds_bytes, lds);
-      std::vector<int32_t> tr(kTileInts, 0);
-      tr[0] = c;
-      tr[1] = B;
-      tr[2] = int32_t(w_pos);
-      tr[3] = int32_t(P.ops.size() / kOpInts);
-      tr[5] = int32_t(P.meta.size() / kMetaInts);
-      tr[6] = units;
-      tr[16] = sk[0];
-      int n_ops = 0, phase = -1, cur_level = 0, item = 0;
-      for (auto& r : rowset) {
-        if (r.k != cur_level) {
-          ++phase;
-          if (phase >= kMaxPhases) throw std::runtime_error("too many phases");
-          tr[8 + phase] = n_ops;
-          cur_level = r.k;
-          item = 0;
-        }
-        int in = 0;
-        if (r.k == 2) in = r.t.v[1];
-        if (r.k >= 3) in = slot.at({r.f, r.k - 1, tail(r.t, r.k - 1)});
-        const int nc = ncol(r.f, r.k);
-        if (tr[21 + 2 * (7 * r.f + r.k)] == 0) tr[20 + 2 * (7 * r.f + r.k)] = n_ops;
-        ++tr[21 + 2 * (7 * r.f + r.k)];
-        const int32_t op[kOpInts] = {r.f, r.k, r.t.v[0], in, slot.at(r), tab_off_fk[r.f][r.k], nc, item};
-        P.ops.insert(P.ops.end(), op, op + kOpInts);
-        item += nc;
-        ++n_ops;
-        if (r.k >= 2) exec += double(nc) * (8.0 * r.k - 2.0);
-      }
-      tr[4] = n_ops;
-      tr[7] = phase + 1;
-      tr[8 + phase + 1] = n_ops;
-      P.max_ops = std::max(P.max_ops, n_ops);
-      // per sink key metadata and the tile's weights (b-major)
-      int pieces = 0;
-      for (int b = 0; b < B; ++b) {
-        const int i = sk[b];
-        const bool run_end = (b + 1 == B) || !(snk[sk[b + 1]].first == snk[i].first);
-        pieces += run_end;
-        const int u_slot = slot.at({0, nf[0], snk[i].first});
-        const int d_slot = slot.at({1, nf[1], snk[i].second});
-        const int32_t m[kMetaInts] = {u_slot, d_slot, run_end ? 1 : 0, i};
-        P.meta.insert(P.meta.end(), m, m + kMetaInts);
-        for (int j = 0; j < n_src; ++j) {
-          const int64_t e = ent[size_t(i) * n_src + j];
-          P.perm[size_t(w_pos)] = e;
-          const double den = double(s.w_den[c]);
-          P.w_exact[size_t(2 * w_pos)] = double(s.entries[e].w_re) / den;
-          P.w_exact[size_t(2 * w_pos + 1)] = double(s.entries[e].w_im) / den;
-          ++w_pos;
-        }
-      }
-      exec += 8.0 * double(B) * n_src + 8.0 * double(pieces) * n_src;
-      P.max_b = std::max(P.max_b, B);
-      P.tiles.insert(P.tiles.end(), tr.begin(), tr.end());
-      ++P.n_tiles;
-    }
+    auto ft = make_tiles(X, budget, kMaxB, fwd_model);
+    P.lds_bytes = std::max(P.lds_bytes, emit_tiles(X, ft, fwd_model, fo));
     cr[4] = P.n_tiles;
+    auto bt = make_tiles(X, bbudget, kMaxB, bwd_model);
+    P.b_lds_ds = std::max(P.b_lds_ds, emit_tiles(X, bt, bwd_model, bo));
+    cr[7] = P.b_n_tiles;
   }
   if (w_pos != P.nnz) throw std::logic_error("plan does not cover the index set");
+  // dW kernel of the backward tiling: S (double buffer), rows, staged ops,
+  // and compensated accumulators of the tile's weights (16 B each)
+  for (int t = 0; t < P.b_n_tiles; ++t) {
+    const int32_t* tr = &P.b_tiles[size_t(t) * kTileInts];
+    const int32_t* cr = &P.corr[size_t(tr[0]) * kCorrInts];
+    int64_t bytes = (576 + int64_t(tr[6])) * csz;
+    bytes = (bytes + 15) & ~int64_t(15);
+    const int64_t lds = bytes + int64_t(tr[17]) * 16 + int64_t(tr[1]) * cr[0] * 2 * csz;
+    P.b_lds_dw = std::max(P.b_lds_dw, lds);
+  }
   P.alg_flops_per_site = alg;
   P.exec_flops_per_site = exec;
 }

@@ -154,3 +154,38 @@ def test_plan_statistics_dinucleon():
     # global minor DAG: 2 x (52*66*14 + 208*208*22) + 8*(520^2 + 208^2)
     assert st.alg_flops_per_site == 2 * (52 * 66 * 14 + 208 * 208 * 22) + 8 * (520 ** 2 + 208 ** 2)
     assert st.lds_bytes <= 160 * 1024
+
+
+def host_backward(ods, Su, Sd, gC, W=None):
+    iset = IndexSet(ods)
+    gW = np.zeros(iset.nnz, dtype=np.complex128)
+    gSu = np.zeros_like(Su)
+    gSd = np.zeros_like(Sd)
+    T, V = Su.shape[:2]
+    Wc = None if W is None else np.ascontiguousarray(W, dtype=np.complex128)
+    gC = np.ascontiguousarray(gC, dtype=np.complex128)
+    B.check(B.lib().mbc_debug_backward_host(iset._h, B.F64, np.ascontiguousarray(Su).ctypes.data,
+                                            np.ascontiguousarray(Sd).ctypes.data, T, V,
+                                            None if Wc is None else Wc.ctypes.data, gC.ctypes.data,
+                                            gW.ctypes.data, gSu.ctypes.data, gSd.ctypes.data))
+    return gW, gSu, gSd
+
+
+@pytest.mark.parametrize("ods,T,V", [
+    ([dict(op="proton", snk_spin=0, src_spin=0)], 2, 2),
+    ([dict(op="proton", snk_spin=1, src_spin=2), dict(op="proton", snk_spin=3, src_spin=3)], 1, 2),
+    ([dict(op="DI")], 2, 1),
+    ([dict(op="DI"), dict(op="DII", sign_mode="r2"), dict(op="DII")], 1, 1),
+    ([dict(op="HE3_I", snk_spin=1, src_spin=1)], 1, 1),
+], ids=["proton", "p2", "DI", "DI+DII", "He3"])
+def test_backward_walk_matches_oracle_gradients(ods, T, V):
+    Su, Sd = synth.iid(T, V, seed=23)
+    rs = O.build_index_set(ods)
+    rng = np.random.default_rng(4)
+    gC = rng.standard_normal((rs.n_corr, T)) + 1j * rng.standard_normal((rs.n_corr, T))
+    gW, gSu, gSd = host_backward(ods, Su, Sd, gC)
+    ref = CO.gradients(Su, Sd, rs, gC)
+    for name, got in (("W", gW), ("S_u", gSu), ("S_d", gSd)):
+        r = ref[name]
+        scale = np.max(np.abs(r)) + 1e-300
+        assert np.max(np.abs(got - r)) <= 1e-11 * scale, name
