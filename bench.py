@@ -68,10 +68,14 @@ def _oracle_init(ops):
 
 
 def _oracle_sites(args):
-    """Oracle forward on a slice of sites (run in a worker process)."""
+    """Oracle forward and gradients on a slice of sites (in a worker process)."""
     Su, Sd = args
+    import numpy as np
     from oracle import correlator as CO
-    CO.site_values(Su, Sd, _W_ISET)
+    S4u, S4d = Su[None], Sd[None]
+    CO.correlator(S4u, S4d, _W_ISET)
+    gC = np.ones((_W_ISET.n_corr, 1), dtype=np.complex128)
+    CO.gradients(S4u, S4d, _W_ISET, gC)
     return Su.shape[0]
 
 
@@ -79,9 +83,9 @@ def cpu_baseline(wl, Su, Sd, nnz, budget_s=15.0):
     """Time the FP64 oracle (as it stands) on a bounded sample of sites.
 
     The sample is the first n sites of the workload, n sized so that the run
-    takes about budget_s seconds; the oracle's forward (determinants of every
-    needed submatrix, then the sum over the index set) runs with one process
-    per host core over sites.
+    takes about budget_s seconds; per site the oracle's forward (determinants
+    of every needed submatrix, then the sum over the index set) and its
+    gradients (dW, dS_u, dS_d by cofactors) run, one process per host core.
     """
     ops = wl["ops"][:1] if wl["name"] == "di_mixed" else wl["ops"]
     nproc = min(os.cpu_count() or 1, 16)
@@ -100,8 +104,8 @@ def cpu_baseline(wl, Su, Sd, nnz, budget_s=15.0):
         t0 = time.perf_counter()
         done = sum(pool.map(_oracle_sites, chunks, chunksize=1))
         dt = time.perf_counter() - t0
-    return {"value": nnz * done / dt, "unit": "index entries/s (fwd)", "cores": nproc, "kind": "oracle",
-            "sample": f"oracle forward over the first {done} sites of this workload ({dt:.1f} s)"}
+    return {"value": nnz * done / dt, "unit": "index entries/s (fwd+bwd)", "cores": nproc, "kind": "oracle",
+            "sample": f"oracle forward + gradients over the first {done} sites of this workload ({dt:.1f} s)"}
 
 
 def main():
@@ -112,6 +116,7 @@ def main():
     ap.add_argument("--workload", default="di_mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="f32c,f64")
+    ap.add_argument("--fwd-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -147,45 +152,70 @@ def main():
     n_sites = T * V
     entries = float(nnz) * n_sites
     stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(11)
+    n_corr = len(iset_ops)
+    gC = torch.from_numpy(rng.standard_normal((n_corr, T)) + 1j * rng.standard_normal((n_corr, T))).to(dev)
+    do_bwd = not args.fwd_only
+
+    def timed(fn, n):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(n):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / n
 
     results = {}
     for prec in args.precisions.split(","):
         t0 = time.perf_counter()
         plan = api.Plan(iset, prec)
         st = plan.stats
-        print(f"[bench] plan {prec}: tiles={st['n_tiles']} lds={st['lds_bytes']} "
-              f"alg={st['alg_flops_per_site']:.3e} exec={st['exec_flops_per_site']:.3e} "
+        print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']} lds={st['lds_bytes']}/"
+              f"{st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} alg fwd={st['alg_flops_per_site']:.3e} "
+              f"dS={st['ds_alg_flops_per_site']:.3e} dW={st['dw_alg_flops_per_site']:.3e} "
               f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
 
-        def step():
+        def fwd():
             return api.contract(plan, su, sd, W)
+
+        def bwd_s():
+            return api.contract_backward(plan, su, sd, W, gC, need_W=False, need_S=True)
+
+        def bwd_w():
+            return api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=False)
+
+        def step():
+            fwd()
+            if do_bwd:
+                api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=True)
 
         for _ in range(args.warmup):
             step()
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
         t_wall = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            step()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
-        ms = ev0.elapsed_time(ev1) / args.steps
-        alg = st["alg_flops_per_site"] * n_sites
-        results[prec] = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall / args.steps,
-                             value=entries / (ms * 1e-3), alg_tflops=alg / (ms * 1e-3) / 1e12,
-                             exec_tflops=st["exec_flops_per_site"] * n_sites / (ms * 1e-3) / 1e12,
-                             frac=alg / (ms * 1e-3) / PEAK[prec], tiles=st["n_tiles"],
-                             lds_bytes=st["lds_bytes"])
-        print(f"[bench] {prec}: {ms:.3f} ms/step  {entries / (ms * 1e-3):.3e} entries/s  "
-              f"alg {alg / (ms * 1e-3) / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
+        ms = timed(step, args.steps)
+        wall = (time.perf_counter() - t_wall) / args.steps
+        kern = {"fwd": (timed(fwd, args.steps), st["alg_flops_per_site"])}
+        if do_bwd:
+            kern["dS"] = (timed(bwd_s, args.steps), st["ds_alg_flops_per_site"])
+            kern["dW"] = (timed(bwd_w, args.steps), st["dw_alg_flops_per_site"])
+        dom = max(kern, key=lambda k: kern[k][0])
+        r = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall, value=entries / (ms * 1e-3), dominant=dom,
+                 kernels={k: {"ms": v[0], "alg_tflops": v[1] * n_sites / (v[0] * 1e-3) / 1e12,
+                              "frac": v[1] * n_sites / (v[0] * 1e-3) / PEAK[prec]} for k, v in kern.items()},
+                 fwd_value=entries / (kern["fwd"][0] * 1e-3),
+                 exec_tflops_fwd=st["exec_flops_per_site"] * n_sites / (kern["fwd"][0] * 1e-3) / 1e12)
+        results[prec] = r
+        print(f"[bench] {prec}: step {ms:.3f} ms ({entries / (ms * 1e-3):.3e} entries/s) " +
+              " ".join(f"{k} {v['ms']:.2f} ms {v['alg_tflops']:.2f} TF" for k, v in r["kernels"].items()),
+              file=sys.stderr, flush=True)
         del plan
 
     head = "f32c" if "f32c" in results else list(results)[0]
     r = results[head]
-    st_alg = None
+    dk = r["kernels"][r["dominant"]]
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -199,17 +229,17 @@ def main():
         "vs_baseline": None,
         "dtype": head,
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "pass": "fwd", "sites": n_sites, "nnz": nnz,
-                   "index_entries_per_step": entries},
-        "roofline": {"bound": "alu", "achieved": r["alg_tflops"], "peak": PEAK[head] / 1e12,
-                     "unit": "TFLOP/s", "frac": r["frac"], "traffic": None},
+        "config": {"workload": wl["desc"], "pass": "fwd+bwd" if do_bwd else "fwd", "sites": n_sites,
+                   "nnz": nnz, "index_entries_per_step": entries},
+        "roofline": {"bound": "alu", "kernel": r["dominant"], "achieved": dk["alg_tflops"],
+                     "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": dk["frac"], "traffic": None},
+        "kernels": r["kernels"],
+        "fwd_only_value": r["fwd_value"],
     }
     for prec, rr in results.items():
         if prec != head:
-            out[prec] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"],
-                         "roofline": {"bound": "alu", "achieved": rr["alg_tflops"], "peak": PEAK[prec] / 1e12,
-                                      "unit": "TFLOP/s", "frac": rr["frac"]}}
-    out["exec_tflops"] = {p: rr["exec_tflops"] for p, rr in results.items()}
+            out[prec] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "fwd_only_value": rr["fwd_value"],
+                         "kernels": rr["kernels"]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, Su, Sd, nnz)
     print(json.dumps(out), flush=True)

@@ -127,6 +127,11 @@ typedef struct {
   double alg_flops_per_site;  /* sum_k #minors_k (8k-2) + 8 (#leaves + #groups), global minor DAG */
   double exec_flops_per_site; /* the same count over what the kernel executes (with recomputation) */
   double in_bytes_per_site;   /* propagator bytes read per site (both flavours) */
+  int32_t b_n_tiles;          /* tiles of the backward schedule */
+  int64_t b_lds_bytes_ds;     /* dynamic LDS per workgroup, dS kernel */
+  int64_t b_lds_bytes_dw;     /* dynamic LDS per workgroup, dW kernel */
+  double ds_alg_flops_per_site; /* dS: minors + reverse sweep (16k per level-k minor) + 16 per entry */
+  double dw_alg_flops_per_site; /* dW: minors + 8 per entry */
 } mbc_plan_stats;
 mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out);
 

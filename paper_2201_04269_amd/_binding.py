@@ -33,7 +33,9 @@ class PlanStats(ctypes.Structure):
                 ("n_d", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
                 ("alg_flops_per_site", ctypes.c_double), ("exec_flops_per_site", ctypes.c_double),
-                ("in_bytes_per_site", ctypes.c_double)]
+                ("in_bytes_per_site", ctypes.c_double), ("b_n_tiles", ctypes.c_int32),
+                ("b_lds_bytes_ds", ctypes.c_int64), ("b_lds_bytes_dw", ctypes.c_int64),
+                ("ds_alg_flops_per_site", ctypes.c_double), ("dw_alg_flops_per_site", ctypes.c_double)]
 
 
 _lib = None

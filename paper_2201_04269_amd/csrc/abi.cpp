@@ -263,6 +263,11 @@ mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out) {
   out->alg_flops_per_site = p->h.alg_flops_per_site;
   out->exec_flops_per_site = p->h.exec_flops_per_site;
   out->in_bytes_per_site = 2.0 * 144.0 * 16.0;
+  out->b_n_tiles = p->h.b_n_tiles;
+  out->b_lds_bytes_ds = p->h.b_lds_ds;
+  out->b_lds_bytes_dw = p->h.b_lds_dw;
+  out->ds_alg_flops_per_site = p->h.ds_alg_flops_per_site;
+  out->dw_alg_flops_per_site = p->h.dw_alg_flops_per_site;
   return MBC_OK;
 }
 

@@ -87,6 +87,11 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
     stats->alg_flops_per_site = h.alg_flops_per_site;
     stats->exec_flops_per_site = h.exec_flops_per_site;
     stats->in_bytes_per_site = 2.0 * 144.0 * 16.0;
+    stats->b_n_tiles = h.b_n_tiles;
+    stats->b_lds_bytes_ds = h.b_lds_ds;
+    stats->b_lds_bytes_dw = h.b_lds_dw;
+    stats->ds_alg_flops_per_site = h.ds_alg_flops_per_site;
+    stats->dw_alg_flops_per_site = h.dw_alg_flops_per_site;
   }
   return MBC_OK;
 }

@@ -109,6 +109,7 @@ struct PlanHost {
   std::vector<int64_t> perm;      // plan-ordered W slot -> index-set entry
   std::vector<double> w_exact;    // plan-ordered exact W (re, im)
   double alg_flops_per_site = 0, exec_flops_per_site = 0;
+  double ds_alg_flops_per_site = 0, dw_alg_flops_per_site = 0;
 };
 
 // Compiles a plan; throws std::invalid_argument / std::runtime_error.

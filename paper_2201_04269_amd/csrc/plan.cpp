@@ -440,7 +440,7 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.w_exact.assign(size_t(2 * P.nnz), 0.0);
   P.perm.assign(size_t(P.nnz), 0);
   int64_t w_pos = 0;
-  double alg = 0, exec = 0;
+  double alg = 0, exec = 0, ds_alg = 0, dw_alg = 0;
   TileSetOut fo{&P.tiles, &P.ops, &P.meta, nullptr, &P.n_tiles, &P.max_ops, &P.max_b, &exec};
   TileSetOut bo{&P.b_tiles, &P.b_ops, &P.b_meta, &P.b_extra, &P.b_n_tiles, &P.b_max_ops, &P.b_max_b, nullptr};
 
@@ -534,13 +534,21 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     }
     backward_tables(X, cr, P.btab);
 
-    // algorithmic flops (global minor DAG + leaves + (r_u, c_u) groups)
+    // algorithmic flops (global minor DAG + leaves + (r_u, c_u) groups);
+    // backward: the minors once more, the reverse sweep (k complex products
+    // for the parent adjoint and k for the S adjoint per minor), both leaf
+    // adjoint sums (dS); the minors and one product per entry (dW)
+    double minors = 0, rev = 0;
     for (int f = 0; f < 2; ++f)
       for (int k = 2; k <= X.nf[f]; ++k) {
         std::set<Key> suf;
         for (auto& kk : X.snk) suf.insert(tail(f == 0 ? kk.first : kk.second, k));
-        alg += double(suf.size()) * X.ncol(f, k) * (8.0 * k - 2.0);
+        minors += double(suf.size()) * X.ncol(f, k) * (8.0 * k - 2.0);
+        rev += double(suf.size()) * X.ncol(f, k) * 16.0 * k;
       }
+    alg += minors;
+    ds_alg += minors + rev + 16.0 * double(X.n_snk) * X.n_src;
+    dw_alg += minors + 8.0 * double(X.n_snk) * X.n_src;
     {
       std::set<Key> ru, cu;
       for (auto& kk : X.snk) ru.insert(kk.first);
@@ -568,6 +576,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   }
   P.alg_flops_per_site = alg;
   P.exec_flops_per_site = exec;
+  P.ds_alg_flops_per_site = ds_alg;
+  P.dw_alg_flops_per_site = dw_alg;
 }
 
 }  // namespace mbc

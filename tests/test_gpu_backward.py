@@ -121,13 +121,23 @@ def test_autograd_function_and_central_differences():
             assert abs(float(fd) - float(c.grad[i])) <= 1e-9 * max(1.0, abs(float(fd)))
         # under R2, W_DII = 2 W_DI exactly, so dL/dc2 = 2 dL/dc1
         assert abs(float(c.grad[1]) - 2 * float(c.grad[0])) <= 1e-9 * abs(float(c.grad[0]))
+        # C is a cubic polynomial in S_u (and in S_d): the five-point stencil
+        # (8 [L(h) - L(-h)] - [L(2h) - L(-2h)]) / 12h is exact for it up to rounding
         E = torch.from_numpy(rng.standard_normal(Su.shape) + 1j * rng.standard_normal(Su.shape)).cuda()
-        fd = (loss(c, su + h * E, sd) - loss(c, su - h * E, sd)) / (2 * h)
+
+        def fd5(f):
+            return (8 * (f(h) - f(-h)) - (f(2 * h) - f(-2 * h))) / (12 * h)
+
+        fd = fd5(lambda d: loss(c, su + d * E, sd))
         an = torch.real(torch.sum(torch.conj(su.grad) * E))
-        assert abs(float(fd) - float(an)) <= 1e-7 * max(1.0, abs(float(an)))
-        fd = (loss(c, su, sd + h * E) - loss(c, su, sd - h * E)) / (2 * h)
+        assert abs(float(fd) - float(an)) <= 1e-8 * max(1.0, abs(float(an)))
+        fd = fd5(lambda d: loss(c, su, sd + d * E))
         an = torch.real(torch.sum(torch.conj(sd.grad) * E))
-        assert abs(float(fd) - float(an)) <= 1e-7 * max(1.0, abs(float(an)))
+        assert abs(float(fd) - float(an)) <= 1e-8 * max(1.0, abs(float(an)))
+        # the plain central difference agrees to its O(h^2) truncation error
+        fd2 = (loss(c, su + h * E, sd) - loss(c, su - h * E, sd)) / (2 * h)
+        an = torch.real(torch.sum(torch.conj(su.grad) * E))
+        assert abs(float(fd2) - float(an)) <= 1e-5 * max(1.0, abs(float(an)))
 
 
 def test_backward_reproducible():
