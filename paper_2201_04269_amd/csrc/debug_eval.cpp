@@ -119,7 +119,7 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
     const int nf[2] = {h.n_u, h.n_d};
     const int32_t* ex = &h.b_extra[size_t(tr[19])];
     const int n_runs = ex[0], n_dg = ex[1];
-    const int32_t* runs = ex + 2;
+    const int32_t* runs = ex + 3;
     const int32_t* dgs = runs + 3 * n_runs;
     const int32_t* child = dgs + 2 * n_dg;
     auto op = [&](int o) { return &h.b_ops[size_t(op0 + o) * kOpInts]; };
@@ -226,17 +226,18 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
             if (p[6] == 0) continue;  // a top row: its adjoint came from the leaves
             const int f = p[0];
             const int ncp = cr[8 + 2 * (6 * f + k - 2)];
-            const int32_t* sup = &h.btab[size_t(cr[52 + 6 * f + k - 2])];
+            const int32_t* ut = &h.btab[size_t(cr[67 + 6 * f + k - 2])];
             const int toff1 = cr[8 + 2 * (6 * f + 0) + 1];
             const cd* Sf = &S[144 * f];
             for (int c = 0; c < ncp; ++c) {
               cd sum(0, 0);
               for (int ci = 0; ci < p[6]; ++ci) {
                 const int32_t* ch = op(child[p[5] + ci]);
-                for (int q = sup[c]; q < sup[c + 1]; ++q) {
-                  const int e = sup[q], C = e & 4095, j = (e >> 12) & 15, pos = e >> 16;
-                  const cd term = A[ch[4] + C] * Sf[12 * ch[2] + j];
-                  sum += (pos & 1) ? -term : term;
+                for (int j = 0; j < 12; ++j) {
+                  const int ent = (ut[6 * c + j / 2] >> (16 * (j % 2))) & 0xffff;
+                  if (ent == 0xffff) continue;
+                  const cd term = A[ch[4] + (ent & 4095)] * Sf[12 * ch[2] + j];
+                  sum += ((ent >> 12) & 1) ? -term : term;
                 }
               }
               if (virt)

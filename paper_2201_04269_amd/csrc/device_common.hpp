@@ -59,6 +59,44 @@ __device__ __forceinline__ C cmul(C a, C b) {
   return r;
 }
 
+// Sum over the 16 lanes of each DPP row (every lane receives the row sum):
+// rotations by 8, 4, 2, 1 within the row double the covered lanes each step.
+__device__ __forceinline__ float row16_sum(float x) {
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x128, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x124, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x122, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x121, 0xf, 0xf, false));
+  return x;
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(v & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(v >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_f64<0x128>(x);
+  x += dpp_f64<0x124>(x);
+  x += dpp_f64<0x122>(x);
+  x += dpp_f64<0x121>(x);
+  return x;
+}
+
+// Negates a complex value when `odd` is 1 (flips both sign bits).
+__device__ __forceinline__ float2 cneg_if(float2 v, int odd) {
+  const unsigned m = unsigned(odd) << 31;
+  v.x = __uint_as_float(__float_as_uint(v.x) ^ m);
+  v.y = __uint_as_float(__float_as_uint(v.y) ^ m);
+  return v;
+}
+__device__ __forceinline__ double2 cneg_if(double2 v, int odd) {
+  const unsigned long long m = static_cast<unsigned long long>(odd) << 63;
+  v.x = __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v.x)) ^ m));
+  v.y = __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(v.y)) ^ m));
+  return v;
+}
+
 // Knuth's TwoSum: s + e == a + b exactly (round-to-nearest, no reassociation).
 template <typename R>
 __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {

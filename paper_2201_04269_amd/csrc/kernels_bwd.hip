@@ -203,7 +203,295 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const double* __restrict
 // ---------------------------------------------------------------------------
 // dS
 // ---------------------------------------------------------------------------
-template <typename R, int NU, int ND, int QMAX>
+// Register tables of the reverse sweep, loaded once per correlator.
+//
+// S-bar partials of a level-K row: bin j collects the columns C that contain
+// j.  Levels K <= 2 have short bins (at most 11 entries): one lane per bin,
+// thread t takes bin t % 12 of row group t / 12 (21 rows side by side).
+// Levels K >= 3: a DPP row of 16 lanes per bin, thread t takes bin t / 16
+// (t < 192) of one row, lane t % 16 holds entries l, l + 16, ...
+__host__ __device__ constexpr int bin_regs(int k) { return k == 1 ? 1 : (k == 2 ? 11 : (k == 3 ? 4 : (k == 4 ? 11 : 14))); }
+__host__ __device__ constexpr int bin_lanes(int k) { return k <= 2 ? 1 : 16; }
+
+template <int K>
+struct BinTab {
+  int n = 0;
+  int e[bin_regs(K)];
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab) {
+    const int t = threadIdx.x;
+    n = 0;
+#pragma unroll
+    for (int m = 0; m < bin_regs(K); ++m) e[m] = 0;
+    const int32_t* jl = btab + cr[40 + 6 * f + K - 1];
+    int j, l;
+    if constexpr (K <= 2) {
+      if (t >= 252) return;
+      j = t % 12;
+      l = 0;
+    } else {
+      if (t >= 192) return;
+      j = t >> 4;
+      l = t & 15;
+    }
+    const int q0 = jl[j], q1 = jl[j + 1];
+#pragma unroll
+    for (int m = 0; m < bin_regs(K); ++m) {
+      const int q = q0 + l + bin_lanes(K) * m;
+      if (q < q1) {
+        e[m] = jl[q];
+        n = m + 1;
+      }
+    }
+  }
+};
+
+// Parent adjoints: the (parent, column) items of a level are spread like the
+// forward row items: with ncol <= NT, G = NT / ncol parents side by side
+// (thread t: column t % ncol of parent group t / ncol); else columns t, t + NT.
+// Entries: index of C' + {j} one level up | parity of the position of j << 11
+// | j << 12, compacted (count n), two per int32.
+template <int K, int QMAX>
+struct UpTab {
+  int ncol = 0, G = 1, g = 0, i0 = 0;
+  int n[QMAX];
+  unsigned up[QMAX][6];
+  int colnum[QMAX];
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab,
+                                       const uint16_t* __restrict__ tabs) {
+    ncol = cr[8 + 2 * (6 * f + K - 1)];
+    const int32_t* ut = btab + cr[67 + 6 * f + K - 1];
+    const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
+    const int t = threadIdx.x;
+    if (ncol > 0 && ncol <= kNT) {
+      G = kNT / ncol;
+      g = t / ncol;
+      i0 = t % ncol;
+    } else {
+      G = 1;
+      g = 0;
+      i0 = t;
+    }
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int c = i0 + kNT * q;
+      const bool ok = c < ncol && g < G;
+      int cnt = 0;
+#pragma unroll
+      for (int w = 0; w < 6; ++w) up[q][w] = 0;
+#pragma unroll
+      for (int j = 0; j < 12; ++j) {
+        const unsigned ent = ok ? ((unsigned(ut[6 * c + (j >> 1)]) >> (16 * (j & 1))) & 0xffffu) : 0xffffu;
+        if (ent != 0xffffu) {
+          const unsigned packed = (ent & 2047u) | (((ent >> 12) & 1u) << 11) | (unsigned(j) << 12);
+          // compact: entry cnt goes to half (cnt & 1) of word cnt >> 1
+#pragma unroll
+          for (int w = 0; w < 6; ++w)
+            if ((cnt >> 1) == w) up[q][w] |= packed << (16 * (cnt & 1));
+          ++cnt;
+        }
+      }
+      n[q] = cnt;
+      colnum[q] = (K == 1 && ok) ? int(tabs[toff + c]) : 0;
+    }
+  }
+};
+
+// Leaf adjoints: thread owns top columns c = t, t + NT and keeps the source
+// keys of each (s | other-flavour column << 11).
+template <int QMAX, int MC>
+struct CsrTab {
+  int ncol = 0;
+  int n[QMAX];
+  int e[QMAX][MC];
+  __device__ __forceinline__ void load(const int32_t* cr, int f, int nf, const int32_t* __restrict__ btab,
+                                       const int32_t* __restrict__ other_col) {
+    ncol = cr[8 + 2 * (6 * f + nf - 1)];
+    const int32_t* lists = btab + cr[64 + f];
+    const int src_off = cr[1];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int c = threadIdx.x + kNT * q;
+      n[q] = 0;
+      int q0 = 0;
+      if (c < ncol) {
+        q0 = lists[c];
+        n[q] = lists[c + 1] - q0;
+      }
+#pragma unroll
+      for (int m = 0; m < MC; ++m) {
+        int v = 0;
+        if (m < n[q]) {
+          const int sidx = lists[q0 + m];
+          v = sidx | (other_col[src_off + sidx] << 11);
+        }
+        e[q][m] = v;
+      }
+    }
+  }
+};
+
+template <int NF, int QMAX>
+struct RevTabs {
+  BinTab<1> b1;
+  BinTab<2> b2;
+  BinTab<3> b3;
+  BinTab<4> b4;
+  BinTab<5> b5;
+  UpTab<1, QMAX> u1;
+  UpTab<2, QMAX> u2;
+  UpTab<3, QMAX> u3;
+  UpTab<4, QMAX> u4;
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* btab, const uint16_t* tabs) {
+    if constexpr (NF == 1) b1.load(cr, f, btab);
+    if constexpr (NF >= 2) b2.load(cr, f, btab);
+    if constexpr (NF >= 3) b3.load(cr, f, btab);
+    if constexpr (NF >= 4) b4.load(cr, f, btab);
+    if constexpr (NF >= 5) b5.load(cr, f, btab);
+    if constexpr (NF >= 2) u1.load(cr, f, btab, tabs);
+    if constexpr (NF >= 3) u2.load(cr, f, btab, tabs);
+    if constexpr (NF >= 4) u3.load(cr, f, btab, tabs);
+    if constexpr (NF >= 5) u4.load(cr, f, btab, tabs);
+  }
+};
+
+template <int K, int NF, int QMAX>
+__device__ __forceinline__ const BinTab<K>& bins_of(const RevTabs<NF, QMAX>& rt) {
+  if constexpr (K == 1) return rt.b1;
+  else if constexpr (K == 2) return rt.b2;
+  else if constexpr (K == 3) return rt.b3;
+  else if constexpr (K == 4) return rt.b4;
+  else return rt.b5;
+}
+template <int K, int NF, int QMAX>
+__device__ __forceinline__ const UpTab<K, QMAX>& ups_of(const RevTabs<NF, QMAX>& rt) {
+  if constexpr (K == 1) return rt.u1;
+  else if constexpr (K == 2) return rt.u2;
+  else if constexpr (K == 3) return rt.u3;
+  else return rt.u4;
+}
+
+template <int K, typename C>
+__device__ __forceinline__ C bin_sum(const BinTab<K>& bt, int4 ov, const C* Sf, const C* sR, const C* sA) {
+  C sum = cmake<C>(0, 0);
+#pragma unroll
+  for (int m = 0; m < bin_regs(K); ++m) {
+    if (m < bt.n) {
+      const int e = bt.e[m];
+      const C av = sA[ov.z + (e & 4095)];
+      if constexpr (K == 1) {
+        sum.x += av.x;
+        sum.y += av.y;
+      } else {
+        const int sub = (e >> 12) & 4095;
+        const C y = (K == 2) ? Sf[12 * ov.y + sub] : sR[ov.y + sub];
+        sum = cmac(cneg_if(av, (e >> 24) & 1), y, sum);
+      }
+    }
+  }
+  return sum;
+}
+
+// (ii) S-bar partials of the level-K rows [o0, o0 + cnt) of one flavour:
+// part[o][j] = sum over columns C containing j of (-1)^pos A(C) M_{K-1}(C \ j).
+template <int K, typename C>
+__device__ __forceinline__ void rev_part(const BinTab<K>& bt, int o0, int cnt, const int4* sOpv, const C* Sf,
+                                         const C* sR, const C* sA, C* sPart) {
+  const int tid = threadIdx.x;
+  if constexpr (K <= 2) {
+    if (tid >= 252) return;
+    const int j = tid % 12;
+    for (int o = o0 + tid / 12; o < o0 + cnt; o += 21) sPart[12 * o + j] = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
+  } else {
+    if (tid >= 192) return;
+    for (int o = o0; o < o0 + cnt; o += 2) {
+      const bool two = o + 1 < o0 + cnt;
+      C s0 = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
+      C s1 = two ? bin_sum<K>(bt, sOpv[o + 1], Sf, sR, sA) : cmake<C>(0, 0);
+      s0.x = row16_sum(s0.x);
+      s0.y = row16_sum(s0.y);
+      s1.x = row16_sum(s1.x);
+      s1.y = row16_sum(s1.y);
+      if ((tid & 15) == 0) {
+        sPart[12 * o + (tid >> 4)] = s0;
+        if (two) sPart[12 * (o + 1) + (tid >> 4)] = s1;
+      }
+    }
+  }
+}
+
+template <int QMAX, typename C>
+__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int n, int4 ox, const int4* sOpv,
+                                        const int32_t* children, const C* Sf, const C* sA) {
+  C sum = cmake<C>(0, 0);
+  const int nch = ox.w & 0xffff;
+  for (int ci = 0; ci < nch; ++ci) {
+    const int4 chv = sOpv[children[ox.z + ci]];
+    const C* srow = Sf + 12 * chv.x;
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+      if (m < n) {
+        const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+        const C av = sA[chv.z + int(ent & 2047u)];
+        sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
+      }
+    }
+  }
+  return sum;
+}
+
+// (i) adjoints of the parents of level K-1 (real rows; S rows for K = 2):
+// A_{K-1}(C') = sum over children, over j not in C', of (-1)^pos S[r0, j] A_K(C' + j).
+template <int K, int QMAX, typename C>
+__device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX>& ut, int p0, int pcnt, const int4* sOpx,
+                                            const int4* sOpv, const int32_t* children, const C* Sf, C* sA,
+                                            C* sAdj1) {
+  if (ut.g >= ut.G) return;
+  for (int p = p0 + ut.g; p < p0 + pcnt; p += ut.G) {
+    const int4 ox = sOpx[p];
+    if ((ox.w & 0xffff) == 0) continue;  // a top row
+    const int4 ov = sOpv[p];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+      const int c = ut.i0 + kNT * q;
+      if (c < ut.ncol) {
+        const C sum = parent_sum<QMAX>(ut.up[q], ut.n[q], ox, sOpv, children, Sf, sA);
+        if (K == 2)
+          sAdj1[ov.z + ut.colnum[q]] = sum;
+        else
+          sA[ov.z + c] = sum;
+      }
+    }
+  }
+}
+
+template <int K, int NU, int ND, int QMAX, typename C>
+__device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX>& ru, const RevTabs<ND, QMAX>& rd,
+                                           const int32_t* tr, const int4* sOpx, const int4* sOpv,
+                                           const int32_t* children, const C* sS, const C* sR, C* sA, C* sAdj1,
+                                           C* sPart) {
+  if constexpr (K >= 1) {
+    if constexpr (K <= NU) rev_part<K>(bins_of<K>(ru), tr[20 + 2 * K], tr[21 + 2 * K], sOpv, sS, sR, sA, sPart);
+    if constexpr (K <= ND)
+      rev_part<K>(bins_of<K>(rd), tr[20 + 2 * (7 + K)], tr[21 + 2 * (7 + K)], sOpv, sS + 144, sR, sA, sPart);
+    if constexpr (K >= 2) {
+      // parents: real rows of level K-1, or the level-1 records for K = 2
+      if constexpr (K <= NU) {
+        const int p0 = (K == 2) ? tr[17] : tr[20 + 2 * (K - 1)];
+        const int pc = (K == 2) ? tr[14] : tr[21 + 2 * (K - 1)];
+        rev_parents<K>(ups_of<K - 1>(ru), p0, pc, sOpx, sOpv, children, sS, sA, sAdj1);
+      }
+      if constexpr (K <= ND) {
+        const int p0 = (K == 2) ? tr[17] + tr[14] : tr[20 + 2 * (7 + K - 1)];
+        const int pc = (K == 2) ? tr[18] - tr[14] : tr[21 + 2 * (7 + K - 1)];
+        rev_parents<K>(ups_of<K - 1>(rd), p0, pc, sOpx, sOpv, children, sS + 144, sA, sAdj1);
+      }
+    }
+    __syncthreads();
+    rev_levels<K - 1, NU, ND, QMAX, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
+  }
+}
+
+template <typename R, int NU, int ND, int QMAX, int MC>
 __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
@@ -216,11 +504,13 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   for (int i = tid; i < 288; i += kNT)
     sS[i] = load_site<C>(i < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (i % 144));
 
-  // S-bar entries owned by this thread: e = tid and tid + NT (< 288)
-  CompAcc<R> sb[2];
+  CompAcc<R> sb[2];  // S-bar entries tid and tid + NT (< 288)
   int cur_corr = -1;
   FlavTabs<NU, QMAX> tu;
   FlavTabs<ND, QMAX> td;
+  RevTabs<NU, QMAX> ru;
+  RevTabs<ND, QMAX> rd;
+  CsrTab<QMAX, MC> cu_tab, cd_tab;
   const int4* meta_all = reinterpret_cast<const int4*>(a.meta);
 
   for (int tile = 0; tile < a.n_tiles; ++tile) {
@@ -228,10 +518,14 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nops = tr[4];
     const int meta0 = tr[5], units = tr[6], nreal = tr[17], nvirt = tr[18], ex_off = tr[19], ex_len = tr[15];
     const int32_t* cr = a.corr + corr * kCorrInts;
-    const int n_src = cr[0], src_off = cr[1];
+    const int n_src = cr[0];
     if (corr != cur_corr) {
       tu.load(cr, 0, a.tabs);
       td.load(cr, 1, a.tabs);
+      ru.load(cr, 0, a.btab, a.tabs);
+      rd.load(cr, 1, a.btab, a.tabs);
+      cu_tab.load(cr, 0, NU, a.btab, a.src_cd);
+      cd_tab.load(cr, 1, ND, a.btab, a.src_cu);
       cur_corr = corr;
     }
     C gbar;
@@ -243,17 +537,18 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     C* sAdj1 = sA + units;
     C* sPart = sAdj1 + 12 * nvirt;
     int4* sOps = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(sPart + 12 * nreal) + 15) & ~uintptr_t(15));
-    int4* sOpx = sOps + nreal;                                  // (f, k, child_begin, n_children | virt << 16)
-    int4* sOpv = sOpx + nops;                                   // (r0, in, out, 0) of all ops
+    int4* sOpx = sOps + nreal;  // (f, k, child_begin, n_children | virt << 16)
+    int4* sOpv = sOpx + nops;   // (r0, in, out, 0)
     int32_t* sEx = reinterpret_cast<int32_t*>(sOpv + nops);
     __syncthreads();  // the previous tile's LDS is no longer read
     const C* Wg = reinterpret_cast<const C*>(a.W) + w_off;
     for (int i = tid; i < B * n_src; i += kNT) sW[i] = Wg[i];
     for (int i = tid; i < nops; i += kNT) {
-      const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
-      if (i < nreal) sOps[i] = make_int4(op[2], op[3], op[4], 0);
-      sOpv[i] = make_int4(op[2], op[3], op[4], 0);
-      sOpx[i] = make_int4(op[0], op[1], op[5], op[6] | (op[7] << 16));
+      const int4* op = reinterpret_cast<const int4*>(a.ops + int64_t(op0 + i) * kOpInts);
+      const int4 lo = op[0], hi = op[1];  // (f, k, r0, in), (out, child_begin, n_children, virt)
+      if (i < nreal) sOps[i] = make_int4(lo.z, lo.w, hi.x, 0);
+      sOpv[i] = make_int4(lo.z, lo.w, hi.x, 0);
+      sOpx[i] = make_int4(lo.x, lo.y, hi.y, hi.z | (hi.w << 16));
     }
     for (int i = tid; i < ex_len; i += kNT) sEx[i] = a.extra[ex_off + i];
     for (int i = tid; i < 12 * nvirt; i += kNT) sAdj1[i] = cmake<C>(0, 0);
@@ -264,128 +559,66 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     // adjoints of the top rows from the factor-tree leaves
     {
       const int n_runs = sEx[0], n_dg = sEx[1];
-      const int32_t* runs = sEx + 2;
+      const int32_t* runs = sEx + 3;
       const int32_t* dgs = runs + 3 * n_runs;
       const int4* meta = meta_all + meta0;
-      const int ncu = cr[8 + 2 * (NU - 1)], ncd = cr[8 + 2 * (6 + ND - 1)];
-      const int32_t* csru = a.btab + cr[64];
-      const int32_t* csrd = a.btab + cr[65];
       for (int r = 0; r < n_runs; ++r) {
         const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
-        for (int c = tid; c < ncu; c += kNT) {
-          C sum = cmake<C>(0, 0);
-          const int q1 = csru[c + 1];
-          for (int q = csru[c]; q < q1; ++q) {
-            const int s = csru[q];
-            const int cds = a.src_cd[src_off + s];
-            for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + s], sR[meta[b].y + cds], sum);
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          const int c = tid + kNT * q;
+          if (c < cu_tab.ncol) {
+            C sum = cmake<C>(0, 0);
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+              if (m < cu_tab.n[q]) {
+                const int e = cu_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
+                for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + sidx], sR[meta[b].y + oc], sum);
+              }
+            }
+            sA[us + c] = cmul(gbar, sum);
           }
-          sA[us + c] = cmul(gbar, sum);
         }
       }
       for (int g = 0; g < n_dg; ++g) {
         const int ds = dgs[2 * g], mask = dgs[2 * g + 1];
-        for (int c = tid; c < ncd; c += kNT) {
-          C sum = cmake<C>(0, 0);
-          const int q1 = csrd[c + 1];
-          for (int q = csrd[c]; q < q1; ++q) {
-            const int s = csrd[q];
-            const int cus = a.src_cu[src_off + s];
-            for (int b = 0; b < B; ++b)
-              if (mask & (1 << b)) sum = cmac(sW[b * n_src + s], sR[meta[b].x + cus], sum);
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          const int c = tid + kNT * q;
+          if (c < cd_tab.ncol) {
+            C sum = cmake<C>(0, 0);
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+              if (m < cd_tab.n[q]) {
+                const int e = cd_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
+                for (int mm = mask; mm; mm &= mm - 1) {
+                  const int b = __ffs(mm) - 1;
+                  sum = cmac(sW[b * n_src + sidx], sR[meta[b].x + oc], sum);
+                }
+              }
+            }
+            sA[ds + c] = cmul(gbar, sum);
           }
-          sA[ds + c] = cmul(gbar, sum);
         }
       }
     }
     __syncthreads();
 
-    // reverse sweep of the Laplace recursion
-    const int32_t* children = sEx + 2 + 3 * sEx[0] + 2 * sEx[1];
-    for (int k = KMAX; k >= 1; --k) {
-      // (ii) per-row partials of S-bar[r0, j], 16 lanes per (row, j)
-      {
-        int lo = 0, cnt = 0;
-        const int cu_ = (k <= NU) ? tr[21 + 2 * k] : 0, cd_ = (k <= ND) ? tr[21 + 2 * (7 + k)] : 0;
-        if (cu_ > 0) lo = tr[20 + 2 * k];
-        else if (cd_ > 0) lo = tr[20 + 2 * (7 + k)];
-        cnt = cu_ + cd_;
-        const int lane16 = tid & 15;
-        for (int pg = tid >> 4; pg < cnt * 12; pg += kNT / 16) {
-          const int o = lo + pg / 12, j = pg % 12;
-          const int4 ox = sOpx[o];
-          const int4 ov = sOpv[o];
-          const int f = ox.x;
-          const C* Sf = sS + 144 * f;
-          const int32_t* jl = a.btab + cr[40 + 6 * f + k - 1];
-          const int q0 = jl[j], q1 = jl[j + 1];
-          C sum = cmake<C>(0, 0);
-          for (int q = q0 + lane16; q < q1; q += 16) {
-            const int e = jl[q];
-            const C av = sA[ov.z + (e & 4095)];
-            if (k == 1) {
-              sum.x += av.x;
-              sum.y += av.y;
-            } else {
-              const int sub = (e >> 12) & 4095;
-              const C y = (k == 2) ? Sf[12 * ov.y + sub] : sR[ov.y + sub];
-              sum = ((e >> 24) & 1) ? cmsub(av, y, sum) : cmac(av, y, sum);
-            }
-          }
-#pragma unroll
-          for (int off = 8; off > 0; off >>= 1) {
-            sum.x += __shfl_xor(sum.x, off, 16);
-            sum.y += __shfl_xor(sum.y, off, 16);
-          }
-          if (lane16 == 0) sPart[12 * o + j] = sum;
-        }
-      }
-      // (i) adjoints of the parents at level k-1 (S rows for k = 2)
-      if (k >= 2) {
-        for (int o = 0; o < nops; ++o) {
-          const int4 ox = sOpx[o];
-          const int virt = ox.w >> 16, nch = ox.w & 0xffff;
-          if (nch == 0) continue;                           // a top row
-          if (virt ? (k != 2) : (ox.y != k - 1)) continue;  // not a parent of level k
-          const int f = ox.x;
-          const int4 ov = sOpv[o];
-          const C* Sf = sS + 144 * f;
-          const int ncp = cr[8 + 2 * (6 * f + k - 2)];
-          const int32_t* sup = a.btab + cr[52 + 6 * f + k - 2];
-          const int toff1 = cr[8 + 2 * (6 * f) + 1];
-          for (int c = tid; c < ncp; c += kNT) {
-            C sum = cmake<C>(0, 0);
-            const int q0 = sup[c], q1 = sup[c + 1];
-            for (int ci = 0; ci < nch; ++ci) {
-              const int4 chv = sOpv[children[ox.z + ci]];
-              for (int q = q0; q < q1; ++q) {
-                const int e = sup[q];
-                const C av = sA[chv.z + (e & 4095)];
-                const C x = Sf[12 * chv.x + ((e >> 12) & 15)];
-                sum = ((e >> 16) & 1) ? cmsub(av, x, sum) : cmac(av, x, sum);
-              }
-            }
-            if (virt)
-              sAdj1[ov.z + a.tabs[toff1 + c]] = sum;
-            else
-              sA[ov.z + c] = sum;
-          }
-        }
-      }
-      __syncthreads();
-    }
+    const int32_t* children = sEx + 3 + 3 * sEx[0] + 2 * sEx[1];
+    const int32_t* rsum = sEx + sEx[2];
+    rev_levels<KMAX, NU, ND, QMAX, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
 
     // fixed-order accumulation of this tile's S-bar contributions
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = tid + kNT * q;
       if (e < 288) {
-        const int f = e / 144, ar = (e % 144) / 12, bc = e % 12;
+        const int row = e / 12, bc = e % 12;  // row = 12 f + r0
         C sum = cmake<C>(0, 0);
-        for (int o = 0; o < nops; ++o) {
-          const int4 ox = sOpx[o];
-          if (ox.x != f || sOpv[o].x != ar) continue;
-          const C v = (ox.w >> 16) ? sAdj1[sOpv[o].z + bc] : sPart[12 * o + bc];
+        const int l1 = rsum[row + 1];
+        for (int l = rsum[row]; l < l1; ++l) {
+          const int o = rsum[l];
+          const C v = (o >= nreal) ? sAdj1[sOpv[o].z + bc] : sPart[12 * o + bc];
           sum.x += v.x;
           sum.y += v.y;
         }
@@ -462,13 +695,20 @@ hipError_t launch_dw_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, 
   return hipErrorNotSupported;
 }
 
+bool bins_fit(const PlanHost& h) {
+  for (int k = 1; k <= 5; ++k)
+    if (h.max_bin[k] > bin_lanes(k) * bin_regs(k)) return false;
+  return h.max_bin[6] == 0;
+}
+
 template <typename R>
 hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
-  const int nu = p->h.n_u, nd = p->h.n_d, qm = p->h.qmax;
-  if (nu == 2 && nd == 1 && qm <= 1) return launch_k(ds_kernel<R, 2, 1, 1>, nb, lds, st, a);
-  if (nu == 1 && nd == 2 && qm <= 1) return launch_k(ds_kernel<R, 1, 2, 1>, nb, lds, st, a);
-  if (nu == 3 && nd == 3 && qm <= 1) return launch_k(ds_kernel<R, 3, 3, 1>, nb, lds, st, a);
-  if (nu == 5 && nd == 4 && qm <= 2) return launch_k(ds_kernel<R, 5, 4, 2>, nb, lds, st, a);
+  const int nu = p->h.n_u, nd = p->h.n_d, qm = p->h.qmax, mc = p->h.max_csr;
+  if (!bins_fit(p->h)) return hipErrorNotSupported;
+  if (nu == 2 && nd == 1 && qm <= 1 && mc <= 2) return launch_k(ds_kernel<R, 2, 1, 1, 2>, nb, lds, st, a);
+  if (nu == 1 && nd == 2 && qm <= 1 && mc <= 2) return launch_k(ds_kernel<R, 1, 2, 1, 2>, nb, lds, st, a);
+  if (nu == 3 && nd == 3 && qm <= 1 && mc <= 6) return launch_k(ds_kernel<R, 3, 3, 1, 6>, nb, lds, st, a);
+  if (nu == 5 && nd == 4 && qm <= 2 && mc <= 10) return launch_k(ds_kernel<R, 5, 4, 2, 10>, nb, lds, st, a);
   return hipErrorNotSupported;
 }
 

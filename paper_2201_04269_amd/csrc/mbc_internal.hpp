@@ -60,6 +60,12 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   [64] csr_u_off [65] csr_d_off  offsets in btab of: ncol_top + 1 relative
 //                     pointers, then the source keys s with that top column
 //   [66] w_base       plan-ordered W offset of the correlator's first entry
+//   [67 + 6*f + k-1]  offset in btab of the "up" table of level k (k < n_f):
+//                     per column C', 12 uint16 (packed two per int32): the
+//                     index of C' + {j} in level k+1 | (position of j) << 12,
+//                     0xffff if C' + {j} is not a needed column
+//   [80 + f]          longest source-key list of a top column of flavour f
+//   [82 + 6*f + k-1]  longest j-list of level k
 // Column table of level k >= 2: ncol*k uint16 entries (sub << 4) | col, the k
 //   terms of the expansion along the first row; col = C_j, sub = index of
 //   C \ C_j in level k-1 (for k = 2: the remaining column number itself).
@@ -71,8 +77,12 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   [16] snk_begin (index of the tile's first sink key in plan order)
 //   [17] virt_begin [18] n_virt  (backward tiles) level-1 parent records
 //   [19] extra_off   (backward tiles) offset in b_extra of: n_runs, n_dgroups,
-//        then runs (u_slot, b_begin, b_end), d-groups (d_slot, b mask), then
-//        the children lists of the ops
+//        rsum_off, then runs (u_slot, b_begin, b_end), d-groups (d_slot, b
+//        mask), the children lists of the ops, and at rsum_off the S-bar row
+//        lists: 25 relative pointers over the 24 (flavour, S row) pairs, then
+//        the records (rows and level-1 parents) whose adjoint lands in that row
+//   [15] extra_len   (backward tiles) ints of that extra block
+//   [14] n_virt_u    (backward tiles) level-1 records of flavour u (listed first)
 //   [20 + 2*(7f + k)], [21 + 2*(7f + k)]: first op (relative) and number of
 //   ops of flavour f at level k; ops are ordered by (level, flavour).
 // Row op (kOpInts ints): flav, level, r0, in, out, tab_off, ncol, item_begin
@@ -83,7 +93,7 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   in the tile's level-1 adjoint rows).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
 // ---------------------------------------------------------------------------
-constexpr int kCorrInts = 72;
+constexpr int kCorrInts = 96;
 constexpr int kTileInts = 48;
 constexpr int kOpInts = 8;
 constexpr int kMetaInts = 4;
@@ -105,6 +115,8 @@ struct PlanHost {
   int64_t b_lds_ds = 0, b_lds_dw = 0;  // dS kernel, dW kernel
   std::vector<int32_t> b_tiles, b_ops, b_meta, b_extra, btab;
   int maxc_top = 0;      // max top-level columns over correlators and flavours
+  int max_csr = 0;       // longest source-key list of a top column
+  int max_bin[7] = {0, 0, 0, 0, 0, 0, 0};  // longest j-list per level
   std::vector<uint16_t> tabs;
   std::vector<int64_t> perm;      // plan-ordered W slot -> index-set entry
   std::vector<double> w_exact;    // plan-ordered exact W (re, im)

@@ -225,7 +225,7 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
     for (auto& r : order) {
       if (r.k != cur_level) {
         ++phase;
-        if (phase >= kMaxPhases) throw std::runtime_error("too many phases");
+        if (phase >= 5) throw std::runtime_error("too many phases (at most five levels of rows per tile)");
         tr[8 + phase] = n_ops;
         cur_level = r.k;
         item = 0;
@@ -280,6 +280,7 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
     if (bwd) {
       tr[17] = n_ops;
       tr[18] = int32_t(virt.size());
+      for (auto& v : virt) tr[14] += (v.first == 0);  // level-1 records of the u flavour come first
       for (size_t v = 0; v < virt.size(); ++v) {
         const auto& ch = children[n_ops + v];
         const int32_t op[kOpInts] = {virt[v].first, 1, virt[v].second, 0, int32_t(12 * v),
@@ -311,11 +312,26 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
       }
       for (int b = 0; b < B; ++b) dmask[slot.at({1, X.nf[1], X.snk[sk[b]].second})] |= (1 << b);
       for (auto& kv : dmask) dgs.insert(dgs.end(), {kv.first, kv.second});
+      // rows of S-bar touched by the tile: for each (flavour, S row r0), the
+      // records (real rows with that first row, level-1 parents of that row)
+      std::vector<std::vector<int32_t>> rsum(24);
+      for (auto& r : order) rsum[12 * r.f + r.t.v[0]].push_back(op_index.at(r));
+      for (size_t v = 0; v < virt.size(); ++v) rsum[12 * virt[v].first + virt[v].second].push_back(n_ops + int(v));
+      int64_t nchild = 0;
+      for (auto& ch : children) nchild += int64_t(ch.size());
       o.extra->push_back(int32_t(runs.size() / 3));
       o.extra->push_back(int32_t(dgs.size() / 2));
+      o.extra->push_back(int32_t(3 + runs.size() + dgs.size() + nchild));  // offset of the S-bar row lists
       o.extra->insert(o.extra->end(), runs.begin(), runs.end());
       o.extra->insert(o.extra->end(), dgs.begin(), dgs.end());
       for (auto& ch : children) o.extra->insert(o.extra->end(), ch.begin(), ch.end());
+      int32_t acc = 25;
+      for (int q = 0; q < 24; ++q) {
+        o.extra->push_back(acc);
+        acc += int32_t(rsum[q].size());
+      }
+      o.extra->push_back(acc);
+      for (auto& v : rsum) o.extra->insert(o.extra->end(), v.begin(), v.end());
     }
     int64_t lds = m(B, X.n_src, units, n_ops, bwd ? int(virt.size()) : 0, child_total);
     if (bwd) {
@@ -362,6 +378,7 @@ void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) 
           jl[C.v[pos]].push_back(e);
         }
       }
+      for (int j = 0; j < 12; ++j) cr[82 + 6 * f + k - 1] = std::max<int32_t>(cr[82 + 6 * f + k - 1], int32_t(jl[j].size()));
       const size_t base = btab.size();
       btab.resize(base + 13);
       int32_t acc = 13;
@@ -394,6 +411,42 @@ void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) 
       }
     }
   }
+  // "up" tables of the parent levels: for each column C' of level k < n_f and
+  // each column number j, the index of C' + {j} in level k + 1 (0xffff if it
+  // is not a needed column), packed two per int32
+  for (int f = 0; f < 2; ++f)
+    for (int k = 1; k < X.nf[f]; ++k) {
+      cr[67 + 6 * f + k - 1] = int32_t(btab.size());
+      const auto& cols = X.lev[f].cols[k];
+      for (const Key& Cp : cols) {
+        uint32_t pk[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < 12; ++j) {
+          int idx = 0xffff;
+          bool in = false;
+          for (int q = 0; q < Cp.n; ++q) in |= (Cp.v[q] == j);
+          if (!in) {
+            Key up;
+            up.n = uint8_t(k + 1);
+            int w = 0;
+            bool put = false;
+            for (int q = 0; q < Cp.n; ++q) {
+              if (!put && j < Cp.v[q]) { up.v[w++] = uint8_t(j); put = true; }
+              up.v[w++] = Cp.v[q];
+            }
+            if (!put) up.v[w++] = uint8_t(j);
+            auto it = X.lev[f].index[k + 1].find(up);
+            if (it != X.lev[f].index[k + 1].end()) {
+              int pos = 0;
+              for (int q = 0; q < Cp.n; ++q) pos += Cp.v[q] < j;
+              if (it->second >= 4096) throw std::runtime_error("column list too long");
+              idx = it->second | (pos << 12);
+            }
+          }
+          pk[j / 2] |= (uint32_t(idx) & 0xffffu) << (16 * (j % 2));
+        }
+        for (uint32_t w : pk) btab.push_back(int32_t(w));
+      }
+    }
   // source keys grouped by their top u column and by their top d column
   for (int f = 0; f < 2; ++f) {
     const int ntop = X.ncol(f, X.nf[f]);
@@ -403,6 +456,7 @@ void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) 
       lists[X.lev[f].index[X.nf[f]].at(col)].push_back(s);
     }
     cr[64 + f] = int32_t(btab.size());
+    for (auto& v : lists) cr[80 + f] = std::max<int32_t>(cr[80 + f], int32_t(v.size()));
     const size_t b3 = btab.size();
     btab.resize(b3 + ntop + 1);
     int32_t a3 = ntop + 1;
@@ -564,6 +618,12 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     cr[7] = P.b_n_tiles;
   }
   if (w_pos != P.nnz) throw std::logic_error("plan does not cover the index set");
+  for (int c = 0; c < s.n_corr; ++c) {
+    const int32_t* cr = &P.corr[size_t(c) * kCorrInts];
+    P.max_csr = std::max({P.max_csr, int(cr[80]), int(cr[81])});
+    for (int f = 0; f < 2; ++f)
+      for (int k = 1; k <= 6; ++k) P.max_bin[k] = std::max(P.max_bin[k], int(cr[82 + 6 * f + k - 1]));
+  }
   // dW kernel of the backward tiling: S (double buffer), rows, staged ops,
   // and compensated accumulators of the tile's weights (16 B each)
   for (int t = 0; t < P.b_n_tiles; ++t) {
