@@ -1,0 +1,200 @@
+"""GPU parity at the workloads' full lattice sizes, on sampled sites.
+
+The propagators are the workloads' own seeded inputs, generated at full size;
+every site outside a seeded sample is then set to zero, so the full-size
+launch (same T, V, chunking and tile grid as the benchmark) sums exactly the
+sampled sites, whose contributions the FP64 oracle computes one by one.
+Properties that hold at any size (D_II under R2 equals 2 D_I) are checked
+on the unmodified inputs.
+"""
+import numpy as np
+import pytest
+
+from oracle import correlator as CO
+from oracle import operators as O
+from paper_2201_04269_amd import synth
+from tests.parity import kappa, tol_f32c, tol_f64
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2201_04269_amd import api
+    return api
+
+
+def keep_sites(Su, Sd, picks):
+    """Zero every site except picks [(t, v), ...]; returns the zeroed copies."""
+    mask = np.zeros(Su.shape[:2], dtype=bool)
+    for t, v in picks:
+        mask[t, v] = True
+    Su = Su.copy()
+    Sd = Sd.copy()
+    Su[~mask] = 0
+    Sd[~mask] = 0
+    return Su, Sd
+
+
+def oracle_on_picks(ods, Su, Sd, picks, W=None):
+    """Oracle C[c, t] and A[c, t] from the picked sites only."""
+    rs = O.build_index_set(ods)
+    if W is not None:
+        rs.weights = lambda: W
+    T = Su.shape[0]
+    C = np.zeros((rs.n_corr, T), dtype=np.complex128)
+    A = np.zeros((rs.n_corr, T))
+    for t, v in picks:
+        su = Su[t, v][None, None]
+        sd = Sd[t, v][None, None]
+        C[:, t] += CO.correlator(su, sd, rs)[:, 0]
+        A[:, t] += CO.sum_abs_terms(su, sd, rs)[:, 0]
+    return C, A, rs
+
+
+def picks_for(T, V, n_t, per_t, seed):
+    rng = np.random.default_rng(seed)
+    ts = np.unique(np.concatenate([[0, T - 1], rng.choice(T, size=n_t, replace=False)]))
+    out = []
+    for t in ts:
+        vs = rng.choice(V, size=per_t, replace=False)
+        out += [(int(t), int(v)) for v in vs]
+    out.append((int(ts[-1]), V - 1))  # the last site of the lattice (ragged tail)
+    return sorted(set(out))
+
+
+def run_forward(ods, Su, Sd, prec, W=None, c64=False):
+    api = _api()
+    plan = api.Plan(api.IndexSet(ods), prec)
+    dt = torch.complex64 if c64 else torch.complex128
+    su = torch.from_numpy(Su).to(dt).cuda()
+    sd = torch.from_numpy(Sd).to(dt).cuda()
+    w = None if W is None else torch.from_numpy(W).cuda()
+    C = api.contract(plan, su, sd, w)
+    torch.cuda.synchronize()
+    return C.cpu().numpy()
+
+
+def _check(C, ref, A, nu, nd, prec, label):
+    err = np.abs(C - ref)
+    tol = tol_f64(ref, A, nu, nd) if prec == "f64" else tol_f32c(A, nu, nd)
+    mask = A > 0
+    print(label, prec, "max err/A", float(np.max(err[mask] / A[mask])) if mask.any() else 0.0, flush=True)
+    assert np.all(err <= tol + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_dinucleon_8x8x8x16_su3_spin(prec):
+    """D_I on 8^3 x 16, SU(3) x spin propagators (seed 1)."""
+    ods = [dict(op="DI")]
+    T, V = 16, 8 ** 3
+    Su, Sd = synth.su3_spin(T, V, seed=1)
+    picks = picks_for(T, V, 3, 2, seed=101)
+    Su, Sd = keep_sites(Su, Sd, picks)
+    C = run_forward(ods, Su, Sd, prec)
+    ref, A, rs = oracle_on_picks(ods, Su, Sd, picks)
+    _check(C, ref, A, 3, 3, prec, "DI 8^3x16")
+    empty_t = [t for t in range(T) if t not in {p[0] for p in picks}]
+    assert np.all(C[:, empty_t] == 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_dinucleon_II_16x16x16x32(prec):
+    """D_II (exact: empty; R2) and D_I on 16^3 x 32, i.i.d. propagators (seed 2)."""
+    ods = [dict(op="DII"), dict(op="DII", sign_mode="r2"), dict(op="DI")]
+    T, V = 32, 16 ** 3
+    Su0, Sd0 = synth.iid(T, V, seed=2)
+    picks = picks_for(T, V, 2, 2, seed=102)
+    Su, Sd = keep_sites(Su0, Sd0, picks)
+    C = run_forward(ods, Su, Sd, prec)
+    ref, A, rs = oracle_on_picks(ods, Su, Sd, picks)
+    assert np.all(C[0] == 0)  # D_II with exact signs vanishes identically
+    _check(C[1:], ref[1:], A[1:], 3, 3, prec, "DII/DI 16^3x32")
+    # any size: D_II(R2) = sqrt(2) D_I as operators, so C_DII(R2) = 2 C_DI
+    if prec == "f64":
+        Cf = run_forward(ods[1:], Su0, Sd0, "f64")
+        assert np.allclose(Cf[0], 2 * Cf[1], rtol=1e-11, atol=0)
+
+
+def test_dinucleon_ragged_lattice_and_complex64_input():
+    """A lattice whose timeslices do not divide into whole chunks."""
+    ods = [dict(op="DI")]
+    T, V = 2, 1000
+    Su, Sd = synth.iid(T, V, seed=12)
+    picks = [(0, 0), (0, 511), (1, 998), (1, 999)]
+    Su, Sd = keep_sites(Su, Sd, picks)
+    for prec in ("f64", "f32c"):
+        C = run_forward(ods, Su, Sd, prec)
+        ref, A, _ = oracle_on_picks(ods, Su, Sd, picks)
+        _check(C, ref, A, 3, 3, prec, "ragged")
+    S32u, S32d = Su.astype(np.complex64), Sd.astype(np.complex64)
+    C = run_forward(ods, S32u, S32d, "f32c", c64=True)
+    ref, A, _ = oracle_on_picks(ods, S32u.astype(np.complex128), S32d.astype(np.complex128), picks)
+    _check(C, ref, A, 3, 3, "f32c", "ragged c64")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_helium3_full_spatial_volume(prec):
+    """3He_I^j and 3He_II^j (R2), j = 0..3, 8 correlators in one launch, on the
+    full 32^3 spatial volume (i.i.d., seed 4); 4 of the 64 timeslices."""
+    ods = [dict(op="HE3_I", snk_spin=j, src_spin=j) for j in range(4)] + \
+          [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2") for j in range(4)]
+    T, V = 4, 32 ** 3
+    Su, Sd = synth.iid(T, V, seed=4)
+    picks = [(0, 5), (1, 17000), (3, V - 1)]
+    Su, Sd = keep_sites(Su, Sd, picks)
+    C = run_forward(ods, Su, Sd, prec, c64=(prec == "f32c"))
+    S_u = Su.astype(np.complex64).astype(np.complex128) if prec == "f32c" else Su
+    S_d = Sd.astype(np.complex64).astype(np.complex128) if prec == "f32c" else Sd
+    ref, A, _ = oracle_on_picks(ods, S_u, S_d, picks)
+    _check(C, ref, A, 5, 4, prec, "He3 32^3")
+
+
+def test_backward_mixed_dinucleon_16x16x16x32():
+    """Gradients on the full 16^3 x 32 lattice (i.i.d., seed 3), W(c) = W_DI + 0.5 W_DII(R2)."""
+    api = _api()
+    T, V = 32, 16 ** 3
+    Su, Sd = synth.iid(T, V, seed=3)
+    picks = [(0, 0), (13, 2047), (31, V - 1)]
+    Su, Sd = keep_sites(Su, Sd, picks)
+    both = api.IndexSet([dict(op="DI"), dict(op="DII", sign_mode="r2")])
+    w = both.weights()
+    n = both.nnz // 2
+    W = w[:n] + 0.5 * w[n:]
+    rng = np.random.default_rng(3)
+    gC = rng.standard_normal((1, T)) + 1j * rng.standard_normal((1, T))
+    rs = O.build_index_set([dict(op="DI")])
+    rs.weights = lambda: W
+    for prec in ("f64", "f32c"):
+        plan = api.Plan(api.IndexSet([dict(op="DI")]), prec)
+        su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
+        gW, gSu, gSd = api.contract_backward(plan, su, sd, torch.from_numpy(W).cuda(), torch.from_numpy(gC).cuda())
+        gW, gSu, gSd = gW.cpu().numpy(), gSu.cpu().numpy(), gSd.cpu().numpy()
+        refW = np.zeros(rs.nnz, dtype=np.complex128)
+        sclW = np.zeros(rs.nnz)
+        u = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+        k = kappa(3, 3)
+        for t, v in picks:
+            su1, sd1 = Su[t, v][None, None], Sd[t, v][None, None]
+            g1 = gC[:, t:t + 1]
+            ref = CO.gradients(su1, sd1, rs, g1)
+            scl = CO.gradient_abs_scales(su1, sd1, rs, g1)
+            refW += ref["W"]
+            sclW += scl["W"]
+            for key, got in (("S_u", gSu[t, v]), ("S_d", gSd[t, v])):
+                err = np.abs(got - ref[key][0, 0])
+                tol = k * u * scl[key][0, 0]
+                if prec == "f64":
+                    tol = np.maximum(tol, 1e-12 * np.abs(ref[key][0, 0]))
+                assert np.all(err <= tol + 1e-300), (prec, key, t, v)
+        # C has degree >= 2 in each flavour, so its gradient vanishes where S = 0
+        zero = np.ones((T, V), dtype=bool)
+        for t, v in picks:
+            zero[t, v] = False
+        assert np.all(gSu[zero] == 0) and np.all(gSd[zero] == 0)
+        errW = np.abs(gW - refW)
+        tolW = k * u * sclW
+        if prec == "f64":
+            tolW = np.maximum(tolW, 1e-12 * np.abs(refW))
+        print("backward 16^3x32", prec, "max dW err / sum|terms|", float(np.max(errW / np.maximum(sclW, 1e-300))))
+        assert np.all(errW <= tolW + 1e-300)
