@@ -15,6 +15,31 @@ namespace dev {
 
 constexpr int kNT = 256;  // threads per workgroup
 
+// Next 16-byte boundary of an LDS pointer, computed as an offset from the
+// dynamic LDS base: the result stays an LDS pointer for the compiler, which a
+// round trip through an integer address would lose (turning every access
+// through it into a flat access).  The base is 16-byte aligned.
+template <typename T>
+__device__ __forceinline__ T* lds_align16(unsigned char* base, const void* p) {
+  const unsigned off = unsigned(reinterpret_cast<const unsigned char*>(p) - base);
+  return reinterpret_cast<T*>(base + ((off + 15u) & ~15u));
+}
+
+// Copies n elements from global memory into LDS with all threads of the
+// workgroup, four loads in flight per thread before the stores.
+template <typename T>
+__device__ __forceinline__ void stage_lds(T* dst, const T* __restrict__ src, int n) {
+  int i = threadIdx.x;
+  for (; i + 3 * kNT < n; i += 4 * kNT) {
+    const T v0 = src[i], v1 = src[i + kNT], v2 = src[i + 2 * kNT], v3 = src[i + 3 * kNT];
+    dst[i] = v0;
+    dst[i + kNT] = v1;
+    dst[i + 2 * kNT] = v2;
+    dst[i + 3 * kNT] = v3;
+  }
+  for (; i < n; i += kNT) dst[i] = src[i];
+}
+
 template <typename R>
 struct cx;
 template <>

@@ -93,15 +93,15 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   C* sS0 = reinterpret_cast<C*>(smem);
   C* sW = sS0 + 576;
   C* sR = sW + B * n_src;
-  int4* sOps = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(sR + row_units) + 15) & ~uintptr_t(15));
+  int4* sOps = lds_align16<int4>(smem, sR + row_units);
+  int4* meta = sOps + nops;  // (u slot, d slot, run end, key) of each sink key
 
   for (int i = tid; i < nops; i += kNT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
-  const C* Wg = reinterpret_cast<const C*>(a.W) + w_off;
-  for (int i = tid; i < B * n_src; i += kNT) sW[i] = Wg[i];
-  const int4* meta = reinterpret_cast<const int4*>(a.meta) + meta0;
+  stage_lds(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+  if (tid < B) meta[tid] = reinterpret_cast<const int4*>(a.meta)[meta0 + tid];
 
   FlavTabs<NU, QMAX> tu;
   FlavTabs<ND, QMAX> td;

@@ -114,15 +114,16 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
 
   C* sS0 = reinterpret_cast<C*>(smem);
   C* sR = sS0 + 576;
-  int4* sOps = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(sR + row_units) + 15) & ~uintptr_t(15));
+  int4* sOps = lds_align16<int4>(smem, sR + row_units);
   R* sAcc = reinterpret_cast<R*>(sOps + nreal);  // [B * n_src][4]: hx, lx, hy, ly
+  int4* meta = reinterpret_cast<int4*>(sAcc + 4 * B * n_src);  // (u slot, d slot, run end, key) per sink key
 
   for (int i = tid; i < nreal; i += kNT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
   for (int i = tid; i < 4 * B * n_src; i += kNT) sAcc[i] = R(0);
-  const int4* meta = reinterpret_cast<const int4*>(a.meta) + meta0;
+  if (tid < B) meta[tid] = reinterpret_cast<const int4*>(a.meta)[meta0 + tid];
   FlavTabs<NU, QMAX> tu;
   FlavTabs<ND, QMAX> td;
   tu.load(cr, 0, a.tabs);
@@ -536,13 +537,17 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     C* sA = sR + units;
     C* sAdj1 = sA + units;
     C* sPart = sAdj1 + 12 * nvirt;
-    int4* sOps = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(sPart + 12 * nreal) + 15) & ~uintptr_t(15));
+    int4* sOps = lds_align16<int4>(smem, sPart + 12 * nreal);
     int4* sOpx = sOps + nreal;  // (f, k, child_begin, n_children | virt << 16)
     int4* sOpv = sOpx + nops;   // (r0, in, out, 0)
     int32_t* sEx = reinterpret_cast<int32_t*>(sOpv + nops);
+    int2* sMeta = reinterpret_cast<int2*>(sEx + ((ex_len + 1) & ~1));  // (u slot, d slot) of each sink key
     __syncthreads();  // the previous tile's LDS is no longer read
-    const C* Wg = reinterpret_cast<const C*>(a.W) + w_off;
-    for (int i = tid; i < B * n_src; i += kNT) sW[i] = Wg[i];
+    stage_lds(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+    if (tid < B) {
+      const int4 mb = meta_all[meta0 + tid];
+      sMeta[tid] = make_int2(mb.x, mb.y);
+    }
     for (int i = tid; i < nops; i += kNT) {
       const int4* op = reinterpret_cast<const int4*>(a.ops + int64_t(op0 + i) * kOpInts);
       const int4 lo = op[0], hi = op[1];  // (f, k, r0, in), (out, child_begin, n_children, virt)
@@ -561,7 +566,6 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
       const int n_runs = sEx[0], n_dg = sEx[1];
       const int32_t* runs = sEx + 3;
       const int32_t* dgs = runs + 3 * n_runs;
-      const int4* meta = meta_all + meta0;
       for (int r = 0; r < n_runs; ++r) {
         const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
 #pragma unroll
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
             for (int m = 0; m < MC; ++m) {
               if (m < cu_tab.n[q]) {
                 const int e = cu_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
-                for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + sidx], sR[meta[b].y + oc], sum);
+                for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + sidx], sR[sMeta[b].y + oc], sum);
               }
             }
             sA[us + c] = cmul(gbar, sum);
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
                 const int e = cd_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
                 for (int mm = mask; mm; mm &= mm - 1) {
                   const int b = __ffs(mm) - 1;
-                  sum = cmac(sW[b * n_src + sidx], sR[meta[b].x + oc], sum);
+                  sum = cmac(sW[b * n_src + sidx], sR[sMeta[b].x + oc], sum);
                 }
               }
             }

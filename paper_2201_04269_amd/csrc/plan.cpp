@@ -137,7 +137,7 @@ struct LdsModel {
   int64_t operator()(int B, int n_src, int64_t row_units, int n_ops, int n_virt, int64_t n_child) const {
     if (!backward) {
       int64_t bytes = (576 + int64_t(B) * n_src + row_units) * csz;
-      return ((bytes + 15) & ~int64_t(15)) + int64_t(n_ops) * 16;
+      return ((bytes + 15) & ~int64_t(15)) + int64_t(n_ops) * 16 + int64_t(B) * 16;
     }
     // dS kernel: S, W, rows, adjoint rows, level-1 adjoints, per-op j-partials,
     // S-bar accumulators (16 B each), staged op records and child lists
@@ -340,11 +340,12 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
       tr[15] = int32_t(ex_len);
       // dS kernel layout: S, W, rows, adjoint rows, level-1 adjoints, per-row
       // S-bar partials (complex, rounded up to 16 B), then int4 op records
-      // (real ops; all ops twice) and the extra ints
+      // (real ops; all ops twice), the extra ints (rounded up to 8 B) and the
+      // (u slot, d slot) pairs of the sink keys
       int64_t cunits = 288 + int64_t(B) * X.n_src + 2 * int64_t(units) + 12 * int64_t(nv) + 12 * int64_t(n_ops);
       int64_t bytes = cunits * m.csz;
       bytes = (bytes + 15) & ~int64_t(15);
-      lds = bytes + int64_t(n_ops + 2 * (n_ops + nv)) * 16 + ex_len * 4;
+      lds = bytes + int64_t(n_ops + 2 * (n_ops + nv)) * 16 + ((ex_len + 1) & ~int64_t(1)) * 4 + int64_t(B) * 8;
     }
     if (lds > 160 * 1024) throw std::runtime_error("a tile exceeds the 160 KiB local memory of a CU");
     max_lds = std::max(max_lds, lds);
@@ -625,13 +626,14 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
       for (int k = 1; k <= 6; ++k) P.max_bin[k] = std::max(P.max_bin[k], int(cr[82 + 6 * f + k - 1]));
   }
   // dW kernel of the backward tiling: S (double buffer), rows, staged ops,
-  // and compensated accumulators of the tile's weights (16 B each)
+  // compensated accumulators of the tile's weights (4 reals each) and the
+  // sink keys' slot records
   for (int t = 0; t < P.b_n_tiles; ++t) {
     const int32_t* tr = &P.b_tiles[size_t(t) * kTileInts];
     const int32_t* cr = &P.corr[size_t(tr[0]) * kCorrInts];
     int64_t bytes = (576 + int64_t(tr[6])) * csz;
     bytes = (bytes + 15) & ~int64_t(15);
-    const int64_t lds = bytes + int64_t(tr[17]) * 16 + int64_t(tr[1]) * cr[0] * 2 * csz;
+    const int64_t lds = bytes + int64_t(tr[17]) * 16 + int64_t(tr[1]) * cr[0] * 2 * csz + int64_t(tr[1]) * 16;
     P.b_lds_dw = std::max(P.b_lds_dw, lds);
   }
   P.alg_flops_per_site = alg;
