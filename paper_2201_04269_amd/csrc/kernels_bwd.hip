@@ -216,13 +216,13 @@ __host__ __device__ constexpr int bin_lanes(int k) { return k <= 2 ? 1 : 16; }
 
 template <int K>
 struct BinTab {
-  int n = 0;
   int e[bin_regs(K)];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab) {
     const int t = threadIdx.x;
-    n = 0;
+    // unused slots read column ncol of the row: its zero element
+    const int pad = cr[8 + 2 * (6 * f + K - 1)];
 #pragma unroll
-    for (int m = 0; m < bin_regs(K); ++m) e[m] = 0;
+    for (int m = 0; m < bin_regs(K); ++m) e[m] = pad;
     const int32_t* jl = btab + cr[40 + 6 * f + K - 1];
     int j, l;
     if constexpr (K <= 2) {
@@ -238,10 +238,7 @@ struct BinTab {
 #pragma unroll
     for (int m = 0; m < bin_regs(K); ++m) {
       const int q = q0 + l + bin_lanes(K) * m;
-      if (q < q1) {
-        e[m] = jl[q];
-        n = m + 1;
-      }
+      if (q < q1) e[m] = jl[q];
     }
   }
 };
@@ -250,16 +247,20 @@ struct BinTab {
 // forward row items: with ncol <= NT, G = NT / ncol parents side by side
 // (thread t: column t % ncol of parent group t / ncol); else columns t, t + NT.
 // Entries: index of C' + {j} one level up | parity of the position of j << 11
-// | j << 12, compacted (count n), two per int32.
+// | j << 12, compacted and padded to 12 - K entries (the most a K-column can
+// have) with the child row's zero element (index ncol one level up), two per
+// int32.
+__host__ __device__ constexpr int up_len(int k) { return 12 - k; }
+
 template <int K, int QMAX>
 struct UpTab {
   int ncol = 0, G = 1, g = 0, i0 = 0;
-  int n[QMAX];
   unsigned up[QMAX][6];
   int colnum[QMAX];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab,
                                        const uint16_t* __restrict__ tabs) {
     ncol = cr[8 + 2 * (6 * f + K - 1)];
+    const unsigned pad = unsigned(cr[8 + 2 * (6 * f + K)]) & 2047u;  // ncol one level up
     const int32_t* ut = btab + cr[67 + 6 * f + K - 1];
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
     const int t = threadIdx.x;
@@ -291,7 +292,9 @@ struct UpTab {
           ++cnt;
         }
       }
-      n[q] = cnt;
+#pragma unroll
+      for (int m = 0; m < up_len(K); ++m)
+        if (m >= cnt) up[q][m >> 1] |= pad << (16 * (m & 1));
       colnum[q] = (K == 1 && ok) ? int(tabs[toff + c]) : 0;
     }
   }
@@ -299,34 +302,38 @@ struct UpTab {
 
 // Leaf adjoints: thread owns top columns c = t, t + NT and keeps the source
 // keys of each (s | other-flavour column << 11).
+// Unused slots pair source key 0 with the zero element of the other
+// flavour's top row; nw[q] is the largest list length in the wave.
 template <int QMAX, int MC>
 struct CsrTab {
   int ncol = 0;
-  int n[QMAX];
+  int nw[QMAX];
   int e[QMAX][MC];
-  __device__ __forceinline__ void load(const int32_t* cr, int f, int nf, const int32_t* __restrict__ btab,
-                                       const int32_t* __restrict__ other_col) {
+  __device__ __forceinline__ void load(const int32_t* cr, int f, int nf, int nf_other,
+                                       const int32_t* __restrict__ btab, const int32_t* __restrict__ other_col) {
     ncol = cr[8 + 2 * (6 * f + nf - 1)];
+    const int pad = cr[8 + 2 * (6 * (1 - f) + nf_other - 1)] << 11;
     const int32_t* lists = btab + cr[64 + f];
     const int src_off = cr[1];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int c = threadIdx.x + kNT * q;
-      n[q] = 0;
-      int q0 = 0;
+      int n = 0, q0 = 0;
       if (c < ncol) {
         q0 = lists[c];
-        n[q] = lists[c + 1] - q0;
+        n = lists[c + 1] - q0;
       }
 #pragma unroll
       for (int m = 0; m < MC; ++m) {
-        int v = 0;
-        if (m < n[q]) {
+        int v = pad;
+        if (m < n) {
           const int sidx = lists[q0 + m];
           v = sidx | (other_col[src_off + sidx] << 11);
         }
         e[q][m] = v;
       }
+      for (int off = 32; off > 0; off >>= 1) n = max(n, __shfl_xor(n, off));
+      nw[q] = __builtin_amdgcn_readfirstlane(n);
     }
   }
 };
@@ -376,17 +383,15 @@ __device__ __forceinline__ C bin_sum(const BinTab<K>& bt, int4 ov, const C* Sf, 
   C sum = cmake<C>(0, 0);
 #pragma unroll
   for (int m = 0; m < bin_regs(K); ++m) {
-    if (m < bt.n) {
-      const int e = bt.e[m];
-      const C av = sA[ov.z + (e & 4095)];
-      if constexpr (K == 1) {
-        sum.x += av.x;
-        sum.y += av.y;
-      } else {
-        const int sub = (e >> 12) & 4095;
-        const C y = (K == 2) ? Sf[12 * ov.y + sub] : sR[ov.y + sub];
-        sum = cmac(cneg_if(av, (e >> 24) & 1), y, sum);
-      }
+    const int e = bt.e[m];
+    const C av = sA[ov.z + (e & 4095)];
+    if constexpr (K == 1) {
+      sum.x += av.x;
+      sum.y += av.y;
+    } else {
+      const int sub = (e >> 12) & 4095;
+      const C y = (K == 2) ? Sf[12 * ov.y + sub] : sR[ov.y + sub];
+      sum = cmac(cneg_if(av, (e >> 24) & 1), y, sum);
     }
   }
   return sum;
@@ -420,8 +425,8 @@ __device__ __forceinline__ void rev_part(const BinTab<K>& bt, int o0, int cnt, c
   }
 }
 
-template <int QMAX, typename C>
-__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int n, int4 ox, const int4* sOpv,
+template <int KP, typename C>
+__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int4 ox, const int4* sOpv,
                                         const int32_t* children, const C* Sf, const C* sA) {
   C sum = cmake<C>(0, 0);
   const int nch = ox.w & 0xffff;
@@ -429,12 +434,10 @@ __device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int n, int4 ox,
     const int4 chv = sOpv[children[ox.z + ci]];
     const C* srow = Sf + 12 * chv.x;
 #pragma unroll
-    for (int m = 0; m < 12; ++m) {
-      if (m < n) {
-        const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
-        const C av = sA[chv.z + int(ent & 2047u)];
-        sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
-      }
+    for (int m = 0; m < up_len(KP); ++m) {
+      const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+      const C av = sA[chv.z + int(ent & 2047u)];
+      sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
     }
   }
   return sum;
@@ -455,7 +458,7 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX>& ut, int p0
     for (int q = 0; q < QMAX; ++q) {
       const int c = ut.i0 + kNT * q;
       if (c < ut.ncol) {
-        const C sum = parent_sum<QMAX>(ut.up[q], ut.n[q], ox, sOpv, children, Sf, sA);
+        const C sum = parent_sum<K - 1>(ut.up[q], ox, sOpv, children, Sf, sA);
         if (K == 2)
           sAdj1[ov.z + ut.colnum[q]] = sum;
         else
@@ -525,8 +528,8 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
       td.load(cr, 1, a.tabs);
       ru.load(cr, 0, a.btab, a.tabs);
       rd.load(cr, 1, a.btab, a.tabs);
-      cu_tab.load(cr, 0, NU, a.btab, a.src_cd);
-      cd_tab.load(cr, 1, ND, a.btab, a.src_cu);
+      cu_tab.load(cr, 0, NU, ND, a.btab, a.src_cd);
+      cd_tab.load(cr, 1, ND, NU, a.btab, a.src_cu);
       cur_corr = corr;
     }
     C gbar;
@@ -551,7 +554,12 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     for (int i = tid; i < nops; i += kNT) {
       const int4* op = reinterpret_cast<const int4*>(a.ops + int64_t(op0 + i) * kOpInts);
       const int4 lo = op[0], hi = op[1];  // (f, k, r0, in), (out, child_begin, n_children, virt)
-      if (i < nreal) sOps[i] = make_int4(lo.z, lo.w, hi.x, 0);
+      if (i < nreal) {
+        sOps[i] = make_int4(lo.z, lo.w, hi.x, 0);
+        const int pad = hi.x + cr[8 + 2 * (6 * lo.x + lo.y - 1)];
+        sR[pad] = cmake<C>(0, 0);
+        sA[pad] = cmake<C>(0, 0);
+      }
       sOpv[i] = make_int4(lo.z, lo.w, hi.x, 0);
       sOpx[i] = make_int4(lo.x, lo.y, hi.y, hi.z | (hi.w << 16));
     }
@@ -575,7 +583,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
             C sum = cmake<C>(0, 0);
 #pragma unroll
             for (int m = 0; m < MC; ++m) {
-              if (m < cu_tab.n[q]) {
+              if (m < cu_tab.nw[q]) {
                 const int e = cu_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
                 for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + sidx], sR[sMeta[b].y + oc], sum);
               }
@@ -593,7 +601,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
             C sum = cmake<C>(0, 0);
 #pragma unroll
             for (int m = 0; m < MC; ++m) {
-              if (m < cd_tab.n[q]) {
+              if (m < cd_tab.nw[q]) {
                 const int e = cd_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
                 for (int mm = mask; mm; mm &= mm - 1) {
                   const int b = __ffs(mm) - 1;

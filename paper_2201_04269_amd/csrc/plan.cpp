@@ -161,7 +161,7 @@ int64_t tile_lds(const CorrCtx& X, const std::vector<int>& sk, const LdsModel& m
   int n_virt = 0;
   std::set<std::pair<int, int>> v1;
   for (auto& r : rows) {
-    units += X.ncol(r.f, r.k);
+    units += X.ncol(r.f, r.k) + (m.backward ? 1 : 0);
     if (r.k == 2) v1.insert({r.f, r.t.v[1]});
   }
   n_virt = int(v1.size());
@@ -206,10 +206,13 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
     std::set<RowId> rowset;
     rows_of(X, sk, &rowset);
     std::map<RowId, int> slot;
+    // backward rows carry one trailing zero element after their ncol columns:
+    // padded table entries of the reverse sweep point there
+    const bool pad_rows = o.extra != nullptr;
     int units = 0;
     for (auto& r : rowset) {
       slot[r] = units;
-      units += X.ncol(r.f, r.k);
+      units += X.ncol(r.f, r.k) + (pad_rows ? 1 : 0);
     }
     std::vector<int32_t> tr(kTileInts, 0);
     tr[0] = X.c;
