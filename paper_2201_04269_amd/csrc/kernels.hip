@@ -71,6 +71,52 @@ __device__ __forceinline__ void site_levels(const FlavTabs<NU, QMAX>& tu, const 
   }
 }
 
+// Factor-tree leaves of one site for the first NL source-key slots of the
+// thread: L_s = sum over a run's keys b of W[b, s] Dd[b, s], then
+// acc += Du[run, s] L_s at the end of the run (compensated).
+template <int NL, int MAXS, typename R, typename C>
+__device__ __forceinline__ void leaf_site(int B, const int4* meta, const C* sW, const C* sR, int n_src,
+                                          const int (&sl)[MAXS], const bool (&live)[MAXS], const int (&cu)[MAXS],
+                                          const int (&cd)[MAXS], CompAcc<R>& acc) {
+  C L[NL];
+#pragma unroll
+  for (int m = 0; m < NL; ++m) L[m] = cmake<C>(0, 0);
+  for (int b = 0; b < B; ++b) {
+    const int4 mb = meta[b];
+    const C* Wb = sW + b * n_src;
+    const C* Dd = sR + mb.y;
+#pragma unroll
+    for (int m = 0; m < NL; ++m) L[m] = cmac(Wb[sl[m]], Dd[cd[m]], L[m]);
+    if (mb.z) {
+      const C* Du = sR + mb.x;
+#pragma unroll
+      for (int m = 0; m < NL; ++m) {
+        C p = cmul(Du[cu[m]], L[m]);
+        if (!live[m]) p = cmake<C>(0, 0);
+        acc.add(p.x, p.y);
+        L[m] = cmake<C>(0, 0);
+      }
+    }
+  }
+}
+
+// Dispatch on the wave's number of live slots (uniform).
+template <int NL, int MAXS, typename R, typename C>
+__device__ __forceinline__ void leaf_dispatch(int nlive, int B, const int4* meta, const C* sW, const C* sR,
+                                              int n_src, const int (&sl)[MAXS], const bool (&live)[MAXS],
+                                              const int (&cu)[MAXS], const int (&cd)[MAXS], CompAcc<R>& acc) {
+  if (nlive <= 0) return;
+  if constexpr (NL >= MAXS) {
+    leaf_site<MAXS, MAXS>(B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
+  } else {
+    if (nlive == NL) {
+      leaf_site<NL, MAXS>(B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
+      return;
+    }
+    leaf_dispatch<NL + 1, MAXS>(nlive, B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
+  }
+}
+
 template <typename R, int NU, int ND, int MAXS, int QMAX>
 __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   using C = typename cx<R>::T;
@@ -108,13 +154,20 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   tu.load(cr, 0, a.tabs);
   td.load(cr, 1, a.tabs);
 
-  int cu[MAXS], cd[MAXS];
+  // source keys s = tid + NT m; lanes past the last key read key n_src - 1
+  // and drop their products; the wave runs the slots its first lane has
+  int cu[MAXS], cd[MAXS], sl[MAXS];
+  bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
     const int s = tid + kNT * m;
-    cu[m] = s < n_src ? a.src_cu[src_off + s] : 0;
-    cd[m] = s < n_src ? a.src_cd[src_off + s] : 0;
+    live[m] = s < n_src;
+    sl[m] = live[m] ? s : n_src - 1;
+    cu[m] = a.src_cu[src_off + sl[m]];
+    cd[m] = a.src_cd[src_off + sl[m]];
   }
+  const int wave0 = tid & ~63;
+  const int nlive = (n_src - wave0 + kNT - 1) / kNT;  // > 0 unless the wave has no key
 
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;
@@ -140,31 +193,7 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
     const bool have_next = v + 1 < v1;
     if (have_next) fetch(v + 1, pre);
     site_levels<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
-    C L[MAXS];
-#pragma unroll
-    for (int m = 0; m < MAXS; ++m) L[m] = cmake<C>(0, 0);
-    for (int b = 0; b < B; ++b) {
-      const int4 mb = meta[b];
-      const C* Wb = sW + b * n_src;
-      const C* Dd = sR + mb.y;
-#pragma unroll
-      for (int m = 0; m < MAXS; ++m) {
-        const int s = tid + kNT * m;
-        if (s < n_src) L[m] = cmac(Wb[s], Dd[cd[m]], L[m]);
-      }
-      if (mb.z) {
-        const C* Du = sR + mb.x;
-#pragma unroll
-        for (int m = 0; m < MAXS; ++m) {
-          const int s = tid + kNT * m;
-          if (s < n_src) {
-            const C p = cmul(Du[cu[m]], L[m]);
-            acc.add(p.x, p.y);
-          }
-          L[m] = cmake<C>(0, 0);
-        }
-      }
-    }
+    leaf_dispatch<1, MAXS>(nlive, B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
     if constexpr (!kOverlapLeaves) __syncthreads();
   }
 

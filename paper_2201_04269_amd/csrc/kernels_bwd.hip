@@ -338,6 +338,48 @@ struct CsrTab {
   }
 };
 
+// Leaf adjoint of one top column: sum over the group's sink keys b and the
+// first NM entries (s, oc) of the column's source-key list of
+// W[b, s] * (other flavour's top minor at b's row slot, column oc).  The u
+// leaves take the run [lo, hi) and the d slots of its keys; the d leaves take
+// the sink keys in the bit mask lo and their u slots.
+template <int NM, int MC, bool MASK, typename C>
+__device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, const C* sW, int n_src, const C* sR,
+                                        const int2* sMeta) {
+  C sum = cmake<C>(0, 0);
+  int sidx[NM], oc[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    sidx[m] = e[m] & 2047;
+    oc[m] = e[m] >> 11;
+  }
+  auto key = [&](int b) {
+    const C* wrow = sW + b * n_src;
+    const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) sum = cmac(wrow[sidx[m]], orow[oc[m]], sum);
+  };
+  if constexpr (MASK) {
+    for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
+  } else {
+    for (int b = lo; b < hi; ++b) key(b);
+  }
+  return sum;
+}
+
+// Dispatch on the wave's longest list (nw, uniform), in steps of two entries;
+// the padded entries of shorter lists contribute zero.
+template <int N, int MC, bool MASK, typename C>
+__device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
+                                      const C* sR, const int2* sMeta) {
+  if constexpr (N >= MC) {
+    return leaf_terms<MC, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
+  } else {
+    if (nw <= N) return leaf_terms<N, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
+    return leaf_sum<N + 2, MC, MASK>(nw, e, lo, hi, sW, n_src, sR, sMeta);
+  }
+}
+
 template <int NF, int QMAX>
 struct RevTabs {
   BinTab<1> b1;
@@ -580,14 +622,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = tid + kNT * q;
           if (c < cu_tab.ncol) {
-            C sum = cmake<C>(0, 0);
-#pragma unroll
-            for (int m = 0; m < MC; ++m) {
-              if (m < cu_tab.nw[q]) {
-                const int e = cu_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
-                for (int b = b0; b < b1; ++b) sum = cmac(sW[b * n_src + sidx], sR[sMeta[b].y + oc], sum);
-              }
-            }
+            const C sum = leaf_sum<2, MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
           }
         }
@@ -598,17 +633,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = tid + kNT * q;
           if (c < cd_tab.ncol) {
-            C sum = cmake<C>(0, 0);
-#pragma unroll
-            for (int m = 0; m < MC; ++m) {
-              if (m < cd_tab.nw[q]) {
-                const int e = cd_tab.e[q][m], sidx = e & 2047, oc = e >> 11;
-                for (int mm = mask; mm; mm &= mm - 1) {
-                  const int b = __ffs(mm) - 1;
-                  sum = cmac(sW[b * n_src + sidx], sR[sMeta[b].x + oc], sum);
-                }
-              }
-            }
+            const C sum = leaf_sum<2, MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
           }
         }

@@ -64,6 +64,10 @@ struct Levels {
   std::vector<std::map<Key, int>> index;  // index[k]
 };
 
+// Needed columns of every level.  `top` lists the source tuples with their
+// multiplicity; the top level is ordered by decreasing multiplicity (the
+// length of a column's source-key list), so that the threads of a wavefront,
+// which own consecutive top columns, walk lists of similar length.
 Levels column_levels(const std::vector<Key>& top, int n) {
   Levels L;
   L.n = n;
@@ -73,6 +77,12 @@ Levels column_levels(const std::vector<Key>& top, int n) {
     std::set<Key> s;
     for (const Key& c : top) k_subsets(c, k, &s);
     L.cols[k].assign(s.begin(), s.end());
+    if (k == n) {
+      std::map<Key, int> mult;
+      for (const Key& c : top) ++mult[c];
+      std::stable_sort(L.cols[k].begin(), L.cols[k].end(),
+                       [&](const Key& a, const Key& b) { return mult[a] > mult[b]; });
+    }
     for (size_t i = 0; i < L.cols[k].size(); ++i) L.index[k][L.cols[k][i]] = int(i);
   }
   return L;
