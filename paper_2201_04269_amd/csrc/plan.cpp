@@ -499,9 +499,10 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.nnz = int64_t(s.entries.size());
   P.threads = 256;
   const int csz = precision == MBC_F64 ? 16 : 8;
-  // local-memory budgets per workgroup (forward; backward dS kernel)
+  // local-memory budgets per workgroup (forward; backward dS kernel): two
+  // workgroups share a CU's 160 KiB, except the FP32 forward (three)
   const int64_t budget = precision == MBC_F64 ? 76 * 1024 : 52 * 1024;
-  const int64_t bbudget = precision == MBC_F64 ? 100 * 1024 : 64 * 1024;
+  const int64_t bbudget = precision == MBC_F64 ? 76 * 1024 : 64 * 1024;
   const int kMaxB = 16;
   const LdsModel fwd_model{false, csz}, bwd_model{true, csz};
   P.corr.assign(size_t(s.n_corr) * kCorrInts, 0);
