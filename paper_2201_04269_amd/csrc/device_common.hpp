@@ -179,10 +179,10 @@ struct LevelTab {
   int ncol = 0, G = 1, g = 0, i0 = 0;
   int e[QMAX][K > 0 ? K : 1];
 
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
+  // t: the thread's index in the workgroup's (possibly rotated) lane order
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs, int t) {
     ncol = cr[8 + 2 * (6 * f + K - 1)];
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
-    const int t = threadIdx.x;
     if (ncol > 0 && ncol <= kNT) {
       G = kNT / ncol;
       g = t / ncol;
@@ -252,13 +252,14 @@ struct FlavTabs {
   LevelTab<4, QMAX> l4;
   LevelTab<5, QMAX> l5;
   LevelTab<6, QMAX> l6;
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs) {
-    if constexpr (NF == 1) l1.load(cr, f, tabs);
-    if constexpr (NF >= 2) l2.load(cr, f, tabs);
-    if constexpr (NF >= 3) l3.load(cr, f, tabs);
-    if constexpr (NF >= 4) l4.load(cr, f, tabs);
-    if constexpr (NF >= 5) l5.load(cr, f, tabs);
-    if constexpr (NF >= 6) l6.load(cr, f, tabs);
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs,
+                                       int t = threadIdx.x) {
+    if constexpr (NF == 1) l1.load(cr, f, tabs, t);
+    if constexpr (NF >= 2) l2.load(cr, f, tabs, t);
+    if constexpr (NF >= 3) l3.load(cr, f, tabs, t);
+    if constexpr (NF >= 4) l4.load(cr, f, tabs, t);
+    if constexpr (NF >= 5) l5.load(cr, f, tabs, t);
+    if constexpr (NF >= 6) l6.load(cr, f, tabs, t);
   }
 };
 

@@ -217,8 +217,7 @@ __host__ __device__ constexpr int bin_lanes(int k) { return k <= 2 ? 1 : 16; }
 template <int K>
 struct BinTab {
   int e[bin_regs(K)];
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab) {
-    const int t = threadIdx.x;
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab, int t) {
     // unused slots read column ncol of the row: its zero element
     const int pad = cr[8 + 2 * (6 * f + K - 1)];
 #pragma unroll
@@ -258,12 +257,11 @@ struct UpTab {
   unsigned up[QMAX][6];
   int colnum[QMAX];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab,
-                                       const uint16_t* __restrict__ tabs) {
+                                       const uint16_t* __restrict__ tabs, int t) {
     ncol = cr[8 + 2 * (6 * f + K - 1)];
     const unsigned pad = unsigned(cr[8 + 2 * (6 * f + K)]) & 2047u;  // ncol one level up
     const int32_t* ut = btab + cr[67 + 6 * f + K - 1];
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
-    const int t = threadIdx.x;
     if (ncol > 0 && ncol <= kNT) {
       G = kNT / ncol;
       g = t / ncol;
@@ -310,14 +308,15 @@ struct CsrTab {
   int nw[QMAX];
   int e[QMAX][MC];
   __device__ __forceinline__ void load(const int32_t* cr, int f, int nf, int nf_other,
-                                       const int32_t* __restrict__ btab, const int32_t* __restrict__ other_col) {
+                                       const int32_t* __restrict__ btab, const int32_t* __restrict__ other_col,
+                                       int t) {
     ncol = cr[8 + 2 * (6 * f + nf - 1)];
     const int pad = cr[8 + 2 * (6 * (1 - f) + nf_other - 1)] << 11;
     const int32_t* lists = btab + cr[64 + f];
     const int src_off = cr[1];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = threadIdx.x + kNT * q;
+      const int c = t + kNT * q;
       int n = 0, q0 = 0;
       if (c < ncol) {
         q0 = lists[c];
@@ -391,16 +390,19 @@ struct RevTabs {
   UpTab<2, QMAX> u2;
   UpTab<3, QMAX> u3;
   UpTab<4, QMAX> u4;
-  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* btab, const uint16_t* tabs) {
-    if constexpr (NF == 1) b1.load(cr, f, btab);
-    if constexpr (NF >= 2) b2.load(cr, f, btab);
-    if constexpr (NF >= 3) b3.load(cr, f, btab);
-    if constexpr (NF >= 4) b4.load(cr, f, btab);
-    if constexpr (NF >= 5) b5.load(cr, f, btab);
-    if constexpr (NF >= 2) u1.load(cr, f, btab, tabs);
-    if constexpr (NF >= 3) u2.load(cr, f, btab, tabs);
-    if constexpr (NF >= 4) u3.load(cr, f, btab, tabs);
-    if constexpr (NF >= 5) u4.load(cr, f, btab, tabs);
+  int tb = 0;  // lane order of the S-bar bins; the parent tables take their own
+  __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* btab, const uint16_t* tabs,
+                                       int t_bins, int t_ups) {
+    tb = t_bins;
+    if constexpr (NF == 1) b1.load(cr, f, btab, t_bins);
+    if constexpr (NF >= 2) b2.load(cr, f, btab, t_bins);
+    if constexpr (NF >= 3) b3.load(cr, f, btab, t_bins);
+    if constexpr (NF >= 4) b4.load(cr, f, btab, t_bins);
+    if constexpr (NF >= 5) b5.load(cr, f, btab, t_bins);
+    if constexpr (NF >= 2) u1.load(cr, f, btab, tabs, t_ups);
+    if constexpr (NF >= 3) u2.load(cr, f, btab, tabs, t_ups);
+    if constexpr (NF >= 4) u3.load(cr, f, btab, tabs, t_ups);
+    if constexpr (NF >= 5) u4.load(cr, f, btab, tabs, t_ups);
   }
 };
 
@@ -442,9 +444,8 @@ __device__ __forceinline__ C bin_sum(const BinTab<K>& bt, int4 ov, const C* Sf, 
 // (ii) S-bar partials of the level-K rows [o0, o0 + cnt) of one flavour:
 // part[o][j] = sum over columns C containing j of (-1)^pos A(C) M_{K-1}(C \ j).
 template <int K, typename C>
-__device__ __forceinline__ void rev_part(const BinTab<K>& bt, int o0, int cnt, const int4* sOpv, const C* Sf,
-                                         const C* sR, const C* sA, C* sPart) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void rev_part(const BinTab<K>& bt, int tid, int o0, int cnt, const int4* sOpv,
+                                         const C* Sf, const C* sR, const C* sA, C* sPart) {
   if constexpr (K <= 2) {
     if (tid >= 252) return;
     const int j = tid % 12;
@@ -516,9 +517,10 @@ __device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX>& ru, const Re
                                            const int32_t* children, const C* sS, const C* sR, C* sA, C* sAdj1,
                                            C* sPart) {
   if constexpr (K >= 1) {
-    if constexpr (K <= NU) rev_part<K>(bins_of<K>(ru), tr[20 + 2 * K], tr[21 + 2 * K], sOpv, sS, sR, sA, sPart);
+    if constexpr (K <= NU)
+      rev_part<K>(bins_of<K>(ru), ru.tb, tr[20 + 2 * K], tr[21 + 2 * K], sOpv, sS, sR, sA, sPart);
     if constexpr (K <= ND)
-      rev_part<K>(bins_of<K>(rd), tr[20 + 2 * (7 + K)], tr[21 + 2 * (7 + K)], sOpv, sS + 144, sR, sA, sPart);
+      rev_part<K>(bins_of<K>(rd), rd.tb, tr[20 + 2 * (7 + K)], tr[21 + 2 * (7 + K)], sOpv, sS + 144, sR, sA, sPart);
     if constexpr (K >= 2) {
       // parents: real rows of level K-1, or the level-1 records for K = 2
       if constexpr (K <= NU) {
@@ -550,7 +552,16 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   for (int i = tid; i < 288; i += kNT)
     sS[i] = load_site<C>(i < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (i % 144));
 
-  CompAcc<R> sb[2];  // S-bar entries tid and tid + NT (< 288)
+  // Lane orders: the workgroup's lanes are rotated by a multiple of a wave
+  // (so that co-resident workgroups put their busiest wave on different
+  // SIMDs), and the u and d flavours and the parent tables start half a
+  // workgroup / a quarter apart, so that small per-flavour tasks of one
+  // level run on different waves side by side.
+  const int rot = int(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & 3) * 64;
+  const int vt = (tid + rot) & (kNT - 1);
+  const int vt_u = vt, vt_d = (vt + 128) & (kNT - 1);
+  const int vt_pu = (vt + 64) & (kNT - 1), vt_pd = (vt + 192) & (kNT - 1);
+  CompAcc<R> sb[2];  // S-bar entries vt and vt + NT (< 288)
   int cur_corr = -1;
   FlavTabs<NU, QMAX> tu;
   FlavTabs<ND, QMAX> td;
@@ -566,12 +577,12 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     const int32_t* cr = a.corr + corr * kCorrInts;
     const int n_src = cr[0];
     if (corr != cur_corr) {
-      tu.load(cr, 0, a.tabs);
-      td.load(cr, 1, a.tabs);
-      ru.load(cr, 0, a.btab, a.tabs);
-      rd.load(cr, 1, a.btab, a.tabs);
-      cu_tab.load(cr, 0, NU, ND, a.btab, a.src_cd);
-      cd_tab.load(cr, 1, ND, NU, a.btab, a.src_cu);
+      tu.load(cr, 0, a.tabs, vt_u);
+      td.load(cr, 1, a.tabs, vt_d);
+      ru.load(cr, 0, a.btab, a.tabs, vt_u, vt_pu);
+      rd.load(cr, 1, a.btab, a.tabs, vt_d, vt_pd);
+      cu_tab.load(cr, 0, NU, ND, a.btab, a.src_cd, vt_u);
+      cd_tab.load(cr, 1, ND, NU, a.btab, a.src_cu, vt_d);
       cur_corr = corr;
     }
     C gbar;
@@ -620,7 +631,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-          const int c = tid + kNT * q;
+          const int c = vt_u + kNT * q;
           if (c < cu_tab.ncol) {
             const C sum = leaf_sum<2, MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
@@ -631,7 +642,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         const int ds = dgs[2 * g], mask = dgs[2 * g + 1];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-          const int c = tid + kNT * q;
+          const int c = vt_d + kNT * q;
           if (c < cd_tab.ncol) {
             const C sum = leaf_sum<2, MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
@@ -648,7 +659,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     // fixed-order accumulation of this tile's S-bar contributions
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int e = tid + kNT * q;
+      const int e = vt + kNT * q;
       if (e < 288) {
         const int row = e / 12, bc = e % 12;  // row = 12 f + r0
         C sum = cmake<C>(0, 0);
@@ -667,7 +678,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   // grad_S = conj(S-bar)
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int e = tid + kNT * q;
+    const int e = vt + kNT * q;
     if (e < 288) {
       const double x = double(sb[q].hx) + double(sb[q].lx);
       const double y = -(double(sb[q].hy) + double(sb[q].ly));
