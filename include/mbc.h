@@ -132,6 +132,7 @@ typedef struct {
   int64_t b_lds_bytes_dw;     /* dynamic LDS per workgroup, dW kernel */
   double ds_alg_flops_per_site; /* dS: minors + reverse sweep (16k per level-k minor) + 16 per entry */
   double dw_alg_flops_per_site; /* dW: minors + 8 per entry */
+  int32_t w_n_tiles;            /* tiles of the dW schedule */
 } mbc_plan_stats;
 mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out);
 

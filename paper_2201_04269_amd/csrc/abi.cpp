@@ -80,8 +80,8 @@ mbc_status upload(const std::vector<T>& v, T** out, hipStream_t st) {
 }
 
 void free_device(PlanDevice& d) {
-  void* ptrs[] = {d.corr,  d.tiles,   d.ops,  d.meta,   d.src_cu,  d.src_cd, d.tabs,
-                  d.perm,  d.w_exact, d.b_tiles, d.b_ops, d.b_meta, d.b_extra, d.btab};
+  void* ptrs[] = {d.corr,    d.tiles,   d.ops,   d.meta,    d.src_cu, d.src_cd,  d.tabs,   d.perm,
+                  d.w_exact, d.b_tiles, d.b_ops, d.b_meta, d.b_extra, d.btab, d.w_tiles, d.w_ops, d.w_meta};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = PlanDevice();
@@ -223,7 +223,9 @@ mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stre
         (st = upload(h.tabs, &p->d.tabs, hs)) != MBC_OK || (st = upload(h.perm, &p->d.perm, hs)) != MBC_OK ||
         (st = upload(h.b_tiles, &p->d.b_tiles, hs)) != MBC_OK ||
         (st = upload(h.b_ops, &p->d.b_ops, hs)) != MBC_OK || (st = upload(h.b_meta, &p->d.b_meta, hs)) != MBC_OK ||
-        (st = upload(h.b_extra, &p->d.b_extra, hs)) != MBC_OK || (st = upload(h.btab, &p->d.btab, hs)) != MBC_OK) {
+        (st = upload(h.b_extra, &p->d.b_extra, hs)) != MBC_OK || (st = upload(h.btab, &p->d.btab, hs)) != MBC_OK ||
+        (st = upload(h.w_tiles, &p->d.w_tiles, hs)) != MBC_OK || (st = upload(h.w_ops, &p->d.w_ops, hs)) != MBC_OK ||
+        (st = upload(h.w_meta, &p->d.w_meta, hs)) != MBC_OK) {
       free_device(p->d);
       delete p;
       return st;
@@ -268,6 +270,7 @@ mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out) {
   out->b_lds_bytes_dw = p->h.b_lds_dw;
   out->ds_alg_flops_per_site = p->h.ds_alg_flops_per_site;
   out->dw_alg_flops_per_site = p->h.dw_alg_flops_per_site;
+  out->w_n_tiles = p->h.w_n_tiles;
   return MBC_OK;
 }
 
@@ -364,8 +367,8 @@ mbc_status mbc_contract_backward(const mbc_plan* p, const void* S_u, const void*
   if (grad_S_u || grad_S_d) {
     const size_t bytes = size_t(T) * size_t(sites_per_t) * 144 * (s_c64 ? 8 : 16);
     if (p->h.b_n_tiles == 0) {
-      if (grad_S_u) MBC_HIP(hipMemsetAsync(grad_S_u, 0, bytes, hs));
-      if (grad_S_d) MBC_HIP(hipMemsetAsync(grad_S_d, 0, bytes, hs));
+      if (grad_S_u) MBC_HIP(launch_zero(grad_S_u, bytes, hs));
+      if (grad_S_d) MBC_HIP(launch_zero(grad_S_d, bytes, hs));
     } else {
       MBC_HIP(launch_backward_ds(p, S_u, S_d, s_c64, T, sites_per_t, W_plan, grad_C, grad_S_u, grad_S_d, hs));
     }

@@ -90,6 +90,7 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
     stats->b_n_tiles = h.b_n_tiles;
     stats->b_lds_bytes_ds = h.b_lds_ds;
     stats->b_lds_bytes_dw = h.b_lds_dw;
+    stats->w_n_tiles = h.w_n_tiles;
     stats->ds_alg_flops_per_site = h.ds_alg_flops_per_site;
     stats->dw_alg_flops_per_site = h.dw_alg_flops_per_site;
   }
@@ -128,7 +129,6 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
     A.assign(size_t(units), cd(0, 0));
     for (int t = 0; t < T; ++t) {
       const cd gbar = std::conj(cd(grad_C[2 * (size_t(corr) * T + t)], grad_C[2 * (size_t(corr) * T + t) + 1]));
-      std::vector<cd> Q(size_t(B) * n_src, cd(0, 0));
       for (int64_t v = 0; v < V; ++v) {
         const int64_t site = int64_t(t) * V + v;
         for (int i = 0; i < 144; ++i) {
@@ -155,12 +155,6 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
             }
             R[outs + i] = val;
           }
-        }
-        // dW: per-entry products summed over the sites of the timeslice
-        for (int b = 0; b < B; ++b) {
-          const int32_t* mb = metab(b);
-          for (int sidx = 0; sidx < n_src; ++sidx)
-            Q[size_t(b) * n_src + sidx] += R[mb[0] + h.src_cu[src_off + sidx]] * R[mb[1] + h.src_cd[src_off + sidx]];
         }
         // leaf adjoints of the top rows (holomorphic, seeded with conj(grad_C))
         const int ncu = cr[8 + 2 * (6 * 0 + nf[0] - 1)], ncd = cr[8 + 2 * (6 * 1 + nf[1] - 1)];
@@ -259,6 +253,49 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
               }
               sb[144 * f + 12 * a + bb] += sum;
             }
+      }
+    }
+  }
+  // dW through its own tiling: per-entry products summed over each timeslice
+  for (int tile = 0; tile < h.w_n_tiles; ++tile) {
+    const int32_t* tr = &h.w_tiles[size_t(tile) * kTileInts];
+    const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nops = tr[4], meta0 = tr[5], units = tr[6];
+    const int32_t* cr = &h.corr[size_t(corr) * kCorrInts];
+    const int n_src = cr[0], src_off = cr[1];
+    R.assign(size_t(units), cd(0, 0));
+    for (int t = 0; t < T; ++t) {
+      std::vector<cd> Q(size_t(B) * n_src, cd(0, 0));
+      for (int64_t v = 0; v < V; ++v) {
+        const int64_t site = int64_t(t) * V + v;
+        for (int i = 0; i < 144; ++i) {
+          S[i] = cd(S_u[2 * (site * 144 + i)], S_u[2 * (site * 144 + i) + 1]);
+          S[144 + i] = cd(S_d[2 * (site * 144 + i)], S_d[2 * (site * 144 + i) + 1]);
+        }
+        for (int o = 0; o < nops; ++o) {
+          const int32_t* p = &h.w_ops[size_t(op0 + o) * kOpInts];
+          const int f = p[0], k = p[1], r0 = p[2], in = p[3], outs = p[4];
+          const int nc = cr[8 + 2 * (6 * f + k - 1)], toff = cr[8 + 2 * (6 * f + k - 1) + 1];
+          const cd* Sf = &S[144 * f];
+          for (int i = 0; i < nc; ++i) {
+            cd val(0, 0);
+            if (k == 1) {
+              val = Sf[12 * r0 + h.tabs[toff + i]];
+            } else {
+              for (int j = 0; j < k; ++j) {
+                const int e = h.tabs[toff + i * k + j];
+                const cd x = Sf[12 * r0 + (e & 15)];
+                const cd y = (k == 2) ? Sf[12 * in + (e >> 4)] : R[in + (e >> 4)];
+                val += (j & 1) ? -x * y : x * y;
+              }
+            }
+            R[outs + i] = val;
+          }
+        }
+        for (int b = 0; b < B; ++b) {
+          const int32_t* mb = &h.w_meta[size_t(meta0 + b) * kMetaInts];
+          for (int sidx = 0; sidx < n_src; ++sidx)
+            Q[size_t(b) * n_src + sidx] += R[mb[0] + h.src_cu[src_off + sidx]] * R[mb[1] + h.src_cd[src_off + sidx]];
+        }
       }
       const cd g(grad_C[2 * (size_t(corr) * T + t)], grad_C[2 * (size_t(corr) * T + t) + 1]);
       for (int b = 0; b < B; ++b)

@@ -358,4 +358,18 @@ hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* parti
   return hipGetLastError();
 }
 
+namespace {
+__global__ void zero_kernel(unsigned long long* p, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 8;
+  if (n == 0) return hipSuccess;
+  const size_t nb = std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(zero_kernel, dim3(unsigned(nb)), dim3(256), 0, st, static_cast<unsigned long long*>(p), n);
+  return hipGetLastError();
+}
+
 }  // namespace mbc

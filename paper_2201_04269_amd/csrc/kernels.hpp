@@ -27,6 +27,10 @@ hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, i
 hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
                          hipStream_t st);
 
+// Zero-fills bytes (a multiple of 8) of device memory with a kernel (no
+// memset node when the caller captures the stream).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
 // Backward: dW (tile-major over timeslice chunks, then a fixed-order sum over
 // chunks into grad_W in index-set order) and dS (one workgroup per site).
 Launch backward_dw_launch_shape(const PlanHost& h, int T, int64_t V);

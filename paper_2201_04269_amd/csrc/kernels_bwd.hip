@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -95,7 +96,32 @@ __device__ __forceinline__ void site_levels_pf(const FlavTabs<NU, QMAX>& tu, con
 // ---------------------------------------------------------------------------
 // dW
 // ---------------------------------------------------------------------------
-template <typename R, int NU, int ND, int MAXS, int QMAX>
+// Products of one site for the tile's NB sink keys and the thread's source
+// slots: acc[b][m] += Du[b, s_m] Dd[b, s_m].  A wave skips the slots past its
+// last source key (uniform); lanes past n_src read key n_src - 1 and are
+// never written out.
+template <int NB, int BW, int MAXS, typename R, typename C>
+__device__ __forceinline__ void dw_products(const C* sR, const int (&us)[BW], const int (&dsl)[BW],
+                                            const int (&cu)[MAXS], const int (&cd)[MAXS], int nlive,
+                                            CompAcc<R> (&acc)[BW][MAXS]) {
+#pragma unroll
+  for (int m = 0; m < MAXS; ++m) {
+    if (m < nlive) {
+      C p[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) p[b] = cmul(sR[us[b] + cu[m]], sR[dsl[b] + cd[m]]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b][m].add(p[b].x, p[b].y);
+    }
+  }
+}
+
+// dW: one workgroup per (dW tile, chunk of sites of one timeslice).  Per site
+// the tile's rows are built (propagators double-buffered), then every
+// (sink key, source key) product of the tile is added to its compensated
+// accumulator, held in registers across the chunk; the chunk's sums,
+// times grad_C, go to partial[t * nc + chunk][entry].
+template <typename R, int NU, int ND, int MAXS, int QMAX, int BW>
 __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
@@ -107,7 +133,7 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
   const int tile = lin % a.n_tiles;
   const int tc = lin / a.n_tiles;
   const int32_t* tr = a.tiles + tile * kTileInts;
-  const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nreal = tr[17];
+  const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], nops = tr[4];
   const int meta0 = tr[5], row_units = tr[6];
   const int32_t* cr = a.corr + corr * kCorrInts;
   const int n_src = cr[0], src_off = cr[1];
@@ -115,26 +141,34 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
   C* sS0 = reinterpret_cast<C*>(smem);
   C* sR = sS0 + 576;
   int4* sOps = lds_align16<int4>(smem, sR + row_units);
-  R* sAcc = reinterpret_cast<R*>(sOps + nreal);  // [B * n_src][4]: hx, lx, hy, ly
-  int4* meta = reinterpret_cast<int4*>(sAcc + 4 * B * n_src);  // (u slot, d slot, run end, key) per sink key
-
-  for (int i = tid; i < nreal; i += kNT) {
+  for (int i = tid; i < nops; i += kNT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
-  for (int i = tid; i < 4 * B * n_src; i += kNT) sAcc[i] = R(0);
-  if (tid < B) meta[tid] = reinterpret_cast<const int4*>(a.meta)[meta0 + tid];
+  int us[BW], dsl[BW];
+#pragma unroll
+  for (int b = 0; b < BW; ++b) {
+    const int4 mb = reinterpret_cast<const int4*>(a.meta)[meta0 + (b < B ? b : 0)];
+    us[b] = mb.x;
+    dsl[b] = mb.y;
+  }
   FlavTabs<NU, QMAX> tu;
   FlavTabs<ND, QMAX> td;
   tu.load(cr, 0, a.tabs);
   td.load(cr, 1, a.tabs);
   int cu[MAXS], cd[MAXS];
+  bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
     const int s = tid + kNT * m;
-    cu[m] = s < n_src ? a.src_cu[src_off + s] : 0;
-    cd[m] = s < n_src ? a.src_cd[src_off + s] : 0;
+    live[m] = s < n_src;
+    const int sl = live[m] ? s : n_src - 1;
+    cu[m] = a.src_cu[src_off + sl];
+    cd[m] = a.src_cd[src_off + sl];
   }
+  const int nlive = (n_src - (tid & ~63) + kNT - 1) / kNT;  // slots the wave runs
+  CompAcc<R> acc[BW][MAXS];
+
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;
   const int64_t v1 = (v0 + a.chunk < a.V) ? v0 + a.chunk : a.V;
@@ -155,35 +189,35 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
     const bool have_next = v + 1 < v1;
     if (have_next) fetch(v + 1, pre);
     site_levels_pf<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
-    for (int b = 0; b < B; ++b) {
-      const int4 mb = meta[b];
-#pragma unroll
-      for (int m = 0; m < MAXS; ++m) {
-        const int s = tid + kNT * m;
-        if (s < n_src) {
-          const C p = cmul(sR[mb.x + cu[m]], sR[mb.y + cd[m]]);
-          R* acc = sAcc + 4 * (b * n_src + s);
-          R sx, ex, sy, ey;
-          two_sum(acc[0], p.x, sx, ex);
-          two_sum(acc[2], p.y, sy, ey);
-          acc[0] = sx;
-          acc[1] += ex;
-          acc[2] = sy;
-          acc[3] += ey;
-        }
-      }
+    // dispatch on the tile's number of sink keys (uniform; written out so
+    // that the accumulators stay in registers)
+    if (nlive > 0) {
+      constexpr int N2 = BW < 2 ? BW : 2, N3 = BW < 3 ? BW : 3;
+      if (B == 1)
+        dw_products<1, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+      else if (B == 2)
+        dw_products<N2, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+      else if (B == 3)
+        dw_products<N3, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+      else
+        dw_products<BW, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
     }
     if constexpr (!kOverlapLeaves) __syncthreads();
   }
-  __syncthreads();
   const double gx = a.grad_C[2 * (int64_t(corr) * a.T + t)], gy = a.grad_C[2 * (int64_t(corr) * a.T + t) + 1];
   double* out = a.partial + 2 * (int64_t(tc) * a.nnz + w_off);
-  for (int i = tid; i < B * n_src; i += kNT) {
-    const R* acc = sAcc + 4 * i;
-    const double qx = double(acc[0]) + double(acc[1]);
-    const double qy = -(double(acc[2]) + double(acc[3]));  // conj(Q)
-    out[2 * i] = gx * qx - gy * qy;
-    out[2 * i + 1] = gx * qy + gy * qx;
+#pragma unroll
+  for (int b = 0; b < BW; ++b) {
+#pragma unroll
+    for (int m = 0; m < MAXS; ++m) {
+      if (b < B && live[m]) {
+        const int i = b * n_src + tid + kNT * m;
+        const double qx = double(acc[b][m].hx) + double(acc[b][m].lx);
+        const double qy = -(double(acc[b][m].hy) + double(acc[b][m].ly));  // conj(Q)
+        out[2 * i] = gx * qx - gy * qy;
+        out[2 * i + 1] = gx * qy + gy * qx;
+      }
+    }
   }
 }
 
@@ -733,13 +767,21 @@ hipError_t launch_k(K k, int nblocks, size_t lds, hipStream_t st, const BwdArgs&
   return hipGetLastError();
 }
 
+template <typename R, int NU, int ND, int QMAX>
+hipError_t launch_dw_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
+  constexpr int MS = dw_src_per_thread(NU, ND);
+  constexpr int BW = dw_keys_per_tile(NU, ND, std::is_same<R, double>::value ? MBC_F64 : MBC_F32C);
+  if (p->h.maxs > MS || p->h.qmax > QMAX || p->h.w_max_b > BW) return hipErrorNotSupported;
+  return launch_k(dw_kernel<R, NU, ND, MS, QMAX, BW>, nb, lds, st, a);
+}
+
 template <typename R>
 hipError_t launch_dw_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
-  const int nu = p->h.n_u, nd = p->h.n_d, ms = p->h.maxs, qm = p->h.qmax;
-  if (nu == 2 && nd == 1 && ms <= 1 && qm <= 1) return launch_k(dw_kernel<R, 2, 1, 1, 1>, nb, lds, st, a);
-  if (nu == 1 && nd == 2 && ms <= 1 && qm <= 1) return launch_k(dw_kernel<R, 1, 2, 1, 1>, nb, lds, st, a);
-  if (nu == 3 && nd == 3 && ms <= 4 && qm <= 1) return launch_k(dw_kernel<R, 3, 3, 4, 1>, nb, lds, st, a);
-  if (nu == 5 && nd == 4 && ms <= 8 && qm <= 2) return launch_k(dw_kernel<R, 5, 4, 8, 2>, nb, lds, st, a);
+  const int nu = p->h.n_u, nd = p->h.n_d;
+  if (nu == 2 && nd == 1) return launch_dw_f<R, 2, 1, 1>(p, a, nb, lds, st);
+  if (nu == 1 && nd == 2) return launch_dw_f<R, 1, 2, 1>(p, a, nb, lds, st);
+  if (nu == 3 && nd == 3) return launch_dw_f<R, 3, 3, 1>(p, a, nb, lds, st);
+  if (nu == 5 && nd == 4) return launch_dw_f<R, 5, 4, 2>(p, a, nb, lds, st);
   return hipErrorNotSupported;
 }
 
@@ -769,7 +811,7 @@ Launch backward_dw_launch_shape(const PlanHost& h, int T, int64_t V) {
   // whole timeslices per workgroup unless the grid would be too small
   const int64_t want = 4096;
   int64_t nc = 1;
-  const int64_t base = int64_t(std::max(1, h.b_n_tiles)) * T;
+  const int64_t base = int64_t(std::max(1, h.w_n_tiles)) * T;
   if (base < want) nc = (want + base - 1) / base;
   if (nc > V) nc = V;
   L.chunk = int((V + nc - 1) / nc);
@@ -782,9 +824,13 @@ hipError_t launch_backward_dw(const mbc_plan* p, const void* S_u, const void* S_
                               hipStream_t st) {
   if (p->h.nnz == 0) return hipSuccess;
   BwdArgs a = make_args(p, S_u, S_d, s_c64, L, W_plan);
+  a.tiles = p->d.w_tiles;
+  a.ops = p->d.w_ops;
+  a.meta = p->d.w_meta;
+  a.n_tiles = p->h.w_n_tiles;
   a.grad_C = grad_C;
   a.partial = partial;
-  const int64_t nb = int64_t(p->h.b_n_tiles) * L.T * L.nc;
+  const int64_t nb = int64_t(p->h.w_n_tiles) * L.T * L.nc;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   const size_t lds = size_t(p->h.b_lds_dw);
   hipError_t e = (p->h.precision == MBC_F64) ? launch_dw_r<double>(p, a, int(nb), lds, st)

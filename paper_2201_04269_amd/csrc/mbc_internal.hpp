@@ -99,6 +99,14 @@ constexpr int kOpInts = 8;
 constexpr int kMetaInts = 4;
 constexpr int kMaxPhases = 7;
 
+// Sink keys per tile of the dW schedule, and source keys per thread the dW
+// kernel is built for, per operator family (n_u, n_d) and precision (the
+// kernel keeps keys x source slots compensated accumulators in registers).
+constexpr int dw_keys_per_tile(int n_u, int n_d, int precision) {
+  return n_u + n_d >= 8 ? 1 : (n_u + n_d >= 6 && precision == MBC_F64 ? 2 : 4);
+}
+constexpr int dw_src_per_thread(int n_u, int n_d) { return n_u + n_d >= 8 ? 6 : (n_u + n_d >= 6 ? 3 : 1); }
+
 struct PlanHost {
   int n_u = 0, n_d = 0, n_corr = 0, precision = MBC_F64;
   int64_t nnz = 0;
@@ -114,6 +122,10 @@ struct PlanHost {
   int b_n_tiles = 0, b_max_ops = 0, b_max_b = 0;
   int64_t b_lds_ds = 0, b_lds_dw = 0;  // dS kernel, dW kernel
   std::vector<int32_t> b_tiles, b_ops, b_meta, b_extra, btab;
+  // dW tiling (at most dw_keys_per_tile sink keys: the kernel keeps every
+  // (key, source key) accumulator of a tile in registers)
+  int w_n_tiles = 0, w_max_ops = 0, w_max_b = 0;
+  std::vector<int32_t> w_tiles, w_ops, w_meta;
   int maxc_top = 0;      // max top-level columns over correlators and flavours
   int max_csr = 0;       // longest source-key list of a top column
   int max_bin[7] = {0, 0, 0, 0, 0, 0, 0};  // longest j-list per level
@@ -142,6 +154,9 @@ struct PlanDevice {
   int32_t* b_meta = nullptr;
   int32_t* b_extra = nullptr;
   int32_t* btab = nullptr;
+  int32_t* w_tiles = nullptr;
+  int32_t* w_ops = nullptr;
+  int32_t* w_meta = nullptr;
 };
 
 void set_error(const std::string& msg);

@@ -142,11 +142,12 @@ struct TileSetOut {
 
 // LDS model of a tile: complex units of (S, W, rows) plus bytes of staged records.
 struct LdsModel {
-  bool backward;
+  bool backward;  // dS kernel (rows carry a zero element, adjoint rows)
   int csz;
+  bool with_w = true;  // forward: the tile's weights are staged (not for dW)
   int64_t operator()(int B, int n_src, int64_t row_units, int n_ops, int n_virt, int64_t n_child) const {
     if (!backward) {
-      int64_t bytes = (576 + int64_t(B) * n_src + row_units) * csz;
+      int64_t bytes = (576 + (with_w ? int64_t(B) * n_src : 0) + row_units) * csz;
       return ((bytes + 15) & ~int64_t(15)) + int64_t(n_ops) * 16 + int64_t(B) * 16;
     }
     // dS kernel: S, W, rows, adjoint rows, level-1 adjoints, per-op j-partials,
@@ -504,7 +505,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   const int64_t budget = precision == MBC_F64 ? 76 * 1024 : 52 * 1024;
   const int64_t bbudget = precision == MBC_F64 ? 76 * 1024 : 64 * 1024;
   const int kMaxB = 16;
-  const LdsModel fwd_model{false, csz}, bwd_model{true, csz};
+  const LdsModel fwd_model{false, csz}, bwd_model{true, csz}, dw_model{false, csz, false};
+  const int dw_keys = dw_keys_per_tile(s.n_u, s.n_d, precision);
   P.corr.assign(size_t(s.n_corr) * kCorrInts, 0);
   P.w_exact.assign(size_t(2 * P.nnz), 0.0);
   P.perm.assign(size_t(P.nnz), 0);
@@ -512,6 +514,7 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   double alg = 0, exec = 0, ds_alg = 0, dw_alg = 0;
   TileSetOut fo{&P.tiles, &P.ops, &P.meta, nullptr, &P.n_tiles, &P.max_ops, &P.max_b, &exec};
   TileSetOut bo{&P.b_tiles, &P.b_ops, &P.b_meta, &P.b_extra, &P.b_n_tiles, &P.b_max_ops, &P.b_max_b, nullptr};
+  TileSetOut wo{&P.w_tiles, &P.w_ops, &P.w_meta, nullptr, &P.w_n_tiles, &P.w_max_ops, &P.w_max_b, nullptr};
 
   for (int c = 0; c < s.n_corr; ++c) {
     int32_t* cr = &P.corr[size_t(c) * kCorrInts];
@@ -631,6 +634,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     auto bt = make_tiles(X, bbudget, kMaxB, bwd_model);
     P.b_lds_ds = std::max(P.b_lds_ds, emit_tiles(X, bt, bwd_model, bo));
     cr[7] = P.b_n_tiles;
+    auto wt = make_tiles(X, budget, dw_keys, dw_model);
+    P.b_lds_dw = std::max(P.b_lds_dw, emit_tiles(X, wt, dw_model, wo));
   }
   if (w_pos != P.nnz) throw std::logic_error("plan does not cover the index set");
   for (int c = 0; c < s.n_corr; ++c) {
@@ -638,17 +643,6 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     P.max_csr = std::max({P.max_csr, int(cr[80]), int(cr[81])});
     for (int f = 0; f < 2; ++f)
       for (int k = 1; k <= 6; ++k) P.max_bin[k] = std::max(P.max_bin[k], int(cr[82 + 6 * f + k - 1]));
-  }
-  // dW kernel of the backward tiling: S (double buffer), rows, staged ops,
-  // compensated accumulators of the tile's weights (4 reals each) and the
-  // sink keys' slot records
-  for (int t = 0; t < P.b_n_tiles; ++t) {
-    const int32_t* tr = &P.b_tiles[size_t(t) * kTileInts];
-    const int32_t* cr = &P.corr[size_t(tr[0]) * kCorrInts];
-    int64_t bytes = (576 + int64_t(tr[6])) * csz;
-    bytes = (bytes + 15) & ~int64_t(15);
-    const int64_t lds = bytes + int64_t(tr[17]) * 16 + int64_t(tr[1]) * cr[0] * 2 * csz + int64_t(tr[1]) * 16;
-    P.b_lds_dw = std::max(P.b_lds_dw, lds);
   }
   P.alg_flops_per_site = alg;
   P.exec_flops_per_site = exec;
