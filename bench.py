@@ -108,6 +108,28 @@ def cpu_baseline(wl, Su, Sd, nnz, budget_s=15.0):
             "sample": f"oracle forward + gradients over the first {done} sites of this workload ({dt:.1f} s)"}
 
 
+KERNEL_PREFIX = {"fwd": "fwd_kernel", "dS": "ds_kernel", "dW": "dw_kernel"}
+
+
+def profiled_traffic(workload, kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    profile of this workload, or None when there is none or the kernel sources
+    changed since it was taken."""
+    from paper_2201_04269_amd.build import source_hash
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    if f"source_hash {source_hash()}" not in lines:
+        return None
+    want = KERNEL_PREFIX[kernel] + ("<float" if prec == "f32c" else "<double")
+    for ln in lines:
+        parts = ln.split()  # traffic <kernel> <dispatches> <fetch B> <write B> <total B>
+        if len(parts) == 6 and parts[0] == "traffic" and parts[1].startswith(want):
+            return float(parts[-1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,7 +254,8 @@ def main():
         "config": {"workload": wl["desc"], "pass": "fwd+bwd" if do_bwd else "fwd", "sites": n_sites,
                    "nnz": nnz, "index_entries_per_step": entries},
         "roofline": {"bound": "alu", "kernel": r["dominant"], "achieved": dk["alg_tflops"],
-                     "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": dk["frac"], "traffic": None},
+                     "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": dk["frac"],
+                     "traffic": profiled_traffic(wl["name"], r["dominant"], head)},
         "kernels": r["kernels"],
         "fwd_only_value": r["fwd_value"],
     }

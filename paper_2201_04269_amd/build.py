@@ -23,6 +23,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
+def source_hash():
+    """SHA-256 (first 16 hex digits) of the sources the device code is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + ".tmp"
