@@ -192,15 +192,12 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
     // dispatch on the tile's number of sink keys (uniform; written out so
     // that the accumulators stay in registers)
     if (nlive > 0) {
-      constexpr int N2 = BW < 2 ? BW : 2, N3 = BW < 3 ? BW : 3;
-      if (B == 1)
-        dw_products<1, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
-      else if (B == 2)
-        dw_products<N2, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
-      else if (B == 3)
-        dw_products<N3, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
-      else
-        dw_products<BW, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+#define MBC_DW_CASE(N)                                                            \
+  else if (B <= (N)) dw_products<((N) < BW ? (N) : BW), BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+      if (B <= 1) dw_products<1, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+      MBC_DW_CASE(2) MBC_DW_CASE(3) MBC_DW_CASE(4) MBC_DW_CASE(5) MBC_DW_CASE(6) MBC_DW_CASE(7)
+      else dw_products<BW, BW, MAXS>(sR, us, dsl, cu, cd, nlive, acc);
+#undef MBC_DW_CASE
     }
     if constexpr (!kOverlapLeaves) __syncthreads();
   }

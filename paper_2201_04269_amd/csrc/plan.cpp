@@ -501,13 +501,14 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.threads = 256;
   const int csz = precision == MBC_F64 ? 16 : 8;
   // local-memory budgets per workgroup (forward; backward dS kernel), sized
-  // to the workgroups per CU that the kernels' registers allow: two share a
-  // CU's 160 KiB (three for the FP32 forward of the small families); the
-  // (5,4) family's dS kernels, and its FP64 forward, run one workgroup per
-  // CU, so their tiles may take nearly all of it (fewer, larger tiles)
+  // to the workgroups per CU that the kernels' registers allow (measured
+  // best on the D_I bench workload): two share a CU's 160 KiB, four for the
+  // FP32 forward of the small families; the (5,4) family's dS kernels, and
+  // its FP64 forward, run one workgroup per CU, so their tiles may take
+  // nearly all of it (fewer, larger tiles)
   const bool big = s.n_u + s.n_d >= 8;
-  const int64_t budget = big ? (precision == MBC_F64 ? 150 : 76) * 1024 : (precision == MBC_F64 ? 76 : 52) * 1024;
-  const int64_t bbudget = big ? 150 * 1024 : (precision == MBC_F64 ? 76 : 64) * 1024;
+  const int64_t budget = big ? (precision == MBC_F64 ? 150 : 76) * 1024 : (precision == MBC_F64 ? 76 : 38) * 1024;
+  const int64_t bbudget = big ? 150 * 1024 : (precision == MBC_F64 ? 76 : 78) * 1024;
   const int kMaxB = 16;
   const LdsModel fwd_model{false, csz}, bwd_model{true, csz}, dw_model{false, csz, false};
   const int dw_keys = dw_keys_per_tile(s.n_u, s.n_d, precision);
