@@ -15,6 +15,8 @@ Workloads (synthetic inputs, the paper's propagators are not available):
   di_8       D_I, 8^3 x 16 sites, SU(3) x spin propagators (seed 1)
   he3        3He_I^j and 3He_II^j (R2), j = 0..3, 8 correlators in one launch,
              32^3 x 64 sites, i.i.d. (seed 4)  [large: ~10 GB of propagators]
+  he3_shard  the same operators on one GPU's share of that lattice when it is
+             split by timeslice over 8 GPUs: 32^3 x 8 sites (i.i.d., seed 4)
 
 Prints one JSON line (rank 0).  `value` is index entries contracted per
 second, sum over correlators of |I_c| times the number of sites, divided by
@@ -53,6 +55,12 @@ def workload(name):
               [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2") for j in range(4)]
         gen = lambda: synth.iid(T, L ** 3, seed=4)  # noqa: E731
         desc = "3He_I^j + 3He_II^j (R2), j=0..3, 32^3x64, iid seed 4"
+    elif name == "he3_shard":
+        L, T = 32, 8
+        ops = [dict(op="HE3_I", snk_spin=j, src_spin=j) for j in range(4)] + \
+              [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2") for j in range(4)]
+        gen = lambda: synth.iid(T, L ** 3, seed=4)  # noqa: E731
+        desc = "3He_I^j + 3He_II^j (R2), j=0..3, 32^3x8 (one timeslice shard of 32^3x64), iid seed 4"
     else:
         raise SystemExit(f"unknown workload {name}")
     return dict(name=name, L=L, T=T, ops=ops, gen=gen, desc=desc)
@@ -179,50 +187,58 @@ def main():
     gC = torch.from_numpy(rng.standard_normal((n_corr, T)) + 1j * rng.standard_normal((n_corr, T))).to(dev)
     do_bwd = not args.fwd_only
 
-    def timed(fn, n):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(n):
-            fn()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / n
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
 
     results = {}
     for prec in args.precisions.split(","):
         t0 = time.perf_counter()
         plan = api.Plan(iset, prec)
         st = plan.stats
-        print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']} lds={st['lds_bytes']}/"
+        print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']}/{st['w_n_tiles']} lds={st['lds_bytes']}/"
               f"{st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} alg fwd={st['alg_flops_per_site']:.3e} "
               f"dS={st['ds_alg_flops_per_site']:.3e} dW={st['dw_alg_flops_per_site']:.3e} "
               f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
 
-        def fwd():
-            return api.contract(plan, su, sd, W)
-
-        def bwd_s():
-            return api.contract_backward(plan, su, sd, W, gC, need_W=False, need_S=True)
-
-        def bwd_w():
-            return api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=False)
-
-        def step():
-            fwd()
+        # one step: forward, then the backward as its two launches (dW, then
+        # dS: the work of one contract_backward with both gradients), with
+        # HIP events on the launch stream between them
+        def step(marks=None):
+            if marks:
+                marks[0].record(stream)
+            api.contract(plan, su, sd, W)
+            if marks:
+                marks[1].record(stream)
             if do_bwd:
-                api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=True)
+                api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=False)
+                if marks:
+                    marks[2].record(stream)
+                api.contract_backward(plan, su, sd, W, gC, need_W=False, need_S=True)
+                if marks:
+                    marks[3].record(stream)
 
-        for _ in range(args.warmup):
+        for i in range(args.warmup):
             step()
+            torch.cuda.synchronize()
+            print(f"[bench] {prec}: warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        marks = [[ev() for _ in range(4)] for _ in range(args.steps)]
+        first, last = ev(), ev()
+        torch.cuda.synchronize()
         t_wall = time.perf_counter()
-        ms = timed(step, args.steps)
+        first.record(stream)
+        for i in range(args.steps):
+            step(marks[i])
+            if args.steps > 1 and n_sites * nnz > 1e13:  # long steps: report progress
+                torch.cuda.synchronize()
+                print(f"[bench] {prec}: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        last.record(stream)
+        torch.cuda.synchronize()
         wall = (time.perf_counter() - t_wall) / args.steps
-        kern = {"fwd": (timed(fwd, args.steps), st["alg_flops_per_site"])}
+        ms = first.elapsed_time(last) / args.steps
+        kern = {"fwd": (sum(m[0].elapsed_time(m[1]) for m in marks) / args.steps, st["alg_flops_per_site"])}
         if do_bwd:
-            kern["dS"] = (timed(bwd_s, args.steps), st["ds_alg_flops_per_site"])
-            kern["dW"] = (timed(bwd_w, args.steps), st["dw_alg_flops_per_site"])
+            kern["dW"] = (sum(m[1].elapsed_time(m[2]) for m in marks) / args.steps, st["dw_alg_flops_per_site"])
+            kern["dS"] = (sum(m[2].elapsed_time(m[3]) for m in marks) / args.steps, st["ds_alg_flops_per_site"])
         dom = max(kern, key=lambda k: kern[k][0])
         r = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall, value=entries / (ms * 1e-3), dominant=dom,
                  kernels={k: {"ms": v[0], "alg_tflops": v[1] * n_sites / (v[0] * 1e-3) / 1e12,
