@@ -13,7 +13,8 @@
 namespace mbc {
 namespace dev {
 
-constexpr int kNT = 256;  // threads per workgroup
+// Workgroup sizes are template parameters (NT, a multiple of 64) of the
+// kernels and of every helper that maps work onto the workgroup's lanes.
 
 // Next 16-byte boundary of an LDS pointer, computed as an offset from the
 // dynamic LDS base: the result stays an LDS pointer for the compiler, which a
@@ -25,19 +26,19 @@ __device__ __forceinline__ T* lds_align16(unsigned char* base, const void* p) {
   return reinterpret_cast<T*>(base + ((off + 15u) & ~15u));
 }
 
-// Copies n elements from global memory into LDS with all threads of the
+// Copies n elements from global memory into LDS with all NT threads of the
 // workgroup, four loads in flight per thread before the stores.
-template <typename T>
+template <int NT, typename T>
 __device__ __forceinline__ void stage_lds(T* dst, const T* __restrict__ src, int n) {
   int i = threadIdx.x;
-  for (; i + 3 * kNT < n; i += 4 * kNT) {
-    const T v0 = src[i], v1 = src[i + kNT], v2 = src[i + 2 * kNT], v3 = src[i + 3 * kNT];
+  for (; i + 3 * NT < n; i += 4 * NT) {
+    const T v0 = src[i], v1 = src[i + NT], v2 = src[i + 2 * NT], v3 = src[i + 3 * NT];
     dst[i] = v0;
-    dst[i + kNT] = v1;
-    dst[i + 2 * kNT] = v2;
-    dst[i + 3 * kNT] = v3;
+    dst[i + NT] = v1;
+    dst[i + 2 * NT] = v2;
+    dst[i + 3 * NT] = v3;
   }
-  for (; i < n; i += kNT) dst[i] = src[i];
+  for (; i < n; i += NT) dst[i] = src[i];
 }
 
 template <typename R>
@@ -160,6 +161,24 @@ __device__ __forceinline__ C load_site(const void* base, int c64, int64_t idx) {
   return r;
 }
 
+// Propagators of one site: thread i < 288 holds entry i of the 288 (the u
+// block, then the d block); with NT < 288, threads i < 288 - NT also hold
+// entry NT + i.
+template <int NT, typename C>
+__device__ __forceinline__ void fetch_site(const void* S_u, const void* S_d, int c64, int64_t site, C* pre) {
+  const int i = threadIdx.x;
+  if (NT <= 288 || i < 288) pre[0] = load_site<C>(i < 144 ? S_u : S_d, c64, site * 144 + (i % 144));
+  if constexpr (NT < 288)
+    if (i < 288 - NT) pre[1] = load_site<C>(S_d, c64, site * 144 + (NT + i - 144));
+}
+template <int NT, typename C>
+__device__ __forceinline__ void store_site(C* dst, const C* pre) {
+  const int i = threadIdx.x;
+  if (NT <= 288 || i < 288) dst[i] = pre[0];
+  if constexpr (NT < 288)
+    if (i < 288 - NT) dst[NT + i] = pre[1];
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block id mod 8).  Map
 // them so that each XCD receives a contiguous range of logical ids, which
 // keeps all tiles of a chunk of sites (same propagators) in one L2.
@@ -174,7 +193,7 @@ __device__ __forceinline__ int xcd_linear(int bid, int nb) {
 // workgroup runs G = NT / ncol row ops of the level side by side (thread t
 // takes column t % ncol of op group t / ncol); otherwise each thread takes
 // columns t, t + NT, ... of one op at a time.
-template <int K, int QMAX>
+template <int K, int QMAX, int NT>
 struct LevelTab {
   int ncol = 0, G = 1, g = 0, i0 = 0;
   int e[QMAX][K > 0 ? K : 1];
@@ -183,8 +202,8 @@ struct LevelTab {
   __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs, int t) {
     ncol = cr[8 + 2 * (6 * f + K - 1)];
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
-    if (ncol > 0 && ncol <= kNT) {
-      G = kNT / ncol;
+    if (ncol > 0 && ncol <= NT) {
+      G = NT / ncol;
       g = t / ncol;
       i0 = t % ncol;
     } else {
@@ -194,7 +213,7 @@ struct LevelTab {
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int i = i0 + q * kNT;
+      const int i = i0 + q * NT;
 #pragma unroll
       for (int j = 0; j < K; ++j) e[q][j] = (i < ncol && g < G) ? int(tabs[toff + i * (K == 1 ? 1 : K) + (K == 1 ? 0 : j)]) : 0;
     }
@@ -219,8 +238,8 @@ __device__ __forceinline__ C minor_entry(const int* e, const C* srow, const C* i
 
 // One (flavour, level) phase: rows of the tile's ops [o0, o0 + nops).
 // Two ops are processed per trip so that their LDS loads overlap.
-template <int K, int QMAX, typename C>
-__device__ __forceinline__ void level_phase(const LevelTab<K, QMAX>& tb, const int4* sOps, int o0, int nops,
+template <int K, int QMAX, int NT, typename C>
+__device__ __forceinline__ void level_phase(const LevelTab<K, QMAX, NT>& tb, const int4* sOps, int o0, int nops,
                                             const C* Sf, C* sR) {
   if (tb.g >= tb.G) return;
   for (int jb = tb.g; jb < nops; jb += 2 * tb.G) {
@@ -233,7 +252,7 @@ __device__ __forceinline__ void level_phase(const LevelTab<K, QMAX>& tb, const i
     const C* ib = (K == 2) ? (Sf + 12 * opb.y) : (sR + opb.y);
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int i = tb.i0 + q * kNT;
+      const int i = tb.i0 + q * NT;
       if (i < tb.ncol) {
         const C va = minor_entry<K>(tb.e[q], sa, ia);
         const C vb = minor_entry<K>(tb.e[q], sb, ib);
@@ -244,14 +263,14 @@ __device__ __forceinline__ void level_phase(const LevelTab<K, QMAX>& tb, const i
   }
 }
 
-template <int NF, int QMAX>
+template <int NF, int QMAX, int NT>
 struct FlavTabs {
-  LevelTab<1, QMAX> l1;
-  LevelTab<2, QMAX> l2;
-  LevelTab<3, QMAX> l3;
-  LevelTab<4, QMAX> l4;
-  LevelTab<5, QMAX> l5;
-  LevelTab<6, QMAX> l6;
+  LevelTab<1, QMAX, NT> l1;
+  LevelTab<2, QMAX, NT> l2;
+  LevelTab<3, QMAX, NT> l3;
+  LevelTab<4, QMAX, NT> l4;
+  LevelTab<5, QMAX, NT> l5;
+  LevelTab<6, QMAX, NT> l6;
   __device__ __forceinline__ void load(const int32_t* cr, int f, const uint16_t* __restrict__ tabs,
                                        int t = threadIdx.x) {
     if constexpr (NF == 1) l1.load(cr, f, tabs, t);
@@ -263,8 +282,8 @@ struct FlavTabs {
   }
 };
 
-template <int K, int NF, int QMAX, typename C>
-__device__ __forceinline__ void run_level(const FlavTabs<NF, QMAX>& ft, const int32_t* tr, int f,
+template <int K, int NF, int QMAX, int NT, typename C>
+__device__ __forceinline__ void run_level(const FlavTabs<NF, QMAX, NT>& ft, const int32_t* tr, int f,
                                           const int4* sOps, const C* Sf, C* sR) {
   const int o0 = tr[20 + 2 * (7 * f + K)], n = tr[21 + 2 * (7 * f + K)];
   if constexpr (K == 1) level_phase<1>(ft.l1, sOps, o0, n, Sf, sR);

@@ -53,21 +53,18 @@ struct FwdArgs {
 // All levels of one site, one barrier after each level.  During the top
 // level the next site's propagators (prefetched in registers) are stored in
 // the other S buffer.
-template <int K, int KMAX, int NU, int ND, int QMAX, typename C>
-__device__ __forceinline__ void site_levels(const FlavTabs<NU, QMAX>& tu, const FlavTabs<ND, QMAX>& td,
+template <int K, int KMAX, int NU, int ND, int QMAX, int NT, typename C>
+__device__ __forceinline__ void site_levels(const FlavTabs<NU, QMAX, NT>& tu, const FlavTabs<ND, QMAX, NT>& td,
                                             const int32_t* tr, const int4* sOps, const C* sS, C* sR,
                                             C* sSnext, const C* pre, bool have_next) {
   if constexpr (K <= KMAX) {
     if constexpr (K <= NU && (K >= 2 || NU == 1)) run_level<K>(tu, tr, 0, sOps, sS, sR);
     if constexpr (K <= ND && (K >= 2 || ND == 1)) run_level<K>(td, tr, 1, sOps, sS + 144, sR);
     if constexpr (K == KMAX) {
-      if (have_next) {
-        sSnext[threadIdx.x] = pre[0];
-        if (threadIdx.x < 288 - kNT) sSnext[kNT + threadIdx.x] = pre[1];
-      }
+      if (have_next) store_site<NT>(sSnext, pre);
     }
     __syncthreads();
-    site_levels<K + 1, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSnext, pre, have_next);
+    site_levels<K + 1, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR, sSnext, pre, have_next);
   }
 }
 
@@ -117,8 +114,8 @@ __device__ __forceinline__ void leaf_dispatch(int nlive, int B, const int4* meta
   }
 }
 
-template <typename R, int NU, int ND, int MAXS, int QMAX>
-__global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
+template <typename R, int NU, int ND, int MAXS, int QMAX, int NT>
+__global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
   constexpr int KMAX = NU > ND ? NU : ND;
@@ -142,15 +139,15 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   int4* sOps = lds_align16<int4>(smem, sR + row_units);
   int4* meta = sOps + nops;  // (u slot, d slot, run end, key) of each sink key
 
-  for (int i = tid; i < nops; i += kNT) {
+  for (int i = tid; i < nops; i += NT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
-  stage_lds(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+  stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
   if (tid < B) meta[tid] = reinterpret_cast<const int4*>(a.meta)[meta0 + tid];
 
-  FlavTabs<NU, QMAX> tu;
-  FlavTabs<ND, QMAX> td;
+  FlavTabs<NU, QMAX, NT> tu;
+  FlavTabs<ND, QMAX, NT> td;
   tu.load(cr, 0, a.tabs);
   td.load(cr, 1, a.tabs);
 
@@ -160,14 +157,14 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
-    const int s = tid + kNT * m;
+    const int s = tid + NT * m;
     live[m] = s < n_src;
     sl[m] = live[m] ? s : n_src - 1;
     cu[m] = a.src_cu[src_off + sl[m]];
     cd[m] = a.src_cd[src_off + sl[m]];
   }
   const int wave0 = tid & ~63;
-  const int nlive = (n_src - wave0 + kNT - 1) / kNT;  // > 0 unless the wave has no key
+  const int nlive = (n_src - wave0 + NT - 1) / NT;  // > 0 unless the wave has no key
 
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;
@@ -175,15 +172,9 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   CompAcc<R> acc;
 
   // propagators of site v: thread i holds entries i and i + NT (< 288)
-  auto fetch = [&](int64_t v, C* pre) {
-    const int64_t site = int64_t(t) * a.V + v;
-    pre[0] = load_site<C>(tid < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (tid % 144));
-    if (tid < 288 - kNT) pre[1] = load_site<C>(a.S_d, a.s_c64, site * 144 + (kNT + tid - 144));
-  };
   C pre[2];
-  fetch(v0, pre);
-  sS0[tid] = pre[0];
-  if (tid < 288 - kNT) sS0[kNT + tid] = pre[1];
+  fetch_site<NT>(a.S_u, a.S_d, a.s_c64, int64_t(t) * a.V + v0, pre);
+  store_site<NT>(sS0, pre);
   __syncthreads();
 
   for (int64_t v = v0; v < v1; ++v) {
@@ -191,8 +182,8 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
     C* sS = sS0 + 288 * buf;
     C* sSn = sS0 + 288 * (buf ^ 1);
     const bool have_next = v + 1 < v1;
-    if (have_next) fetch(v + 1, pre);
-    site_levels<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
+    if (have_next) fetch_site<NT>(a.S_u, a.S_d, a.s_c64, int64_t(t) * a.V + v + 1, pre);
+    site_levels<KMIN, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
     leaf_dispatch<1, MAXS>(nlive, B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
     if constexpr (!kOverlapLeaves) __syncthreads();
   }
@@ -214,7 +205,7 @@ __global__ __launch_bounds__(kNT) void fwd_kernel(FwdArgs a) {
   __syncthreads();
   if (tid == 0) {
     double sx = 0, sy = 0;
-    for (int w = 0; w < kNT / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       sx += red[2 * w];
       sy += red[2 * w + 1];
     }
@@ -270,23 +261,25 @@ __global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__
 }
 
 template <typename R, int NU, int ND, int MAXS, int QMAX>
-hipError_t launch_fwd_t(const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
-  auto k = fwd_kernel<R, NU, ND, MAXS, QMAX>;
+hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  constexpr int NT = family_threads(NU, ND);
+  if ((p->h.max_src + NT - 1) / NT > MAXS || (p->h.max_ncol + NT - 1) / NT > QMAX) return hipErrorNotSupported;
+  auto k = fwd_kernel<R, NU, ND, MAXS, QMAX, NT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(nblocks), dim3(kNT), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(nblocks), dim3(NT), lds, st, a);
   return hipGetLastError();
 }
 
 // Instantiated shapes: proton (2,1), neutron (1,2), dinucleon (3,3), 3He (5,4).
 template <typename R>
 hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
-  const int nu = p->h.n_u, nd = p->h.n_d, ms = p->h.maxs, qm = p->h.qmax;
-  if (nu == 2 && nd == 1 && ms <= 1 && qm <= 1) return launch_fwd_t<R, 2, 1, 1, 1>(a, nblocks, lds, st);
-  if (nu == 1 && nd == 2 && ms <= 1 && qm <= 1) return launch_fwd_t<R, 1, 2, 1, 1>(a, nblocks, lds, st);
-  if (nu == 3 && nd == 3 && ms <= 4 && qm <= 1) return launch_fwd_t<R, 3, 3, 4, 1>(a, nblocks, lds, st);
-  if (nu == 5 && nd == 4 && ms <= 8 && qm <= 2) return launch_fwd_t<R, 5, 4, 8, 2>(a, nblocks, lds, st);
+  const int nu = p->h.n_u, nd = p->h.n_d;
+  if (nu == 2 && nd == 1) return launch_fwd_t<R, 2, 1, 1, 1>(p, a, nblocks, lds, st);
+  if (nu == 1 && nd == 2) return launch_fwd_t<R, 1, 2, 1, 1>(p, a, nblocks, lds, st);
+  if (nu == 3 && nd == 3) return launch_fwd_t<R, 3, 3, 4, 1>(p, a, nblocks, lds, st);
+  if (nu == 5 && nd == 4) return launch_fwd_t<R, 5, 4, 4, 1>(p, a, nblocks, lds, st);
   return hipErrorNotSupported;
 }
 

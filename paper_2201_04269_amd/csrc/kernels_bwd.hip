@@ -63,33 +63,30 @@ __device__ __forceinline__ C cconj(C a) {
 }
 
 // Rows of one site for one tile (no propagator prefetch): one barrier per level.
-template <int K, int KMAX, int NU, int ND, int QMAX, typename C>
-__device__ __forceinline__ void tile_levels(const FlavTabs<NU, QMAX>& tu, const FlavTabs<ND, QMAX>& td,
+template <int K, int KMAX, int NU, int ND, int QMAX, int NT, typename C>
+__device__ __forceinline__ void tile_levels(const FlavTabs<NU, QMAX, NT>& tu, const FlavTabs<ND, QMAX, NT>& td,
                                             const int32_t* tr, const int4* sOps, const C* sS, C* sR) {
   if constexpr (K <= KMAX) {
     if constexpr (K <= NU && (K >= 2 || NU == 1)) run_level<K>(tu, tr, 0, sOps, sS, sR);
     if constexpr (K <= ND && (K >= 2 || ND == 1)) run_level<K>(td, tr, 1, sOps, sS + 144, sR);
     __syncthreads();
-    tile_levels<K + 1, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR);
+    tile_levels<K + 1, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR);
   }
 }
 
 // Same with the next site's propagators stored during the top level.
-template <int K, int KMAX, int NU, int ND, int QMAX, typename C>
-__device__ __forceinline__ void site_levels_pf(const FlavTabs<NU, QMAX>& tu, const FlavTabs<ND, QMAX>& td,
+template <int K, int KMAX, int NU, int ND, int QMAX, int NT, typename C>
+__device__ __forceinline__ void site_levels_pf(const FlavTabs<NU, QMAX, NT>& tu, const FlavTabs<ND, QMAX, NT>& td,
                                                const int32_t* tr, const int4* sOps, const C* sS, C* sR, C* sSnext,
                                                const C* pre, bool have_next) {
   if constexpr (K <= KMAX) {
     if constexpr (K <= NU && (K >= 2 || NU == 1)) run_level<K>(tu, tr, 0, sOps, sS, sR);
     if constexpr (K <= ND && (K >= 2 || ND == 1)) run_level<K>(td, tr, 1, sOps, sS + 144, sR);
     if constexpr (K == KMAX) {
-      if (have_next) {
-        sSnext[threadIdx.x] = pre[0];
-        if (threadIdx.x < 288 - kNT) sSnext[kNT + threadIdx.x] = pre[1];
-      }
+      if (have_next) store_site<NT>(sSnext, pre);
     }
     __syncthreads();
-    site_levels_pf<K + 1, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSnext, pre, have_next);
+    site_levels_pf<K + 1, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR, sSnext, pre, have_next);
   }
 }
 
@@ -121,8 +118,8 @@ __device__ __forceinline__ void dw_products(const C* sR, const int (&us)[BW], co
 // (sink key, source key) product of the tile is added to its compensated
 // accumulator, held in registers across the chunk; the chunk's sums,
 // times grad_C, go to partial[t * nc + chunk][entry].
-template <typename R, int NU, int ND, int MAXS, int QMAX, int BW>
-__global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
+template <typename R, int NU, int ND, int MAXS, int QMAX, int BW, int NT>
+__global__ __launch_bounds__(NT) void dw_kernel(BwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
   constexpr int KMAX = NU > ND ? NU : ND;
@@ -141,7 +138,7 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
   C* sS0 = reinterpret_cast<C*>(smem);
   C* sR = sS0 + 576;
   int4* sOps = lds_align16<int4>(smem, sR + row_units);
-  for (int i = tid; i < nops; i += kNT) {
+  for (int i = tid; i < nops; i += NT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
@@ -152,43 +149,37 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
     us[b] = mb.x;
     dsl[b] = mb.y;
   }
-  FlavTabs<NU, QMAX> tu;
-  FlavTabs<ND, QMAX> td;
+  FlavTabs<NU, QMAX, NT> tu;
+  FlavTabs<ND, QMAX, NT> td;
   tu.load(cr, 0, a.tabs);
   td.load(cr, 1, a.tabs);
   int cu[MAXS], cd[MAXS];
   bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
-    const int s = tid + kNT * m;
+    const int s = tid + NT * m;
     live[m] = s < n_src;
     const int sl = live[m] ? s : n_src - 1;
     cu[m] = a.src_cu[src_off + sl];
     cd[m] = a.src_cd[src_off + sl];
   }
-  const int nlive = (n_src - (tid & ~63) + kNT - 1) / kNT;  // slots the wave runs
+  const int nlive = (n_src - (tid & ~63) + NT - 1) / NT;  // slots the wave runs
   CompAcc<R> acc[BW][MAXS];
 
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;
   const int64_t v1 = (v0 + a.chunk < a.V) ? v0 + a.chunk : a.V;
-  auto fetch = [&](int64_t v, C* pre) {
-    const int64_t site = int64_t(t) * a.V + v;
-    pre[0] = load_site<C>(tid < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (tid % 144));
-    if (tid < 288 - kNT) pre[1] = load_site<C>(a.S_d, a.s_c64, site * 144 + (kNT + tid - 144));
-  };
   C pre[2];
-  fetch(v0, pre);
-  sS0[tid] = pre[0];
-  if (tid < 288 - kNT) sS0[kNT + tid] = pre[1];
+  fetch_site<NT>(a.S_u, a.S_d, a.s_c64, int64_t(t) * a.V + v0, pre);
+  store_site<NT>(sS0, pre);
   __syncthreads();
   for (int64_t v = v0; v < v1; ++v) {
     const int buf = int((v - v0) & 1);
     C* sS = sS0 + 288 * buf;
     C* sSn = sS0 + 288 * (buf ^ 1);
     const bool have_next = v + 1 < v1;
-    if (have_next) fetch(v + 1, pre);
-    site_levels_pf<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
+    if (have_next) fetch_site<NT>(a.S_u, a.S_d, a.s_c64, int64_t(t) * a.V + v + 1, pre);
+    site_levels_pf<KMIN, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
     // dispatch on the tile's number of sink keys (uniform; written out so
     // that the accumulators stay in registers)
     if (nlive > 0) {
@@ -208,7 +199,7 @@ __global__ __launch_bounds__(kNT) void dw_kernel(BwdArgs a) {
 #pragma unroll
     for (int m = 0; m < MAXS; ++m) {
       if (b < B && live[m]) {
-        const int i = b * n_src + tid + kNT * m;
+        const int i = b * n_src + tid + NT * m;
         const double qx = double(acc[b][m].hx) + double(acc[b][m].lx);
         const double qy = -(double(acc[b][m].hy) + double(acc[b][m].ly));  // conj(Q)
         out[2 * i] = gx * qx - gy * qy;
@@ -245,7 +236,7 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const double* __restrict
 __host__ __device__ constexpr int bin_regs(int k) { return k == 1 ? 1 : (k == 2 ? 11 : (k == 3 ? 4 : (k == 4 ? 11 : 14))); }
 __host__ __device__ constexpr int bin_lanes(int k) { return k <= 2 ? 1 : 16; }
 
-template <int K>
+template <int K, int NT>
 struct BinTab {
   int e[bin_regs(K)];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab, int t) {
@@ -256,12 +247,12 @@ struct BinTab {
     const int32_t* jl = btab + cr[40 + 6 * f + K - 1];
     int j, l;
     if constexpr (K <= 2) {
-      if (t >= 252) return;
+      if (t >= 12 * (NT / 12)) return;
       j = t % 12;
       l = 0;
     } else {
-      if (t >= 192) return;
-      j = t >> 4;
+      if (t >= 192 * (NT / 192)) return;
+      j = (t % 192) >> 4;
       l = t & 15;
     }
     const int q0 = jl[j], q1 = jl[j + 1];
@@ -282,7 +273,7 @@ struct BinTab {
 // int32.
 __host__ __device__ constexpr int up_len(int k) { return 12 - k; }
 
-template <int K, int QMAX>
+template <int K, int QMAX, int NT>
 struct UpTab {
   int ncol = 0, G = 1, g = 0, i0 = 0;
   unsigned up[QMAX][6];
@@ -293,8 +284,8 @@ struct UpTab {
     const unsigned pad = unsigned(cr[8 + 2 * (6 * f + K)]) & 2047u;  // ncol one level up
     const int32_t* ut = btab + cr[67 + 6 * f + K - 1];
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
-    if (ncol > 0 && ncol <= kNT) {
-      G = kNT / ncol;
+    if (ncol > 0 && ncol <= NT) {
+      G = NT / ncol;
       g = t / ncol;
       i0 = t % ncol;
     } else {
@@ -304,7 +295,7 @@ struct UpTab {
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = i0 + kNT * q;
+      const int c = i0 + NT * q;
       const bool ok = c < ncol && g < G;
       int cnt = 0;
 #pragma unroll
@@ -333,7 +324,7 @@ struct UpTab {
 // keys of each (s | other-flavour column << 11).
 // Unused slots pair source key 0 with the zero element of the other
 // flavour's top row; nw[q] is the largest list length in the wave.
-template <int QMAX, int MC>
+template <int QMAX, int MC, int NT>
 struct CsrTab {
   int ncol = 0;
   int nw[QMAX];
@@ -347,7 +338,7 @@ struct CsrTab {
     const int src_off = cr[1];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = t + kNT * q;
+      const int c = t + NT * q;
       int n = 0, q0 = 0;
       if (c < ncol) {
         q0 = lists[c];
@@ -410,17 +401,17 @@ __device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi
   }
 }
 
-template <int NF, int QMAX>
+template <int NF, int QMAX, int NT>
 struct RevTabs {
-  BinTab<1> b1;
-  BinTab<2> b2;
-  BinTab<3> b3;
-  BinTab<4> b4;
-  BinTab<5> b5;
-  UpTab<1, QMAX> u1;
-  UpTab<2, QMAX> u2;
-  UpTab<3, QMAX> u3;
-  UpTab<4, QMAX> u4;
+  BinTab<1, NT> b1;
+  BinTab<2, NT> b2;
+  BinTab<3, NT> b3;
+  BinTab<4, NT> b4;
+  BinTab<5, NT> b5;
+  UpTab<1, QMAX, NT> u1;
+  UpTab<2, QMAX, NT> u2;
+  UpTab<3, QMAX, NT> u3;
+  UpTab<4, QMAX, NT> u4;
   int tb = 0;  // lane order of the S-bar bins; the parent tables take their own
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* btab, const uint16_t* tabs,
                                        int t_bins, int t_ups) {
@@ -437,24 +428,24 @@ struct RevTabs {
   }
 };
 
-template <int K, int NF, int QMAX>
-__device__ __forceinline__ const BinTab<K>& bins_of(const RevTabs<NF, QMAX>& rt) {
+template <int K, int NF, int QMAX, int NT>
+__device__ __forceinline__ const BinTab<K, NT>& bins_of(const RevTabs<NF, QMAX, NT>& rt) {
   if constexpr (K == 1) return rt.b1;
   else if constexpr (K == 2) return rt.b2;
   else if constexpr (K == 3) return rt.b3;
   else if constexpr (K == 4) return rt.b4;
   else return rt.b5;
 }
-template <int K, int NF, int QMAX>
-__device__ __forceinline__ const UpTab<K, QMAX>& ups_of(const RevTabs<NF, QMAX>& rt) {
+template <int K, int NF, int QMAX, int NT>
+__device__ __forceinline__ const UpTab<K, QMAX, NT>& ups_of(const RevTabs<NF, QMAX, NT>& rt) {
   if constexpr (K == 1) return rt.u1;
   else if constexpr (K == 2) return rt.u2;
   else if constexpr (K == 3) return rt.u3;
   else return rt.u4;
 }
 
-template <int K, typename C>
-__device__ __forceinline__ C bin_sum(const BinTab<K>& bt, int4 ov, const C* Sf, const C* sR, const C* sA) {
+template <int K, int NT, typename C>
+__device__ __forceinline__ C bin_sum(const BinTab<K, NT>& bt, int4 ov, const C* Sf, const C* sR, const C* sA) {
   C sum = cmake<C>(0, 0);
 #pragma unroll
   for (int m = 0; m < bin_regs(K); ++m) {
@@ -474,16 +465,21 @@ __device__ __forceinline__ C bin_sum(const BinTab<K>& bt, int4 ov, const C* Sf, 
 
 // (ii) S-bar partials of the level-K rows [o0, o0 + cnt) of one flavour:
 // part[o][j] = sum over columns C containing j of (-1)^pos A(C) M_{K-1}(C \ j).
-template <int K, typename C>
-__device__ __forceinline__ void rev_part(const BinTab<K>& bt, int tid, int o0, int cnt, const int4* sOpv,
+// Levels K <= 2: NT / 12 rows side by side, one lane per bin.  K >= 3:
+// NT / 192 groups of 12 bins x 16 lanes, each taking two rows per trip.
+template <int K, int NT, typename C>
+__device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o0, int cnt, const int4* sOpv,
                                          const C* Sf, const C* sR, const C* sA, C* sPart) {
   if constexpr (K <= 2) {
-    if (tid >= 252) return;
+    constexpr int RB = NT / 12;
+    if (tid >= 12 * RB) return;
     const int j = tid % 12;
-    for (int o = o0 + tid / 12; o < o0 + cnt; o += 21) sPart[12 * o + j] = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
+    for (int o = o0 + tid / 12; o < o0 + cnt; o += RB) sPart[12 * o + j] = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
   } else {
-    if (tid >= 192) return;
-    for (int o = o0; o < o0 + cnt; o += 2) {
+    constexpr int NG = NT / 192;
+    if (tid >= 192 * NG) return;
+    const int lt = tid % 192;
+    for (int o = o0 + 2 * (tid / 192); o < o0 + cnt; o += 2 * NG) {
       const bool two = o + 1 < o0 + cnt;
       C s0 = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
       C s1 = two ? bin_sum<K>(bt, sOpv[o + 1], Sf, sR, sA) : cmake<C>(0, 0);
@@ -491,9 +487,9 @@ __device__ __forceinline__ void rev_part(const BinTab<K>& bt, int tid, int o0, i
       s0.y = row16_sum(s0.y);
       s1.x = row16_sum(s1.x);
       s1.y = row16_sum(s1.y);
-      if ((tid & 15) == 0) {
-        sPart[12 * o + (tid >> 4)] = s0;
-        if (two) sPart[12 * (o + 1) + (tid >> 4)] = s1;
+      if ((lt & 15) == 0) {
+        sPart[12 * o + (lt >> 4)] = s0;
+        if (two) sPart[12 * (o + 1) + (lt >> 4)] = s1;
       }
     }
   }
@@ -519,8 +515,8 @@ __device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int4 ox, const 
 
 // (i) adjoints of the parents of level K-1 (real rows; S rows for K = 2):
 // A_{K-1}(C') = sum over children, over j not in C', of (-1)^pos S[r0, j] A_K(C' + j).
-template <int K, int QMAX, typename C>
-__device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX>& ut, int p0, int pcnt, const int4* sOpx,
+template <int K, int QMAX, int NT, typename C>
+__device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, int p0, int pcnt, const int4* sOpx,
                                             const int4* sOpv, const int32_t* children, const C* Sf, C* sA,
                                             C* sAdj1) {
   if (ut.g >= ut.G) return;
@@ -530,7 +526,7 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX>& ut, int p0
     const int4 ov = sOpv[p];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = ut.i0 + kNT * q;
+      const int c = ut.i0 + NT * q;
       if (c < ut.ncol) {
         const C sum = parent_sum<K - 1>(ut.up[q], ox, sOpv, children, Sf, sA);
         if (K == 2)
@@ -542,8 +538,8 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX>& ut, int p0
   }
 }
 
-template <int K, int NU, int ND, int QMAX, typename C>
-__device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX>& ru, const RevTabs<ND, QMAX>& rd,
+template <int K, int NU, int ND, int QMAX, int NT, typename C>
+__device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX, NT>& ru, const RevTabs<ND, QMAX, NT>& rd,
                                            const int32_t* tr, const int4* sOpx, const int4* sOpv,
                                            const int32_t* children, const C* sS, const C* sR, C* sA, C* sAdj1,
                                            C* sPart) {
@@ -566,12 +562,12 @@ __device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX>& ru, const Re
       }
     }
     __syncthreads();
-    rev_levels<K - 1, NU, ND, QMAX, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
+    rev_levels<K - 1, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
   }
 }
 
-template <typename R, int NU, int ND, int QMAX, int MC>
-__global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
+template <typename R, int NU, int ND, int QMAX, int MC, int NT>
+__global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
   constexpr int KMAX = NU > ND ? NU : ND;
@@ -580,7 +576,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   const int64_t site = blockIdx.x;
   const int t = int(site / a.V);
   C* sS = reinterpret_cast<C*>(smem);
-  for (int i = tid; i < 288; i += kNT)
+  for (int i = tid; i < 288; i += NT)
     sS[i] = load_site<C>(i < 144 ? a.S_u : a.S_d, a.s_c64, site * 144 + (i % 144));
 
   // Lane orders: the workgroup's lanes are rotated by a multiple of a wave
@@ -588,17 +584,18 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
   // SIMDs), and the u and d flavours and the parent tables start half a
   // workgroup / a quarter apart, so that small per-flavour tasks of one
   // level run on different waves side by side.
-  const int rot = int(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & 3) * 64;
-  const int vt = (tid + rot) & (kNT - 1);
-  const int vt_u = vt, vt_d = (vt + 128) & (kNT - 1);
-  const int vt_pu = (vt + 64) & (kNT - 1), vt_pd = (vt + 192) & (kNT - 1);
-  CompAcc<R> sb[2];  // S-bar entries vt and vt + NT (< 288)
+  constexpr int NQ = (288 + NT - 1) / NT;  // S-bar entries per thread
+  const int rot = int(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & (NT / 64 - 1)) * 64;
+  const int vt = (tid + rot) & (NT - 1);
+  const int vt_u = vt, vt_d = (vt + NT / 2) & (NT - 1);
+  const int vt_pu = (vt + NT / 4) & (NT - 1), vt_pd = (vt + 3 * NT / 4) & (NT - 1);
+  CompAcc<R> sb[NQ];  // S-bar entries vt + NT q (< 288)
   int cur_corr = -1;
-  FlavTabs<NU, QMAX> tu;
-  FlavTabs<ND, QMAX> td;
-  RevTabs<NU, QMAX> ru;
-  RevTabs<ND, QMAX> rd;
-  CsrTab<QMAX, MC> cu_tab, cd_tab;
+  FlavTabs<NU, QMAX, NT> tu;
+  FlavTabs<ND, QMAX, NT> td;
+  RevTabs<NU, QMAX, NT> ru;
+  RevTabs<ND, QMAX, NT> rd;
+  CsrTab<QMAX, MC, NT> cu_tab, cd_tab;
   const int4* meta_all = reinterpret_cast<const int4*>(a.meta);
 
   for (int tile = 0; tile < a.n_tiles; ++tile) {
@@ -630,12 +627,12 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
     int32_t* sEx = reinterpret_cast<int32_t*>(sOpv + nops);
     int2* sMeta = reinterpret_cast<int2*>(sEx + ((ex_len + 1) & ~1));  // (u slot, d slot) of each sink key
     __syncthreads();  // the previous tile's LDS is no longer read
-    stage_lds(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+    stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
     if (tid < B) {
       const int4 mb = meta_all[meta0 + tid];
       sMeta[tid] = make_int2(mb.x, mb.y);
     }
-    for (int i = tid; i < nops; i += kNT) {
+    for (int i = tid; i < nops; i += NT) {
       const int4* op = reinterpret_cast<const int4*>(a.ops + int64_t(op0 + i) * kOpInts);
       const int4 lo = op[0], hi = op[1];  // (f, k, r0, in), (out, child_begin, n_children, virt)
       if (i < nreal) {
@@ -647,11 +644,11 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
       sOpv[i] = make_int4(lo.z, lo.w, hi.x, 0);
       sOpx[i] = make_int4(lo.x, lo.y, hi.y, hi.z | (hi.w << 16));
     }
-    for (int i = tid; i < ex_len; i += kNT) sEx[i] = a.extra[ex_off + i];
-    for (int i = tid; i < 12 * nvirt; i += kNT) sAdj1[i] = cmake<C>(0, 0);
+    for (int i = tid; i < ex_len; i += NT) sEx[i] = a.extra[ex_off + i];
+    for (int i = tid; i < 12 * nvirt; i += NT) sAdj1[i] = cmake<C>(0, 0);
     __syncthreads();
 
-    tile_levels<KMIN, KMAX, NU, ND, QMAX, C>(tu, td, tr, sOps, sS, sR);
+    tile_levels<KMIN, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR);
 
     // adjoints of the top rows from the factor-tree leaves
     {
@@ -662,7 +659,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-          const int c = vt_u + kNT * q;
+          const int c = vt_u + NT * q;
           if (c < cu_tab.ncol) {
             const C sum = leaf_sum<2, MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
@@ -673,7 +670,7 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
         const int ds = dgs[2 * g], mask = dgs[2 * g + 1];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-          const int c = vt_d + kNT * q;
+          const int c = vt_d + NT * q;
           if (c < cd_tab.ncol) {
             const C sum = leaf_sum<2, MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
@@ -685,12 +682,12 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
 
     const int32_t* children = sEx + 3 + 3 * sEx[0] + 2 * sEx[1];
     const int32_t* rsum = sEx + sEx[2];
-    rev_levels<KMAX, NU, ND, QMAX, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
+    rev_levels<KMAX, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
 
     // fixed-order accumulation of this tile's S-bar contributions
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = vt + kNT * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int e = vt + NT * q;
       if (e < 288) {
         const int row = e / 12, bc = e % 12;  // row = 12 f + r0
         C sum = cmake<C>(0, 0);
@@ -708,8 +705,8 @@ __global__ __launch_bounds__(kNT) void ds_kernel(BwdArgs a) {
 
   // grad_S = conj(S-bar)
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = vt + kNT * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int e = vt + NT * q;
     if (e < 288) {
       const double x = double(sb[q].hx) + double(sb[q].lx);
       const double y = -(double(sb[q].hy) + double(sb[q].ly));
@@ -756,20 +753,22 @@ BwdArgs make_args(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64
 }
 
 template <typename K>
-hipError_t launch_k(K k, int nblocks, size_t lds, hipStream_t st, const BwdArgs& a) {
+hipError_t launch_k(K k, int nt, int nblocks, size_t lds, hipStream_t st, const BwdArgs& a) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(nblocks), dim3(kNT), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(nblocks), dim3(nt), lds, st, a);
   return hipGetLastError();
 }
 
 template <typename R, int NU, int ND, int QMAX>
 hipError_t launch_dw_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
+  constexpr int NT = family_threads(NU, ND);
   constexpr int MS = dw_src_per_thread(NU, ND);
   constexpr int BW = dw_keys_per_tile(NU, ND, std::is_same<R, double>::value ? MBC_F64 : MBC_F32C);
-  if (p->h.maxs > MS || p->h.qmax > QMAX || p->h.w_max_b > BW) return hipErrorNotSupported;
-  return launch_k(dw_kernel<R, NU, ND, MS, QMAX, BW>, nb, lds, st, a);
+  if ((p->h.max_src + NT - 1) / NT > MS || (p->h.max_ncol + NT - 1) / NT > QMAX || p->h.w_max_b > BW)
+    return hipErrorNotSupported;
+  return launch_k(dw_kernel<R, NU, ND, MS, QMAX, BW, NT>, NT, nb, lds, st, a);
 }
 
 template <typename R>
@@ -778,7 +777,7 @@ hipError_t launch_dw_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, 
   if (nu == 2 && nd == 1) return launch_dw_f<R, 2, 1, 1>(p, a, nb, lds, st);
   if (nu == 1 && nd == 2) return launch_dw_f<R, 1, 2, 1>(p, a, nb, lds, st);
   if (nu == 3 && nd == 3) return launch_dw_f<R, 3, 3, 1>(p, a, nb, lds, st);
-  if (nu == 5 && nd == 4) return launch_dw_f<R, 5, 4, 2>(p, a, nb, lds, st);
+  if (nu == 5 && nd == 4) return launch_dw_f<R, 5, 4, 1>(p, a, nb, lds, st);
   return hipErrorNotSupported;
 }
 
@@ -788,14 +787,23 @@ bool bins_fit(const PlanHost& h) {
   return h.max_bin[6] == 0;
 }
 
+template <typename R, int NU, int ND, int MAXCOL, int MC>
+hipError_t launch_ds_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
+  constexpr int NT = ds_threads(NU, ND, std::is_same<R, double>::value ? MBC_F64 : MBC_F32C);
+  constexpr int QMAX = (MAXCOL + NT - 1) / NT;
+  if (p->h.max_ncol > MAXCOL || p->h.max_csr > MC) return hipErrorNotSupported;
+  return launch_k(ds_kernel<R, NU, ND, QMAX, MC, NT>, NT, nb, lds, st, a);
+}
+
 template <typename R>
 hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
-  const int nu = p->h.n_u, nd = p->h.n_d, qm = p->h.qmax, mc = p->h.max_csr;
+  const int nu = p->h.n_u, nd = p->h.n_d;
   if (!bins_fit(p->h)) return hipErrorNotSupported;
-  if (nu == 2 && nd == 1 && qm <= 1 && mc <= 2) return launch_k(ds_kernel<R, 2, 1, 1, 2>, nb, lds, st, a);
-  if (nu == 1 && nd == 2 && qm <= 1 && mc <= 2) return launch_k(ds_kernel<R, 1, 2, 1, 2>, nb, lds, st, a);
-  if (nu == 3 && nd == 3 && qm <= 1 && mc <= 6) return launch_k(ds_kernel<R, 3, 3, 1, 6>, nb, lds, st, a);
-  if (nu == 5 && nd == 4 && qm <= 2 && mc <= 10) return launch_k(ds_kernel<R, 5, 4, 2, 10>, nb, lds, st, a);
+  // instantiated for at most MAXCOL columns per level and MC source keys per top column
+  if (nu == 2 && nd == 1) return launch_ds_f<R, 2, 1, 256, 2>(p, a, nb, lds, st);
+  if (nu == 1 && nd == 2) return launch_ds_f<R, 1, 2, 256, 2>(p, a, nb, lds, st);
+  if (nu == 3 && nd == 3) return launch_ds_f<R, 3, 3, 256, 6>(p, a, nb, lds, st);
+  if (nu == 5 && nd == 4) return launch_ds_f<R, 5, 4, 512, 10>(p, a, nb, lds, st);
   return hipErrorNotSupported;
 }
 

@@ -99,20 +99,32 @@ constexpr int kOpInts = 8;
 constexpr int kMetaInts = 4;
 constexpr int kMaxPhases = 7;
 
+// Threads per workgroup of the kernels of an operator family: the (5,4)
+// family's columns (up to 489 per level) and source keys (up to 1308) fit
+// one slot per thread at 512, halving the per-thread register tables.
+constexpr int family_threads(int n_u, int n_d) { return n_u + n_d >= 8 ? 512 : 256; }
+// The dS kernel of the (5,4) family in FP64 keeps 256 (at 512 its registers
+// spill to scratch memory).
+constexpr int ds_threads(int n_u, int n_d, int precision) {
+  return (n_u + n_d >= 8 && precision == MBC_F64) ? 256 : family_threads(n_u, n_d);
+}
+
 // Sink keys per tile of the dW schedule, and source keys per thread the dW
 // kernel is built for, per operator family (n_u, n_d) and precision (the
 // kernel keeps keys x source slots compensated accumulators in registers;
 // on the D_I bench workload 2 keys (FP32) and 1 (FP64) measured fastest).
 constexpr int dw_keys_per_tile(int n_u, int n_d, int precision) {
-  return n_u + n_d >= 8 ? 1 : (n_u + n_d >= 6 ? (precision == MBC_F64 ? 1 : 2) : 4);
+  return n_u + n_d >= 8 ? 2 : (n_u + n_d >= 6 ? (precision == MBC_F64 ? 1 : 2) : 4);
 }
-constexpr int dw_src_per_thread(int n_u, int n_d) { return n_u + n_d >= 8 ? 6 : (n_u + n_d >= 6 ? 3 : 1); }
+constexpr int dw_src_per_thread(int n_u, int n_d) { return n_u + n_d >= 8 ? 3 : (n_u + n_d >= 6 ? 3 : 1); }
 
 struct PlanHost {
   int n_u = 0, n_d = 0, n_corr = 0, precision = MBC_F64;
   int64_t nnz = 0;
   int threads = 256;
-  int maxs = 1;          // max source keys per thread
+  int maxs = 1;          // max source keys per thread (256 threads)
+  int max_src = 0;       // max source keys of a correlator
+  int max_ncol = 0;      // max columns of a level
   int max_b = 0;         // max sink keys per tile
   int max_ops = 0;       // max row ops per tile
   int qmax = 1;          // max column subsets per thread at one level

@@ -498,16 +498,15 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.n_corr = s.n_corr;
   P.precision = precision;
   P.nnz = int64_t(s.entries.size());
-  P.threads = 256;
+  P.threads = family_threads(s.n_u, s.n_d);
   const int csz = precision == MBC_F64 ? 16 : 8;
   // local-memory budgets per workgroup (forward; backward dS kernel), sized
   // to the workgroups per CU that the kernels' registers allow (measured
   // best on the D_I bench workload): two share a CU's 160 KiB, four for the
-  // FP32 forward of the small families; the (5,4) family's dS kernels, and
-  // its FP64 forward, run one workgroup per CU, so their tiles may take
-  // nearly all of it (fewer, larger tiles)
+  // FP32 forward of the small families; the (5,4) family's 512-thread
+  // workgroups run one per CU, so their tiles may take nearly all of it
   const bool big = s.n_u + s.n_d >= 8;
-  const int64_t budget = big ? (precision == MBC_F64 ? 150 : 76) * 1024 : (precision == MBC_F64 ? 76 : 38) * 1024;
+  const int64_t budget = big ? 150 * 1024 : (precision == MBC_F64 ? 76 : 38) * 1024;
   const int64_t bbudget = big ? 150 * 1024 : (precision == MBC_F64 ? 76 : 78) * 1024;
   const int kMaxB = 16;
   const LdsModel fwd_model{false, csz}, bwd_model{true, csz}, dw_model{false, csz, false};
@@ -605,9 +604,13 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
       P.src_cd.push_back(X.lev[1].index[X.nf[1]].at(k.second));
     }
     P.maxs = std::max(P.maxs, (X.n_src + P.threads - 1) / P.threads);
+    P.max_src = std::max(P.max_src, X.n_src);
     for (int f = 0; f < 2; ++f) {
       P.maxc_top = std::max(P.maxc_top, X.ncol(f, X.nf[f]));
-      for (int k = 1; k <= X.nf[f]; ++k) P.qmax = std::max(P.qmax, (X.ncol(f, k) + P.threads - 1) / P.threads);
+      for (int k = 1; k <= X.nf[f]; ++k) {
+        P.qmax = std::max(P.qmax, (X.ncol(f, k) + P.threads - 1) / P.threads);
+        P.max_ncol = std::max(P.max_ncol, X.ncol(f, k));
+      }
     }
     backward_tables(X, cr, P.btab);
 
