@@ -56,12 +56,6 @@ struct BwdArgs {
   int64_t nnz;
 };
 
-template <typename C>
-__device__ __forceinline__ C cconj(C a) {
-  a.y = -a.y;
-  return a;
-}
-
 // Rows of one site for one tile (no propagator prefetch): one barrier per level.
 template <int K, int KMAX, int NU, int ND, int QMAX, int NT, typename C>
 __device__ __forceinline__ void tile_levels(const FlavTabs<NU, QMAX, NT>& tu, const FlavTabs<ND, QMAX, NT>& td,

@@ -92,6 +92,10 @@ void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
 //   (virtual = a level-1 parent standing for S row r0: out = 12 * its index
 //   in the tile's level-1 adjoint rows).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
+// Three tilings of the sink keys per plan: the forward's (tiles/ops/meta),
+// the dS kernel's (b_*: backward records, every row slot followed by one
+// zero element that padded table entries point at) and the dW kernel's
+// (w_*: forward-style records, at most dw_keys_per_tile keys per tile).
 // ---------------------------------------------------------------------------
 constexpr int kCorrInts = 96;
 constexpr int kTileInts = 48;
@@ -122,12 +126,10 @@ struct PlanHost {
   int n_u = 0, n_d = 0, n_corr = 0, precision = MBC_F64;
   int64_t nnz = 0;
   int threads = 256;
-  int maxs = 1;          // max source keys per thread (256 threads)
   int max_src = 0;       // max source keys of a correlator
-  int max_ncol = 0;      // max columns of a level
+  int max_ncol = 0;      // max columns of a level (the kernels' per-thread slots follow)
   int max_b = 0;         // max sink keys per tile
   int max_ops = 0;       // max row ops per tile
-  int qmax = 1;          // max column subsets per thread at one level
   int64_t lds_bytes = 0; // dynamic LDS of the forward kernel
   int n_tiles = 0;
   std::vector<int32_t> corr, tiles, ops, meta, src_cu, src_cd;
@@ -139,7 +141,6 @@ struct PlanHost {
   // (key, source key) accumulator of a tile in registers)
   int w_n_tiles = 0, w_max_ops = 0, w_max_b = 0;
   std::vector<int32_t> w_tiles, w_ops, w_meta;
-  int maxc_top = 0;      // max top-level columns over correlators and flavours
   int max_csr = 0;       // longest source-key list of a top column
   int max_bin[7] = {0, 0, 0, 0, 0, 0, 0};  // longest j-list per level
   std::vector<uint16_t> tabs;

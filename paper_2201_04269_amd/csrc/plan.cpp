@@ -603,15 +603,9 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
       P.src_cu.push_back(X.lev[0].index[X.nf[0]].at(k.first));
       P.src_cd.push_back(X.lev[1].index[X.nf[1]].at(k.second));
     }
-    P.maxs = std::max(P.maxs, (X.n_src + P.threads - 1) / P.threads);
     P.max_src = std::max(P.max_src, X.n_src);
-    for (int f = 0; f < 2; ++f) {
-      P.maxc_top = std::max(P.maxc_top, X.ncol(f, X.nf[f]));
-      for (int k = 1; k <= X.nf[f]; ++k) {
-        P.qmax = std::max(P.qmax, (X.ncol(f, k) + P.threads - 1) / P.threads);
-        P.max_ncol = std::max(P.max_ncol, X.ncol(f, k));
-      }
-    }
+    for (int f = 0; f < 2; ++f)
+      for (int k = 1; k <= X.nf[f]; ++k) P.max_ncol = std::max(P.max_ncol, X.ncol(f, k));
     backward_tables(X, cr, P.btab);
 
     // algorithmic flops (global minor DAG + leaves + (r_u, c_u) groups);
