@@ -179,6 +179,15 @@ __device__ __forceinline__ void store_site(C* dst, const C* pre) {
     if (i < 288 - NT) dst[NT + i] = pre[1];
 }
 
+// A rotation of the workgroup's lane order by a multiple of a wave, varied
+// between workgroups, so that the wave given the most work (for instance an
+// extra source slot) falls on different SIMDs in co-resident workgroups.
+template <int NT>
+__device__ __forceinline__ int rotated_lane() {
+  const int rot = int(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & (NT / 64 - 1)) * 64;
+  return (int(threadIdx.x) + rot) & (NT - 1);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block id mod 8).  Map
 // them so that each XCD receives a contiguous range of logical ids, which
 // keeps all tiles of a chunk of sites (same propagators) in one L2.

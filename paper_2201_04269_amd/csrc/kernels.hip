@@ -124,6 +124,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
   constexpr bool kOverlapLeaves = (NU >= 3 && ND >= 3);
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
+  const int vt = rotated_lane<NT>();
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
   const int tile = lin % a.n_tiles;
   const int tc = lin / a.n_tiles;  // t * nc + chunk
@@ -151,20 +152,19 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
   tu.load(cr, 0, a.tabs);
   td.load(cr, 1, a.tabs);
 
-  // source keys s = tid + NT m; lanes past the last key read key n_src - 1
+  // source keys s = vt + NT m (vt: rotated lane); lanes past the last key read key n_src - 1
   // and drop their products; the wave runs the slots its first lane has
   int cu[MAXS], cd[MAXS], sl[MAXS];
   bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
-    const int s = tid + NT * m;
+    const int s = vt + NT * m;
     live[m] = s < n_src;
     sl[m] = live[m] ? s : n_src - 1;
     cu[m] = a.src_cu[src_off + sl[m]];
     cd[m] = a.src_cd[src_off + sl[m]];
   }
-  const int wave0 = tid & ~63;
-  const int nlive = (n_src - wave0 + NT - 1) / NT;  // > 0 unless the wave has no key
+  const int nlive = (n_src - (vt & ~63) + NT - 1) / NT;  // > 0 unless the wave has no key
 
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;

@@ -120,6 +120,7 @@ __global__ __launch_bounds__(NT) void dw_kernel(BwdArgs a) {
   constexpr bool kOverlapLeaves = (NU >= 3 && ND >= 3);
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
+  const int vt = rotated_lane<NT>();
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
   const int tile = lin % a.n_tiles;
   const int tc = lin / a.n_tiles;
@@ -151,13 +152,13 @@ __global__ __launch_bounds__(NT) void dw_kernel(BwdArgs a) {
   bool live[MAXS];
 #pragma unroll
   for (int m = 0; m < MAXS; ++m) {
-    const int s = tid + NT * m;
+    const int s = vt + NT * m;
     live[m] = s < n_src;
     const int sl = live[m] ? s : n_src - 1;
     cu[m] = a.src_cu[src_off + sl];
     cd[m] = a.src_cd[src_off + sl];
   }
-  const int nlive = (n_src - (tid & ~63) + NT - 1) / NT;  // slots the wave runs
+  const int nlive = (n_src - (vt & ~63) + NT - 1) / NT;  // slots the wave runs
   CompAcc<R> acc[BW][MAXS];
 
   const int t = tc / a.nc, ch = tc % a.nc;
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(NT) void dw_kernel(BwdArgs a) {
 #pragma unroll
     for (int m = 0; m < MAXS; ++m) {
       if (b < B && live[m]) {
-        const int i = b * n_src + tid + NT * m;
+        const int i = b * n_src + vt + NT * m;
         const double qx = double(acc[b][m].hx) + double(acc[b][m].lx);
         const double qy = -(double(acc[b][m].hy) + double(acc[b][m].ly));  // conj(Q)
         out[2 * i] = gx * qx - gy * qy;
@@ -579,8 +580,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
   // workgroup / a quarter apart, so that small per-flavour tasks of one
   // level run on different waves side by side.
   constexpr int NQ = (288 + NT - 1) / NT;  // S-bar entries per thread
-  const int rot = int(((blockIdx.x >> 3) + (blockIdx.x >> 8)) & (NT / 64 - 1)) * 64;
-  const int vt = (tid + rot) & (NT - 1);
+  const int vt = rotated_lane<NT>();
   const int vt_u = vt, vt_d = (vt + NT / 2) & (NT - 1);
   const int vt_pu = (vt + NT / 4) & (NT - 1), vt_pd = (vt + 3 * NT / 4) & (NT - 1);
   CompAcc<R> sb[NQ];  // S-bar entries vt + NT q (< 288)
