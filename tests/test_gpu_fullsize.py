@@ -198,3 +198,64 @@ def test_backward_mixed_dinucleon_16x16x16x32():
             tolW = np.maximum(tolW, 1e-12 * np.abs(refW))
         print("backward 16^3x32", prec, "max dW err / sum|terms|", float(np.max(errW / np.maximum(sclW, 1e-300))))
         assert np.all(errW <= tolW + 1e-300)
+
+
+def test_backward_ragged_lattice_and_complex64():
+    """Gradients on a lattice whose timeslices do not divide into whole chunks
+    (1000 sites per timeslice), complex128 and complex64 propagators."""
+    api = _api()
+    T, V = 2, 1000
+    Su, Sd = synth.iid(T, V, seed=13)
+    picks = [(0, 0), (0, 777), (1, 999)]
+    Su, Sd = keep_sites(Su, Sd, picks)
+    rs = O.build_index_set([dict(op="DI")])
+    gC = np.array([[0.7 - 0.2j, -0.4 + 1.1j]])
+    k = kappa(3, 3)
+    for prec, c64 in (("f64", False), ("f32c", False), ("f32c", True)):
+        plan = api.Plan(api.IndexSet([dict(op="DI")]), prec)
+        dt = torch.complex64 if c64 else torch.complex128
+        su, sd = torch.from_numpy(Su).to(dt).cuda(), torch.from_numpy(Sd).to(dt).cuda()
+        gW, gSu, gSd = api.contract_backward(plan, su, sd, None, torch.from_numpy(gC).cuda())
+        gW, gSu, gSd = gW.cpu().numpy(), gSu.cpu().numpy(), gSd.cpu().numpy()
+        assert gSu.dtype == (np.complex64 if c64 else np.complex128)
+        S_u = Su.astype(np.complex64).astype(np.complex128) if c64 else Su
+        S_d = Sd.astype(np.complex64).astype(np.complex128) if c64 else Sd
+        u = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+        refW = np.zeros(rs.nnz, dtype=np.complex128)
+        sclW = np.zeros(rs.nnz)
+        for t, v in picks:
+            su1, sd1 = S_u[t, v][None, None], S_d[t, v][None, None]
+            ref = CO.gradients(su1, sd1, rs, gC[:, t:t + 1])
+            scl = CO.gradient_abs_scales(su1, sd1, rs, gC[:, t:t + 1])
+            refW += ref["W"]
+            sclW += scl["W"]
+            for key, got in (("S_u", gSu[t, v]), ("S_d", gSd[t, v])):
+                tol = k * u * scl[key][0, 0]
+                if prec == "f64":
+                    tol = np.maximum(tol, 1e-12 * np.abs(ref[key][0, 0]))
+                if c64:  # the gradient is rounded to complex64 on output
+                    tol = tol + 2.0 ** -24 * np.abs(ref[key][0, 0])
+                assert np.all(np.abs(got - ref[key][0, 0]) <= tol + 1e-300), (prec, c64, key, t, v)
+        tolW = k * u * sclW
+        if prec == "f64":
+            tolW = np.maximum(tolW, 1e-12 * np.abs(refW))
+        assert np.all(np.abs(gW - refW) <= tolW + 1e-300), (prec, c64)
+
+
+def test_autograd_example_from_the_readme():
+    """C.abs().sum().backward() through Contract gives the oracle's dL/dW*."""
+    api = _api()
+    iset = api.IndexSet([dict(op="DI")])
+    plan = api.Plan(iset, "f64")
+    Su, Sd = synth.su3_spin(2, 3, seed=1)
+    su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
+    W = torch.from_numpy(iset.weights()).cuda().requires_grad_()
+    C = api.Contract.apply(su, sd, W, plan)
+    C.abs().sum().backward()
+    rs = O.build_index_set([dict(op="DI")])
+    Cref = CO.correlator(Su, Sd, rs)
+    gC = Cref / np.abs(Cref)  # d|C|/dC* for PyTorch's convention
+    ref = CO.gradients(Su, Sd, rs, gC)
+    scl = CO.gradient_abs_scales(Su, Sd, rs, gC)
+    err = np.abs(W.grad.cpu().numpy() - ref["W"])
+    assert np.all(err <= np.maximum(kappa(3, 3) * 2.0 ** -53 * scl["W"], 1e-12 * np.abs(ref["W"])) + 1e-300)
