@@ -19,6 +19,10 @@ wick         Brute-force Grassmann Wick contraction of one (sink term, source
 correlator   Determinant-form correlator C[t], sum of |Wick terms| A[t], and
              the gradients dC/dW, dC/dS (Jacobi's formula with explicit
              cofactors).
+blocks       Hadron blocks with sink momentum projection (Sec. 2), the
+             block-level correlator by the partition sum of Wick's theorem
+             (Sec. 3), a site-labelled determinant brute force that pins it,
+             and the multiplicity count of the expanded form (Sec. 3, Fig. 2).
 
 Every function documents the passage it follows.  Where the paper is silent the
 reading used is stated in the docstring.

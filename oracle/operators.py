@@ -158,6 +158,39 @@ def operator_terms(op, spin=0, sign_mode="exact"):
     return terms, s2
 
 
+def baryon_products(op, spin=0, sign_mode="exact"):
+    """Sink operator of eq. "ops" as a sum of products of single baryons.
+
+    Returns (products, s2): products a list of (coef, slots) with slots a
+    tuple of (baryon name, open spin) in written order, so that the operator
+    is sum coef * prod_i B_i^{spin_i}; coef carries the written relative sign
+    (or +1 under "r2") times (C gamma5)_{alpha beta} of the first two baryons.
+    The third baryon of 3He carries the open index j = ``spin``.  A single
+    baryon is one product with coefficient 1.  Used by the block-level
+    correlator, where baryon i of a product sits at its own sink point.
+    """
+    if sign_mode not in ("exact", "r2"):
+        raise ValueError(sign_mode)
+    if op in ("proton", "neutron"):
+        return [((1, 0), (("p" if op == "proton" else "n", spin),))], Fraction(1)
+    if op not in _MULTI:
+        raise ValueError(op)
+    s2, prods = _MULTI[op]
+    gre, gim = cg5(0)
+    out = []
+    for relsign, *names in prods:
+        if sign_mode == "r2":
+            relsign = 1
+        for al in range(4):
+            for be in range(4):
+                g = (int(gre[al, be]), int(gim[al, be]))
+                if g == (0, 0):
+                    continue
+                slots = ((names[0], al), (names[1], be)) + (((names[2], spin),) if len(names) == 3 else ())
+                out.append((gscale(g, relsign), slots))
+    return out, s2
+
+
 def quark_counts(op):
     """(n_u, n_d) of an operator."""
     terms, _ = operator_terms(op)

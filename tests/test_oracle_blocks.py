@@ -1,0 +1,138 @@
+"""Pins of the oracle's hadron blocks and block-level correlators.
+
+Each check takes a route that shares no step with the block construction:
+the paper's explicit proton block formula (Sec. 2), the determinant-form
+oracle at a single site (already pinned against brute-force Wick sums), a
+site-labelled determinant brute force over every tuple of sink points, the
+partition count N_w = 9 of D_I (Sec. 3), lattice translations, and exact
+counting identities of the expansion.
+"""
+import numpy as np
+import pytest
+
+from oracle import blocks as B
+from oracle import correlator as CO
+from oracle import gamma as G
+from oracle import operators as O
+from paper_2201_04269_amd import synth
+
+
+def _iset(op, s, sp, mode):
+    return O.build_index_set([dict(op=op, snk_spin=s, src_spin=sp, sign_mode=mode)])
+
+
+def test_proton_block_entries_equal_the_papers_formula():
+    # f^P(a', beta', b', gamma', c', alpha')_alpha of Sec. 2, written out with
+    # plain loops, against the oracle's pairing-sum block at one site.
+    Su, Sd = synth.iid(1, 1, seed=21)
+    f = B.block(Su, Sd, "p", (0, 0, 0), (1, 1, 1))[0]
+    Gm = G.complex_of(G.cg5(0))
+    eps = dict(O._levi_civita3())
+    su, sd = Su[0, 0], Sd[0, 0]
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        al, A, Y, C = (int(v) for v in rng.integers(0, [4, 12, 12, 12]))
+        ref = 0j
+        for (a, b, c), e in eps.items():
+            for be in range(4):
+                for ga in range(4):
+                    if Gm[be, ga] == 0:
+                        continue
+                    ref += e * Gm[be, ga] * (su[4 * a + be, C] * su[4 * c + al, A]
+                                             - su[4 * a + be, A] * su[4 * c + al, C]) * sd[4 * b + ga, Y]
+        assert abs(f[al, (A * 12 + Y) * 12 + C] - ref) <= 1e-14 * max(1.0, abs(ref))
+
+
+def test_blocks_are_antisymmetric_in_the_two_like_antiquarks():
+    Su, Sd = synth.iid(1, 2, seed=22)
+    for name in ("p", "n+", "p-"):
+        f = B.block(Su, Sd, name, (1, 0, 0), (2, 1, 1)).reshape(1, 4, 12, 12, 12)
+        assert np.allclose(f, -f.transpose(0, 1, 4, 3, 2), rtol=0, atol=1e-15)
+        assert np.abs(np.einsum("taiyi->tay", f)).max() == 0.0
+
+
+def test_block_momentum_phase_under_a_lattice_translation():
+    # S'(x) = S(x + e_d) gives f'_p = e^{+2 pi i n_d / L_d} f_p: pins the site
+    # order (x1 fastest) and the sign of the exponent together.
+    dims = (3, 2, 2)
+    Su, Sd = synth.iid(1, 12, seed=23)
+    mom = (1, 1, 0)
+    f = B.block(Su, Sd, "n", mom, dims)
+    for axis, d in ((3, 0), (2, 1)):
+        sh = [np.roll(S.reshape(1, 2, 2, 3, 12, 12), -1, axis=axis).reshape(1, 12, 12, 12) for S in (Su, Sd)]
+        f2 = B.block(sh[0], sh[1], "n", mom, dims)
+        assert np.allclose(f2, np.exp(2j * np.pi * mom[d] / dims[d]) * f, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("op,s,sp,mode", [("proton", 1, 2, "exact"), ("neutron", 3, 0, "exact"),
+                                          ("DI", 0, 0, "exact"), ("DII", 0, 0, "r2"),
+                                          ("HE3_I", 1, 1, "exact")])
+def test_one_site_equals_the_local_determinant_form(op, s, sp, mode):
+    # With one site per timeslice every baryon sits at the same point, so the
+    # block-level correlator is eq. 1's local correlator.
+    Su, Sd = synth.iid(2, 1, seed=24)
+    A = 1 if op in ("proton", "neutron") else (2 if op.startswith("D") else 3)
+    C = B.block_correlator(Su, Sd, op, s, sp, mode, [(0, 0, 0)] * A, (1, 1, 1))
+    ref = CO.correlator(Su, Sd, _iset(op, s, sp, mode))[0]
+    assert np.abs(C - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("op,moms,dims,T", [
+    ("proton", [(1, 1, 0)], (2, 2, 1), 2),
+    ("neutron", [(0, 1, 0)], (2, 2, 1), 2),
+    ("DI", [(1, 0, 0), (0, 1, 0)], (2, 2, 1), 1),
+    ("DI", [(1, 0, 0), (-1, 0, 0)], (2, 1, 1), 2),
+])
+def test_separate_sinks_equal_the_labelled_determinant_bruteforce(op, moms, dims, T):
+    V = dims[0] * dims[1] * dims[2]
+    Su, Sd = synth.iid(T, V, seed=25)
+    C = B.block_correlator(Su, Sd, op, 2, 1, "exact", moms, dims)
+    bf = B.block_correlator_bruteforce(Su, Sd, op, 2, 1, "exact", moms, dims)
+    assert np.abs(C - bf).max() <= 1e-13 * np.abs(bf).max()
+
+
+def test_three_baryons_at_two_points_equal_the_bruteforce():
+    Su, Sd = synth.iid(1, 2, seed=26)
+    moms = [(1, 0, 0), (0, 0, 0), (-1, 0, 0)]
+    C = B.block_correlator(Su, Sd, "HE3_I", 1, 3, "exact", moms, (2, 1, 1))
+    bf = B.block_correlator_bruteforce(Su, Sd, "HE3_I", 1, 3, "exact", moms, (2, 1, 1))
+    assert abs(C[0] - bf[0]) <= 1e-13 * abs(bf[0])
+
+
+def test_raw_and_canonical_source_forms_agree():
+    Su, Sd = synth.iid(1, 2, seed=27)
+    moms = [(1, 0, 0), (-1, 0, 0)]
+    a = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (2, 1, 1), source="raw")
+    b = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (2, 1, 1))
+    assert abs(a[0] - b[0]) <= 1e-13 * abs(b[0])
+
+
+def test_dinucleon_has_nine_partitions_and_three_helium_three_sixty():
+    # N_w = 9 for D_I (Sec. 3): 3 ways to give the proton two of the three
+    # ubar, times 3 ways to give it one of the three dbar.
+    for fl in [(O.U,) * 3 + (O.D,) * 3, (O.D, O.U, O.D, O.U, O.U, O.D)]:
+        parts = B.partitions(["n", "p"], fl)
+        assert len(parts) == 9
+        assert len({g for g, _ in parts}) == 9
+    # 3He (p-, n+, p+): 5!/(2! 1! 2!) u assignments x 4!/(1! 2! 1!) d assignments
+    assert len(B.partitions(["p", "n", "p"], (O.U,) * 5 + (O.D,) * 4)) == 30 * 12
+
+
+def test_exact_sign_dii_vanishes_and_r2_is_twice_di():
+    Su, Sd = synth.iid(1, 2, seed=28)
+    moms = [(1, 0, 0), (-1, 0, 0)]
+    blocks = {}
+    di = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (2, 1, 1), blocks=blocks)
+    ex = B.block_correlator(Su, Sd, "DII", 0, 0, "exact", moms, (2, 1, 1), blocks=blocks)
+    r2 = B.block_correlator(Su, Sd, "DII", 0, 0, "r2", moms, (2, 1, 1), blocks=blocks)
+    assert ex[0] == 0
+    assert abs(r2[0] - 2 * di[0]) <= 1e-13 * abs(di[0])
+
+
+@pytest.mark.parametrize("op,mode,n_src,n_prod,n_part", [("DI", "exact", 2304, 4, 9),
+                                                         ("DII", "r2", 4608, 8, 9)])
+def test_multiplicity_histogram_counts(op, mode, n_src, n_prod, n_part):
+    n, hist = B.multiplicity_histogram(op, 0, 0, mode)
+    assert n == n_src * n_prod * n_part
+    assert sum(m * k for m, k in hist.items()) == n
+    assert min(hist) >= 1
