@@ -18,6 +18,10 @@ Workloads (synthetic inputs, the paper's propagators are not available):
   he3_shard  the same operators on one GPU's share of that lattice when it is
              split by timeslice over 8 GPUs: 32^3 x 8 sites (i.i.d., seed 4)
 
+Beside each workload the hadron-block path (Sec. 2 blocks with sink
+momentum projection, Sec. 3 block-level correlators; FP64) is timed on the
+same propagators and reported under "blocks" (--no-blocks skips it).
+
 Prints one JSON line (rank 0).  `value` is index entries contracted per
 second, sum over correlators of |I_c| times the number of sites, divided by
 the time of one step, for the FP32-compensated path; the FP64 path is timed
@@ -64,6 +68,66 @@ def workload(name):
     else:
         raise SystemExit(f"unknown workload {name}")
     return dict(name=name, L=L, T=T, ops=ops, gen=gen, desc=desc)
+
+
+def block_corrs(name):
+    """Block-level correlators timed beside a workload (same propagators).
+
+    di_mixed: D_I and D_II (R2) with the two nucleons at relative momentum 0
+    and back to back at +-(1, 0, 0); he3_shard: 3He_I^j and 3He_II^j (R2),
+    j = 0..3, all three baryons at zero momentum.
+    """
+    if name == "di_mixed":
+        out = []
+        for op, mode in (("DI", "exact"), ("DII", "r2")):
+            out.append(dict(op=op, sign_mode=mode, moms=[(0, 0, 0), (0, 0, 0)]))
+            out.append(dict(op=op, sign_mode=mode, moms=[(1, 0, 0), (-1, 0, 0)]))
+        return out
+    if name == "he3_shard":
+        return [dict(op="HE3_I", snk_spin=j, src_spin=j, moms=[(0, 0, 0)] * 3) for j in range(4)] + \
+               [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2", moms=[(0, 0, 0)] * 3) for j in range(4)]
+    return None
+
+
+def bench_blocks(api, torch, name, su, sd, L, steps, warmup):
+    """Hadron blocks (one launch pair) and their contraction, timed with HIP
+    events on the launch stream; FP64."""
+    corrs = block_corrs(name)
+    if corrs is None:
+        return None
+    t0 = time.perf_counter()
+    bset = api.BlockSet(corrs)
+    plan = api.BlockPlan(bset)
+    st = plan.stats
+    T, V = su.shape[:2]
+    dims = (L, L, L)
+    ws = torch.empty(plan.workspace_bytes(T, dims), dtype=torch.uint8, device=su.device)
+    print(f"[bench] blocks: {bset.n_types} types, {bset.n_terms} terms ({time.perf_counter() - t0:.1f}s)",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        api.block_contract(plan, api.blocks(plan, su, sd, dims, workspace=ws), workspace=ws)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for e in ev:
+        e[0].record(stream)
+        blk = api.blocks(plan, su, sd, dims, workspace=ws)
+        e[1].record(stream)
+        api.block_contract(plan, blk, workspace=ws)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    ms_b = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    ms_c = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    flops_b = st["block_flops_per_site"] * T * V
+    flops_c = st["contract_flops_per_t"] * T
+    print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction {ms_c:.3f} ms",
+          file=sys.stderr, flush=True)
+    return {"correlators": len(corrs), "block_types": bset.n_types, "terms": bset.n_terms, "dtype": "f64",
+            "ms_blocks": ms_b, "ms_contract": ms_c, "sites_per_s": T * V / ((ms_b + ms_c) * 1e-3),
+            "roofline": {"bound": "alu", "kernel": "block_g", "achieved": flops_b / (ms_b * 1e-3) / 1e12,
+                         "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                         "frac": flops_b / (ms_b * 1e-3) / PEAK["f64"]},
+            "contract_tflops": flops_c / (ms_c * 1e-3) / 1e12}
 
 
 _W_ISET = None
@@ -147,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="f32c,f64")
     ap.add_argument("--fwd-only", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -279,6 +344,10 @@ def main():
         if prec != head:
             out[prec] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "fwd_only_value": rr["fwd_value"],
                          "kernels": rr["kernels"]}
+    if not args.no_blocks:
+        blk = bench_blocks(api, torch, wl["name"], su, sd, wl["L"], args.steps, args.warmup)
+        if blk is not None:
+            out["blocks"] = blk
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, Su, Sd, nnz)
     print(json.dumps(out), flush=True)

@@ -82,41 +82,66 @@ def _all_source_triples():
     return np.stack([A.ravel(), Y.ravel(), C.ravel()], axis=1)  # xi = (A*12 + Y)*12 + C
 
 
-def block(S_u, S_d, name, mom, dims, batch=16):
-    """f^h_p[t, alpha, xi] for baryon ``name``, xi = (A*12 + Y)*12 + C.
+def _projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites=None):
+    """[T, len(src)]: sum_x e^{-i p.x} < h_alpha(x) q1bar(A) q2bar(Y) q1bar(C) > for src rows (A, Y, C).
 
-    S_u, S_d: [T, V, 12, 12] complex128 with V = L1 L2 L3.  Returns
-    [T, 4, 1728] complex128.  Every entry is the pairing sum of ``wick`` over
-    the baryon's written terms (Sec. 1), summed over sites with e^{-i p.x}.
+    ``sites``: optional flat site indices t*V + v to sum over (the others are
+    taken to be zero); default every site.
     """
     T, V = S_u.shape[:2]
     if V != dims[0] * dims[1] * dims[2]:
         raise ValueError("sites per timeslice do not match dims")
     kind, proj = kind_of(name)
     flav = _FLAV[kind]
-    src = _all_source_triples()
     pairs = wick.pairings(flav, flav)
     ph = phases(mom, dims)
-    out = np.zeros((T, 4, src.shape[0]), dtype=np.complex128)
     S_of = {U: S_u.reshape(T * V, 12, 12), D: S_d.reshape(T * V, 12, 12)}
-    for alpha in range(4):
-        terms = O.baryon_terms(kind, alpha, proj)
-        coef = np.array([complex(c[0], c[1]) for c, _ in terms])
-        snk = np.array([[i for _, i in f] for _, f in terms])
-        for s0 in range(0, T * V, batch):
-            sl = slice(s0, min(T * V, s0 + batch))
-            E = np.zeros((sl.stop - sl.start, snk.shape[0], src.shape[0]), dtype=np.complex128)
-            for pi, sgn in pairs:
-                term = np.full(E.shape, float(sgn), dtype=np.complex128)
-                for i, f in enumerate(flav):
-                    term *= S_of[f][sl][:, snk[:, i][:, None], src[:, pi[i]][None, :]]
-                E += term
-            vals = np.einsum("r,brx->bx", coef, E)
-            sites = np.arange(sl.start, sl.stop)
-            w = ph[sites % V]
-            for t in np.unique(sites // V):
-                m = (sites // V) == t
-                out[t, alpha] += (w[m, None] * vals[m]).sum(axis=0)
+    terms = O.baryon_terms(kind, alpha, proj)
+    coef = np.array([complex(c[0], c[1]) for c, _ in terms])
+    snk = np.array([[i for _, i in f] for _, f in terms])
+    out = np.zeros((T, src.shape[0]), dtype=np.complex128)
+    every = np.arange(T * V) if sites is None else np.asarray(sites, dtype=np.int64)
+    for s0 in range(0, every.shape[0], batch):
+        sl = every[s0:s0 + batch]
+        E = np.zeros((sl.shape[0], snk.shape[0], src.shape[0]), dtype=np.complex128)
+        for pi, sgn in pairs:
+            term = np.full(E.shape, float(sgn), dtype=np.complex128)
+            for i, f in enumerate(flav):
+                term *= S_of[f][sl][:, snk[:, i][:, None], src[:, pi[i]][None, :]]
+            E += term
+        vals = np.einsum("r,brx->bx", coef, E)
+        w = ph[sl % V]
+        for t in np.unique(sl // V):
+            m = (sl // V) == t
+            out[t] += (w[m, None] * vals[m]).sum(axis=0)
+    return out
+
+
+def block(S_u, S_d, name, mom, dims, batch=16, sites=None):
+    """f^h_p[t, alpha, xi] for baryon ``name``, xi = (A*12 + Y)*12 + C.
+
+    S_u, S_d: [T, V, 12, 12] complex128 with V = L1 L2 L3.  Returns
+    [T, 4, 1728] complex128.  Every entry is the pairing sum of ``wick`` over
+    the baryon's written terms (Sec. 1), summed over sites with e^{-i p.x}
+    (over the flat sites t*V + v listed in ``sites`` only, if given).
+    """
+    src = _all_source_triples()
+    return np.stack([_projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites) for alpha in range(4)],
+                    axis=1)
+
+
+def block_entries(S_u, S_d, name, mom, dims, entries, batch=512):
+    """Selected block entries [T, len(entries)] for entries (alpha, A, Y, C).
+
+    The same definition as ``block``, evaluated for a few entries only, so
+    that large lattices stay cheap.
+    """
+    entries = [tuple(int(v) for v in e) for e in entries]
+    out = np.zeros((S_u.shape[0], len(entries)), dtype=np.complex128)
+    for alpha in sorted({e[0] for e in entries}):
+        cols = [k for k, e in enumerate(entries) if e[0] == alpha]
+        src = np.array([entries[k][1:] for k in cols])
+        out[:, cols] = _projected(S_u, S_d, name, mom, dims, alpha, src, batch)
     return out
 
 

@@ -1,4 +1,4 @@
-"""ctypes binding of libmbc (include/mbc.h): argument marshalling only.
+"""ctypes binding of libmbc (include/mbc.h, include/mbc_blocks.h): argument marshalling only.
 
 Every step of the contraction runs in the library; this module only converts
 Python/torch arguments to pointers and sizes and raises on a non-zero status.
@@ -39,6 +39,19 @@ class PlanStats(ctypes.Structure):
                 ("w_n_tiles", ctypes.c_int32)]
 
 
+class BlockCorrDesc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("snk_spin", ctypes.c_int32), ("src_spin", ctypes.c_int32),
+                ("sign_mode", ctypes.c_int32), ("mom", (ctypes.c_int32 * 3) * 3)]
+
+
+class BlockPlanStats(ctypes.Structure):
+    _fields_ = [("n_types", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("n_corr", ctypes.c_int32),
+                ("n_terms", ctypes.c_int64), ("block_flops_per_site", ctypes.c_double),
+                ("contract_flops_per_t", ctypes.c_double)]
+
+
+FAMILIES = {0: "p", 1: "n"}
+
 _lib = None
 
 # exported symbols and their signatures: (name, restype, argtypes)
@@ -59,6 +72,20 @@ SIGNATURES = [
     ("mbc_contract_backward", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("mbc_debug_eval_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, ctypes.POINTER(PlanStats)]),
     ("mbc_debug_backward_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, _P, _P, _P]),
+    ("mbc_block_set_build", _I32, [ctypes.POINTER(BlockCorrDesc), _I32, ctypes.POINTER(_P)]),
+    ("mbc_block_set_dims", _I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                  ctypes.POINTER(_I64)]),
+    ("mbc_block_set_types", _I32, [_P, _P, _P, _P]),
+    ("mbc_block_set_export", _I32, [_P] * 6),
+    ("mbc_block_set_free", None, [_P]),
+    ("mbc_block_multiplicities", _I32, [ctypes.POINTER(BlockCorrDesc), _I64, ctypes.POINTER(_I64),
+                                        ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _I32]),
+    ("mbc_block_plan_create", _I32, [_P, _P, ctypes.POINTER(_P)]),
+    ("mbc_block_plan_get_stats", _I32, [_P, ctypes.POINTER(BlockPlanStats)]),
+    ("mbc_block_workspace_bytes", _I32, [_P, _I32, _P, ctypes.POINTER(_SZ)]),
+    ("mbc_block_plan_destroy", None, [_P]),
+    ("mbc_blocks_compute", _I32, [_P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    ("mbc_block_contract", _I32, [_P, _P, _I32, _P, _P, _SZ, _P]),
 ]
 
 

@@ -36,6 +36,7 @@ class IndexSet:
         descs = _op_descs(self.ops)
         B.check(B.lib().mbc_build_index_set(descs, len(self.ops), ctypes.byref(h)))
         self._h = h
+        self._free = B.lib().mbc_index_set_free
         nu, nd, nc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         nnz = ctypes.c_int64()
         B.check(B.lib().mbc_index_set_dims(h, ctypes.byref(nu), ctypes.byref(nd), ctypes.byref(nnz),
@@ -66,7 +67,7 @@ class IndexSet:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            B.lib().mbc_index_set_free(h)
+            self._free(h)
             self._h = None
 
 
@@ -85,6 +86,7 @@ class Plan:
         h = ctypes.c_void_p()
         B.check(B.lib().mbc_plan_create(iset._h, prec, _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
+        self._free = B.lib().mbc_plan_destroy
         st = B.PlanStats()
         B.check(B.lib().mbc_plan_get_stats(h, ctypes.byref(st)))
         self.stats = {k: getattr(st, k) for k, _ in B.PlanStats._fields_}
@@ -102,7 +104,7 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            B.lib().mbc_plan_destroy(h)
+            self._free(h)
             self._h = None
 
 
@@ -178,3 +180,141 @@ class Contract(torch.autograd.Function):
         return (gSu if ctx.needs_input_grad[0] else None,
                 gSd if ctx.needs_input_grad[1] else None,
                 gW if need_W else None, None)
+
+
+# ---------------------------------------------------------------------------
+# Hadron blocks and block-level correlators (include/mbc_blocks.h)
+# ---------------------------------------------------------------------------
+def _block_descs(corrs):
+    arr = (B.BlockCorrDesc * len(corrs))()
+    for i, c in enumerate(corrs):
+        arr[i].op = B.OPS[c["op"]]
+        arr[i].snk_spin = int(c.get("snk_spin", 0))
+        arr[i].src_spin = int(c.get("src_spin", c.get("snk_spin", 0)))
+        arr[i].sign_mode = B.SIGNS[c.get("sign_mode", "exact")]
+        for s, mom in enumerate(c.get("moms", [])):
+            for d in range(3):
+                arr[i].mom[s][d] = int(mom[d])
+    return arr
+
+
+class BlockSet:
+    """Block types and merged product terms of block-level correlators (host).
+
+    ``corrs``: list of dicts with keys op, snk_spin, src_spin, sign_mode and
+    moms (one integer momentum triple per baryon slot, written order).
+    Mirrors mbc_block_set_build.
+    """
+
+    def __init__(self, corrs):
+        self.corrs = [dict(c) for c in corrs]
+        h = ctypes.c_void_p()
+        B.check(B.lib().mbc_block_set_build(_block_descs(self.corrs), len(self.corrs), ctypes.byref(h)))
+        self._h = h
+        self._free = B.lib().mbc_block_set_free
+        nc, ns, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nterms = ctypes.c_int64()
+        B.check(B.lib().mbc_block_set_dims(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(nt),
+                                           ctypes.byref(nterms)))
+        self.n_corr, self.n_slots, self.n_types, self.n_terms = nc.value, ns.value, nt.value, nterms.value
+
+    def types(self):
+        """List of (family "p"/"n", projector, momentum triple) in block order."""
+        fam = np.zeros(self.n_types, np.int32)
+        proj = np.zeros(self.n_types, np.int32)
+        mom = np.zeros((self.n_types, 3), np.int32)
+        B.check(B.lib().mbc_block_set_types(self._h, fam.ctypes.data_as(ctypes.c_void_p),
+                                            proj.ctypes.data_as(ctypes.c_void_p),
+                                            mom.ctypes.data_as(ctypes.c_void_p)))
+        return [(B.FAMILIES[int(f)], int(p), tuple(int(v) for v in m)) for f, p, m in zip(fam, proj, mom)]
+
+    def export(self):
+        """dict of numpy arrays: factor [n_terms, n_slots], corr_id, num_re, num_im, den."""
+        n = self.n_terms
+        out = dict(factor=np.zeros((n, self.n_slots), np.int32), corr_id=np.zeros(n, np.int32),
+                   num_re=np.zeros(n, np.int64), num_im=np.zeros(n, np.int64),
+                   den=np.zeros(self.n_corr, np.int64))
+        ptr = [out[k].ctypes.data_as(ctypes.c_void_p) for k in ("factor", "corr_id", "num_re", "num_im", "den")]
+        B.check(B.lib().mbc_block_set_export(self._h, *ptr))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._free(h)
+            self._h = None
+
+
+def block_multiplicities(corr, max_terms=1 << 26):
+    """(n_terms, n_distinct, hist) of mbc_block_multiplicities for one correlator dict."""
+    d = _block_descs([corr])
+    nt, nd, mm = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    B.check(B.lib().mbc_block_multiplicities(d, int(max_terms), ctypes.byref(nt), ctypes.byref(nd),
+                                             ctypes.byref(mm), None, 0))
+    hist = np.zeros(mm.value + 1, np.int64)
+    B.check(B.lib().mbc_block_multiplicities(d, int(max_terms), ctypes.byref(nt), ctypes.byref(nd),
+                                             ctypes.byref(mm), hist.ctypes.data_as(ctypes.c_void_p),
+                                             hist.shape[0]))
+    return nt.value, nd.value, hist
+
+
+class BlockPlan:
+    """A block set's types and terms, resident on the device."""
+
+    def __init__(self, bset, stream=None):
+        self.bset = bset
+        h = ctypes.c_void_p()
+        B.check(B.lib().mbc_block_plan_create(bset._h, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self._free = B.lib().mbc_block_plan_destroy
+        st = B.BlockPlanStats()
+        B.check(B.lib().mbc_block_plan_get_stats(h, ctypes.byref(st)))
+        self.stats = {k: getattr(st, k) for k, _ in B.BlockPlanStats._fields_}
+
+    def workspace_bytes(self, T, dims):
+        n = ctypes.c_size_t()
+        d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+        B.check(B.lib().mbc_block_workspace_bytes(self._h, int(T), d, ctypes.byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._free(h)
+            self._h = None
+
+
+def _workspace(plan, T, dims, device):
+    return torch.empty(max(plan.workspace_bytes(T, dims), 16), dtype=torch.uint8, device=device)
+
+
+def blocks(plan, S_u, S_d, dims, workspace=None, stream=None):
+    """Momentum-projected blocks [T, n_types, 4, 12, 12, 12] complex128 (mbc_blocks_compute)."""
+    dt = _check_S(S_u, S_d)
+    T, V = S_u.shape[:2]
+    if V != dims[0] * dims[1] * dims[2]:
+        raise ValueError("sites per timeslice must equal L1 L2 L3")
+    out = torch.empty((T, plan.bset.n_types, 4, 12, 12, 12), dtype=torch.complex128, device=S_u.device)
+    ws = workspace if workspace is not None else _workspace(plan, T, dims, S_u.device)
+    d = (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+    B.check(B.lib().mbc_blocks_compute(plan._h, _ptr(S_u), _ptr(S_d), dt, int(T), d, _ptr(out), _ptr(ws),
+                                       ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+    return out
+
+
+def block_contract(plan, blk, workspace=None, stream=None):
+    """C [n_corr, T] complex128 from blocks (mbc_block_contract)."""
+    if not (blk.is_cuda and blk.dtype == torch.complex128 and blk.is_contiguous()):
+        raise ValueError("blocks must be a contiguous CUDA complex128 tensor")
+    T = blk.shape[0]
+    C = torch.empty((plan.bset.n_corr, T), dtype=torch.complex128, device=blk.device)
+    ws = workspace if workspace is not None else _workspace(plan, T, (1, 1, 1), blk.device)
+    B.check(B.lib().mbc_block_contract(plan._h, _ptr(blk), int(T), _ptr(C), _ptr(ws),
+                                       ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+    return C
+
+
+def block_correlators(plan, S_u, S_d, dims, stream=None):
+    """(C [n_corr, T], blocks): the blocks of every type, then their contraction."""
+    blk = blocks(plan, S_u, S_d, dims, stream=stream)
+    return block_contract(plan, blk, stream=stream), blk

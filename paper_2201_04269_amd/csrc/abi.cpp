@@ -2,6 +2,7 @@
 // plan upload and the orchestration of the device kernels.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -115,9 +116,7 @@ BwdWorkspace bwd_workspace(const PlanHost& h, const Launch& L, bool user_w) {
   return w;
 }
 
-mbc_status check_common(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
-                        int32_t T, int64_t V) {
-  if (!p) return fail(MBC_ERR_INVALID, "plan is NULL");
+mbc_status check_inputs(const void* S_u, const void* S_d, int32_t s_dtype, int32_t T, int64_t V) {
   if (T <= 0) return fail(MBC_ERR_INVALID, "T must be positive");
   if (V <= 0) return fail(MBC_ERR_INVALID, "sites_per_t must be positive");
   if (s_dtype != MBC_C128 && s_dtype != MBC_C64) return fail(MBC_ERR_INVALID, "unknown s_dtype");
@@ -125,6 +124,12 @@ mbc_status check_common(const mbc_plan* p, const void* S_u, const void* S_d, int
     return fail(MBC_ERR_INVALID, "S_u and S_d must be device pointers");
   if (!aligned16(S_u) || !aligned16(S_d)) return fail(MBC_ERR_INVALID, "S_u/S_d must be 16-byte aligned");
   return MBC_OK;
+}
+
+mbc_status check_common(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
+                        int32_t T, int64_t V) {
+  if (!p) return fail(MBC_ERR_INVALID, "plan is NULL");
+  return check_inputs(S_u, S_d, s_dtype, T, V);
 }
 
 }  // namespace
@@ -395,6 +400,188 @@ mbc_status mbc_debug_backward_host(const mbc_index_set* s, int32_t precision, co
   return guarded([&]() {
     return debug_backward(s, precision, S_u, S_d, T, sites_per_t, W, grad_C, grad_W, grad_S_u, grad_S_d);
   });
+}
+
+// ---- hadron blocks and block-level correlators (include/mbc_blocks.h) ----
+
+mbc_status mbc_block_set_build(const mbc_block_corr_desc* corrs, int32_t n_corr, mbc_block_set** out) {
+  if (!corrs || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (n_corr < 1) return fail(MBC_ERR_INVALID, "n_corr must be >= 1");
+  *out = nullptr;
+  return guarded([&]() {
+    auto* s = new mbc_block_set();
+    try {
+      build_block_set(corrs, n_corr, &s->s);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_block_set_dims(const mbc_block_set* s, int32_t* n_corr, int32_t* n_slots, int32_t* n_types,
+                              int64_t* n_terms) {
+  if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
+  if (n_corr) *n_corr = s->s.n_corr;
+  if (n_slots) *n_slots = s->s.n_slots;
+  if (n_types) *n_types = int32_t(s->s.types.size());
+  if (n_terms) *n_terms = int64_t(s->s.corr.size());
+  return MBC_OK;
+}
+
+mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t* projector, int32_t* mom) {
+  if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
+  for (size_t k = 0; k < s->s.types.size(); ++k) {
+    const BlockType& t = s->s.types[k];
+    if (family) family[k] = t.family;
+    if (projector) projector[k] = t.proj;
+    if (mom)
+      for (int d = 0; d < 3; ++d) mom[3 * k + d] = t.mom[d];
+  }
+  return MBC_OK;
+}
+
+mbc_status mbc_block_set_export(const mbc_block_set* s, int32_t* factor, int32_t* corr_id, int64_t* num_re,
+                                int64_t* num_im, int64_t* den) {
+  if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
+  const BlockSet& b = s->s;
+  if (factor) std::copy(b.factor.begin(), b.factor.end(), factor);
+  if (corr_id) std::copy(b.corr.begin(), b.corr.end(), corr_id);
+  if (num_re) std::copy(b.num_re.begin(), b.num_re.end(), num_re);
+  if (num_im) std::copy(b.num_im.begin(), b.num_im.end(), num_im);
+  if (den) std::copy(b.den.begin(), b.den.end(), den);
+  return MBC_OK;
+}
+
+void mbc_block_set_free(mbc_block_set* s) { delete s; }
+
+mbc_status mbc_block_multiplicities(const mbc_block_corr_desc* corr, int64_t max_terms, int64_t* n_terms,
+                                    int64_t* n_distinct, int64_t* max_mult, int64_t* hist, int32_t hist_len) {
+  if (!corr) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (hist && hist_len < 1) return fail(MBC_ERR_INVALID, "hist_len must be >= 1");
+  return guarded([&]() {
+    int64_t nt = 0, nd = 0;
+    std::vector<int64_t> hh;
+    const bool done = block_multiplicities(*corr, max_terms, &nt, &nd, &hh);
+    if (n_terms) *n_terms = nt;
+    if (!done) return fail(MBC_ERR_UNSUPPORTED, "expansion has more than max_terms terms");
+    if (n_distinct) *n_distinct = nd;
+    if (max_mult) *max_mult = int64_t(hh.size()) - 1;
+    if (hist)
+      for (int32_t m = 0; m < hist_len; ++m) hist[m] = size_t(m) < hh.size() ? hh[m] : 0;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block_plan** out) {
+  if (!s || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  return guarded([&]() -> mbc_status {
+    auto* p = new mbc_block_plan();
+    try {
+      compile_block_plan(s->s, &p->h);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    auto release = [](mbc_block_plan* q) {
+      for (void* ptr : {static_cast<void*>(q->types), static_cast<void*>(q->factor), static_cast<void*>(q->coef),
+                        static_cast<void*>(q->chunks)})
+        if (ptr) (void)hipFree(ptr);
+      delete q;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return hip_fail(hipGetLastError(), "hipGetDevice");
+    }
+    hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    mbc_status st = MBC_OK;
+    if ((st = upload(p->h.types, &p->types, hs)) != MBC_OK || (st = upload(p->h.factor, &p->factor, hs)) != MBC_OK ||
+        (st = upload(p->h.coef, &p->coef, hs)) != MBC_OK || (st = upload(p->h.chunks, &p->chunks, hs)) != MBC_OK) {
+      release(p);
+      return st;
+    }
+    hipError_t e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) {
+      release(p);
+      return hip_fail(e, "hipStreamSynchronize");
+    }
+    *out = p;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_block_plan_get_stats(const mbc_block_plan* p, mbc_block_plan_stats* out) {
+  if (!p || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  out->n_types = p->h.n_types;
+  out->n_slots = p->h.n_slots;
+  out->n_corr = p->h.n_corr;
+  out->n_terms = p->h.n_terms;
+  out->block_flops_per_site = p->h.block_flops_per_site;
+  out->contract_flops_per_t = p->h.contract_flops_per_t;
+  return MBC_OK;
+}
+
+mbc_status mbc_block_workspace_bytes(const mbc_block_plan* p, int32_t T, const int32_t dims[3], size_t* bytes) {
+  if (!p || !dims || !bytes) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (T <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0)
+    return fail(MBC_ERR_INVALID, "T and dims must be positive");
+  *bytes = block_workspace_bytes(p->h, T, int64_t(dims[0]) * dims[1] * dims[2]);
+  return MBC_OK;
+}
+
+void mbc_block_plan_destroy(mbc_block_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  for (void* ptr : {static_cast<void*>(p->types), static_cast<void*>(p->factor), static_cast<void*>(p->coef),
+                    static_cast<void*>(p->chunks)})
+    if (ptr) (void)hipFree(ptr);
+  delete p;
+}
+
+mbc_status mbc_blocks_compute(const mbc_block_plan* p, const void* S_u, const void* S_d, int32_t s_dtype, int32_t T,
+                              const int32_t dims[3], double* blocks, void* workspace, size_t ws_bytes,
+                              void* stream) {
+  if (!p || !dims) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (T <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0)
+    return fail(MBC_ERR_INVALID, "T and dims must be positive");
+  const int64_t V = int64_t(dims[0]) * dims[1] * dims[2];
+  mbc_status st = check_inputs(S_u, S_d, s_dtype, T, V);
+  if (st != MBC_OK) return st;
+  if (p->h.n_types == 0) return MBC_OK;
+  if (!is_device_ptr(blocks) || !aligned16(blocks)) return fail(MBC_ERR_INVALID, "blocks must be an aligned device pointer");
+  const size_t need = block_workspace_bytes(p->h, T, V);
+  if (!workspace || !is_device_ptr(workspace) || !aligned16(workspace))
+    return fail(MBC_ERR_INVALID, "workspace must be an aligned device pointer");
+  if (ws_bytes < need) return fail(MBC_ERR_INVALID, "workspace too small");
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
+  MBC_HIP(launch_blocks(p, S_u, S_d, s_dtype == MBC_C64, T, dims, blocks, workspace,
+                        reinterpret_cast<hipStream_t>(stream)));
+  return MBC_OK;
+}
+
+mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int32_t T, double* C, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  if (!p) return fail(MBC_ERR_INVALID, "plan is NULL");
+  if (T <= 0) return fail(MBC_ERR_INVALID, "T must be positive");
+  if (!is_device_ptr(C) || !aligned16(C)) return fail(MBC_ERR_INVALID, "C must be an aligned device pointer");
+  const size_t need = align256(size_t(p->h.chunks.size() / 3) * size_t(T) * 16);
+  if (p->h.n_terms > 0) {
+    if (!is_device_ptr(blocks) || !aligned16(blocks))
+      return fail(MBC_ERR_INVALID, "blocks must be an aligned device pointer");
+    if (!workspace || !is_device_ptr(workspace) || !aligned16(workspace))
+      return fail(MBC_ERR_INVALID, "workspace must be an aligned device pointer");
+    if (ws_bytes < need) return fail(MBC_ERR_INVALID, "workspace too small");
+  }
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
+  MBC_HIP(launch_block_contract(p, blocks, T, C, workspace, reinterpret_cast<hipStream_t>(stream)));
+  return MBC_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,298 @@
+// Block-level correlators (host, exact integer arithmetic).
+//
+// Expands a multi-baryon correlator whose baryons sit at separate,
+// separately momentum-projected sink points into products of baryon blocks
+// (Sec. 2 blocks, Sec. 3 expanded form).  Wick's theorem splits every
+// contraction < h_1 .. h_A qbar_1 .. qbar_n > by the set partition of the
+// source antiquarks among the baryons:
+//
+//   sum_P sign(P) (-1)^{A(A-1)/2} prod_i < h_i Qbar_i >,
+//
+// Qbar_i the three antiquarks of baryon i in block order (q1, q2, q1),
+// sign(P) the parity of bringing the source's antiquarks to Qbar_1 .. Qbar_A,
+// and (-1)^{A(A-1)/2} the sign of moving each three-field group next to its
+// baryon.  The source runs over the canonical keys of eq. 1's index set
+// (antiquarks u..u d..d, each flavour sorted), so the two like antiquarks of
+// a block always arrive in increasing order and no block factor has a
+// repeated like index.  The factors of a product are sorted and equal
+// products merged exactly (the canonical ordering with multiplicities of
+// Sec. 3).
+#include <algorithm>
+#include <array>
+#include <stdexcept>
+#include <unordered_map>
+
+#include "mbc_internal.hpp"
+
+namespace mbc {
+
+namespace {
+
+inline Gauss gmul(Gauss a, Gauss b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+inline Gauss gconj(Gauss a) { return {a.re, -a.im}; }
+
+int parity(const int* v, int n) {
+  int inv = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) inv += v[i] > v[j];
+  return (inv & 1) ? -1 : 1;
+}
+
+// One set partition of the source antiquarks: grp[i] = positions (first q1,
+// q2, second q1) of baryon i's antiquarks; sign includes (-1)^{A(A-1)/2}.
+struct Partition {
+  int grp[3][3];
+  int sign;
+};
+
+void enumerate(const int* family, int A, const uint8_t* flav, int n, int i, bool* used, int (*grp)[3],
+               std::vector<Partition>* out) {
+  if (i == A) {
+    int seq[9];
+    for (int k = 0; k < A; ++k)
+      for (int m = 0; m < 3; ++m) seq[3 * k + m] = grp[k][m];
+    Partition p;
+    for (int k = 0; k < 3; ++k)
+      for (int m = 0; m < 3; ++m) p.grp[k][m] = k < A ? grp[k][m] : -1;
+    p.sign = parity(seq, 3 * A) * (((A * (A - 1) / 2) & 1) ? -1 : 1);
+    out->push_back(p);
+    return;
+  }
+  const uint8_t q1 = family[i] == MBC_FAMILY_P ? kFlavU : kFlavD;
+  const uint8_t q2 = family[i] == MBC_FAMILY_P ? kFlavD : kFlavU;
+  for (int a = 0; a < n; ++a) {
+    if (used[a] || flav[a] != q1) continue;
+    for (int c = a + 1; c < n; ++c) {
+      if (used[c] || flav[c] != q1) continue;
+      for (int y = 0; y < n; ++y) {
+        if (used[y] || flav[y] != q2) continue;
+        used[a] = used[c] = used[y] = true;
+        grp[i][0] = a;
+        grp[i][1] = y;
+        grp[i][2] = c;
+        enumerate(family, A, flav, n, i + 1, used, grp, out);
+        used[a] = used[c] = used[y] = false;
+      }
+    }
+  }
+}
+
+std::vector<Partition> partitions(const int* family, int A, const uint8_t* flav, int n) {
+  std::vector<Partition> out;
+  if (3 * A != n) return out;
+  bool used[12] = {};
+  int grp[3][3];
+  enumerate(family, A, flav, n, 0, used, grp, &out);
+  return out;
+}
+
+void check_desc(const mbc_block_corr_desc& d) {
+  if (d.op < MBC_OP_PROTON || d.op > MBC_OP_HE3_II) throw std::invalid_argument("unknown operator");
+  if (d.sign_mode != MBC_SIGNS_EXACT && d.sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
+  if (d.snk_spin < 0 || d.snk_spin > 3 || d.src_spin < 0 || d.src_spin > 3)
+    throw std::invalid_argument("spin index out of range");
+}
+
+int type_index(std::vector<BlockType>* types, int family, int proj, const int32_t* mom) {
+  for (size_t k = 0; k < types->size(); ++k) {
+    const BlockType& t = (*types)[k];
+    if (t.family == family && t.proj == proj && t.mom[0] == mom[0] && t.mom[1] == mom[1] && t.mom[2] == mom[2])
+      return int(k);
+  }
+  BlockType t;
+  t.family = family;
+  t.proj = proj;
+  for (int d = 0; d < 3; ++d) t.mom[d] = mom[d];
+  types->push_back(t);
+  return int(types->size()) - 1;
+}
+
+using Factors = std::array<int32_t, 3>;
+
+struct Pending {
+  Factors f;
+  Gauss w;
+};
+
+}  // namespace
+
+void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out) {
+  *out = BlockSet();
+  out->n_corr = n_corr;
+  out->den.assign(n_corr, 1);
+  out->corr_begin.assign(n_corr + 1, 0);
+  std::vector<std::vector<Pending>> per_corr(n_corr);
+  for (int c = 0; c < n_corr; ++c) {
+    const mbc_block_corr_desc& d = corrs[c];
+    check_desc(d);
+    int den = 1;
+    const std::vector<SinkProduct> prods = sink_products(d.op, d.snk_spin, d.sign_mode, &den);
+    const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, true);
+    out->den[c] = den;
+    const int A = prods.empty() ? 0 : prods[0].nb;
+    out->n_slots = std::max(out->n_slots, A);
+    std::vector<Pending> terms;
+    for (const SinkProduct& sp : prods) {
+      int family[3], type[3];
+      for (int i = 0; i < sp.nb; ++i) {
+        family[i] = sp.b[i].family;
+        type[i] = type_index(&out->types, sp.b[i].family, sp.b[i].proj, d.mom[i]);
+      }
+      if (src.empty()) continue;
+      // every canonical key has the same flavour sequence u..u d..d
+      const std::vector<Partition> parts = partitions(family, sp.nb, src[0].flav, src[0].n);
+      for (const Partition& P : parts) {
+        for (const FieldTerm& key : src) {
+          Pending t;
+          t.w = gmul(sp.coef, gconj(key.coef));
+          if (P.sign < 0) t.w = {-t.w.re, -t.w.im};
+          t.f = {-1, -1, -1};
+          for (int i = 0; i < sp.nb; ++i) {
+            const int a = key.idx[P.grp[i][0]], y = key.idx[P.grp[i][1]], cc = key.idx[P.grp[i][2]];
+            if (a >= cc) throw std::logic_error("like antiquarks of a canonical key out of order");
+            t.f[i] = ((type[i] * 4 + sp.b[i].spin) * 12 + a) * 144 + y * 12 + cc;
+          }
+          std::sort(t.f.begin(), t.f.begin() + sp.nb);
+          terms.push_back(t);
+        }
+      }
+    }
+    std::sort(terms.begin(), terms.end(), [](const Pending& x, const Pending& y) { return x.f < y.f; });
+    std::vector<Pending> merged;
+    for (size_t k = 0; k < terms.size();) {
+      Pending m = terms[k];
+      size_t e = k + 1;
+      for (; e < terms.size() && terms[e].f == m.f; ++e) {
+        m.w.re += terms[e].w.re;
+        m.w.im += terms[e].w.im;
+      }
+      if (m.w.re != 0 || m.w.im != 0) merged.push_back(m);
+      k = e;
+    }
+    per_corr[c].swap(merged);
+  }
+  for (int c = 0; c < n_corr; ++c) {
+    for (const Pending& t : per_corr[c]) {
+      for (int i = 0; i < out->n_slots; ++i) out->factor.push_back(t.f[i]);
+      out->corr.push_back(c);
+      out->num_re.push_back(t.w.re);
+      out->num_im.push_back(t.w.im);
+    }
+    out->corr_begin[c + 1] = int64_t(out->corr.size());
+  }
+}
+
+void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
+  *out = BlockPlanHost();
+  out->n_types = int(s.types.size());
+  out->n_slots = s.n_slots;
+  out->n_corr = s.n_corr;
+  out->n_terms = int64_t(s.corr.size());
+  for (const BlockType& t : s.types) {
+    BlockTypeDev d;
+    d.family = t.family;
+    for (int k = 0; k < 3; ++k) d.mom[k] = t.mom[k];
+    int64_t re[16], im[16];
+    gamma_cg5(t.proj, re, im);
+    for (int e = 0; e < 16; ++e) {
+      if (re[e] == 0 && im[e] == 0) continue;
+      d.gidx[d.n_gamma] = e;
+      d.gval[d.n_gamma][0] = double(re[e]);
+      d.gval[d.n_gamma][1] = double(im[e]);
+      ++d.n_gamma;
+    }
+    out->types.push_back(d);
+    // B: 432 entries x (2 colour pairs x n_gamma products + one phase
+    // multiply); G: 48 x 144 entries x 3 colours, 8 flops per multiply-add
+    out->block_flops_per_site += 432.0 * (2.0 * d.n_gamma * 8.0 + 6.0) + 6912.0 * 3.0 * 8.0;
+  }
+  out->factor = s.factor;
+  out->coef.resize(size_t(out->n_terms) * 2);
+  for (int64_t k = 0; k < out->n_terms; ++k) {
+    const double den = double(s.den[s.corr[k]]);
+    out->coef[2 * k] = double(s.num_re[k]) / den;
+    out->coef[2 * k + 1] = double(s.num_im[k]) / den;
+    int used = 0;
+    for (int i = 0; i < s.n_slots; ++i) used += s.factor[k * s.n_slots + i] >= 0;
+    out->contract_flops_per_t += 6.0 * used + 2.0;
+  }
+  for (int c = 0; c < s.n_corr; ++c)
+    for (int64_t b = s.corr_begin[c]; b < s.corr_begin[c + 1]; b += kBlockTermChunk) {
+      out->chunks.push_back(c);
+      out->chunks.push_back(int32_t(b));
+      out->chunks.push_back(int32_t(std::min<int64_t>(b + kBlockTermChunk, s.corr_begin[c + 1])));
+    }
+}
+
+bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64_t* n_terms, int64_t* n_distinct,
+                          std::vector<int64_t>* hist) {
+  check_desc(d);
+  int den = 1;
+  const std::vector<SinkProduct> prods = sink_products(d.op, d.snk_spin, d.sign_mode, &den);
+  const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, false);
+  // partitions depend on the slots' families and the source term's flavour
+  // sequence only: count the expansion before forming any string
+  std::unordered_map<uint64_t, std::vector<Partition>> cache;
+  int64_t total = 0;
+  for (size_t p = 0; p < prods.size(); ++p) {
+    int family[3];
+    uint64_t fkey = 0;
+    for (int i = 0; i < prods[p].nb; ++i) {
+      family[i] = prods[p].b[i].family;
+      fkey = fkey * 2 + uint64_t(family[i]);
+    }
+    for (size_t s = 0; s < src.size(); ++s) {
+      uint64_t key = fkey;
+      for (int i = 0; i < src[s].n; ++i) key = key * 2 + src[s].flav[i];
+      key = key * 16 + uint64_t(prods[p].nb);
+      auto it = cache.find(key);
+      if (it == cache.end()) it = cache.emplace(key, partitions(family, prods[p].nb, src[s].flav, src[s].n)).first;
+      total += int64_t(it->second.size());
+    }
+  }
+  *n_terms = total;
+  if (total > max_terms) return false;
+  // hadron (family, projector) and momentum of a slot -> small id
+  std::vector<BlockType> ids;
+  std::vector<Factors> strings;
+  strings.reserve(size_t(total));
+  for (const SinkProduct& sp : prods) {
+    int family[3], id[3];
+    uint64_t fkey = 0;
+    for (int i = 0; i < sp.nb; ++i) {
+      family[i] = sp.b[i].family;
+      fkey = fkey * 2 + uint64_t(family[i]);
+      id[i] = type_index(&ids, sp.b[i].family, sp.b[i].proj, d.mom[i]);
+    }
+    for (const FieldTerm& t : src) {
+      uint64_t key = fkey;
+      for (int i = 0; i < t.n; ++i) key = key * 2 + t.flav[i];
+      key = key * 16 + uint64_t(sp.nb);
+      for (const Partition& P : cache.at(key)) {
+        Factors f = {-1, -1, -1};
+        for (int i = 0; i < sp.nb; ++i) {
+          const int a = t.idx[P.grp[i][0]], y = t.idx[P.grp[i][1]], cc = t.idx[P.grp[i][2]];
+          f[i] = (((id[i] * 12 + a) * 12 + y) * 12 + cc) * 4 + sp.b[i].spin;
+        }
+        std::sort(f.begin(), f.begin() + sp.nb);
+        strings.push_back(f);
+      }
+    }
+  }
+  std::sort(strings.begin(), strings.end());
+  hist->assign(1, 0);
+  int64_t distinct = 0;
+  for (size_t k = 0; k < strings.size();) {
+    size_t e = k + 1;
+    while (e < strings.size() && strings[e] == strings[k]) ++e;
+    const size_t m = e - k;
+    if (hist->size() <= m) hist->resize(m + 1, 0);
+    ++(*hist)[m];
+    ++distinct;
+    k = e;
+  }
+  *n_distinct = distinct;
+  return true;
+}
+
+}  // namespace mbc

@@ -150,23 +150,28 @@ Term concat(const Term& a, const Term& b, G extra) {
   return t;
 }
 
-// Written terms of an operator (before flavour separation) and s^2 denominator.
-std::vector<Term> operator_terms(int op, int spin, int sign_mode, int* den) {
-  std::vector<Product> prods;
+// The written products X^T (C gamma5) Y [Z^j] of a multi-baryon operator of
+// eq. "ops" with their relative signs, and the s^2 denominator.
+std::vector<Product> written_products(int op, int* den) {
   *den = 1;
   switch (op) {
-    case MBC_OP_PROTON: return baryon(true, 0, spin);
-    case MBC_OP_NEUTRON: return baryon(false, 0, spin);
-    case MBC_OP_DI: prods = {{+1, 2, {N, P}}}; break;
-    case MBC_OP_DII: prods = {{+1, 2, {N, P}}, {-1, 2, {P, N}}}; *den = 2; break;
-    case MBC_OP_HE3_I: prods = {{+1, 3, {PM, NP, PP}}}; break;
+    case MBC_OP_DI: return {{+1, 2, {N, P}}};
+    case MBC_OP_DII: *den = 2; return {{+1, 2, {N, P}}, {-1, 2, {P, N}}};
+    case MBC_OP_HE3_I: return {{+1, 3, {PM, NP, PP}}};
     case MBC_OP_HE3_II:
-      prods = {{+1, 3, {PM, NP, PP}}, {-1, 3, {PP, NP, PM}}, {+1, 3, {NP, PP, PM}},
-               {-1, 3, {NP, PM, PP}}, {+1, 3, {PP, PM, NP}}, {-1, 3, {PM, PP, NP}}};
       *den = 6;
-      break;
+      return {{+1, 3, {PM, NP, PP}}, {-1, 3, {PP, NP, PM}}, {+1, 3, {NP, PP, PM}},
+              {-1, 3, {NP, PM, PP}}, {+1, 3, {PP, PM, NP}}, {-1, 3, {PM, PP, NP}}};
     default: throw std::invalid_argument("unknown operator");
   }
+}
+
+// Written terms of an operator (before flavour separation) and s^2 denominator.
+std::vector<Term> operator_terms(int op, int spin, int sign_mode, int* den) {
+  *den = 1;
+  if (op == MBC_OP_PROTON) return baryon(true, 0, spin);
+  if (op == MBC_OP_NEUTRON) return baryon(false, 0, spin);
+  const std::vector<Product> prods = written_products(op, den);
   const M4 gm = cg5(0);
   std::vector<Term> out;
   for (const Product& pr : prods) {
@@ -284,7 +289,98 @@ KeyList make_keys(int op, int spin, int sign_mode, bool sym, int* nu, int* nd, i
   return kl;
 }
 
+BaryonSlot slot_of(BaryonName b, int spin) {
+  BaryonSlot x;
+  x.family = b.proton ? MBC_FAMILY_P : MBC_FAMILY_N;
+  x.proj = b.proj;
+  x.spin = spin;
+  return x;
+}
+
 }  // namespace
+
+std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den) {
+  if (sign_mode != MBC_SIGNS_EXACT && sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
+  if (spin < 0 || spin > 3) throw std::invalid_argument("spin index out of range");
+  std::vector<SinkProduct> out;
+  *den = 1;
+  if (op == MBC_OP_PROTON || op == MBC_OP_NEUTRON) {
+    SinkProduct p;
+    p.coef = {1, 0};
+    p.nb = 1;
+    p.b[0] = slot_of(op == MBC_OP_PROTON ? P : N, spin);
+    out.push_back(p);
+    return out;
+  }
+  const std::vector<Product> prods = written_products(op, den);
+  const M4 gm = cg5(0);
+  for (const Product& pr : prods) {
+    const int rel = (sign_mode == MBC_SIGNS_R2) ? 1 : pr.sign;
+    for (int al = 0; al < 4; ++al)
+      for (int be = 0; be < 4; ++be) {
+        G g = gm[al][be];
+        if (gzero(g)) continue;
+        if (rel < 0) g = gneg(g);
+        SinkProduct sp;
+        sp.coef = {g.re, g.im};
+        sp.nb = pr.nb;
+        sp.b[0] = slot_of(pr.b[0], al);
+        sp.b[1] = slot_of(pr.b[1], be);
+        if (pr.nb == 3) sp.b[2] = slot_of(pr.b[2], spin);
+        out.push_back(sp);
+      }
+  }
+  return out;
+}
+
+std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical_form) {
+  if (sign_mode != MBC_SIGNS_EXACT && sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
+  if (spin < 0 || spin > 3) throw std::invalid_argument("spin index out of range");
+  int den = 1;
+  const std::vector<Term> terms = operator_terms(op, spin, sign_mode, &den);
+  std::vector<FieldTerm> out;
+  if (!canonical_form) {
+    out.reserve(terms.size());
+    for (const Term& t : terms) {
+      FieldTerm f;
+      f.coef = {t.coef.re, t.coef.im};
+      f.n = t.n;
+      for (int i = 0; i < t.n; ++i) {
+        f.flav[i] = t.flav[i];
+        f.idx[i] = t.idx[i];
+      }
+      out.push_back(f);
+    }
+    return out;
+  }
+  int nu = 0, nd = 0;
+  for (auto& kv : canonical(separate(terms, &nu, &nd))) {
+    FieldTerm f;
+    f.coef = {kv.second.re, kv.second.im};
+    const Key& u = kv.first.first;
+    const Key& d = kv.first.second;
+    f.n = u.n + d.n;
+    for (int i = 0; i < u.n; ++i) {
+      f.flav[i] = kFlavU;
+      f.idx[i] = u.v[i];
+    }
+    for (int i = 0; i < d.n; ++i) {
+      f.flav[u.n + i] = kFlavD;
+      f.idx[u.n + i] = d.v[i];
+    }
+    out.push_back(f);
+  }
+  return out;
+}
+
+void gamma_cg5(int proj, int64_t re[16], int64_t im[16]) {
+  const M4 m = cg5(proj);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      re[4 * i + j] = m[i][j].re;
+      im[4 * i + j] = m[i][j].im;
+    }
+}
 
 bool operator<(const Key& a, const Key& b) {
   if (a.n != b.n) return a.n < b.n;

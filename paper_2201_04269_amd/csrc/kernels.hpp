@@ -41,4 +41,17 @@ hipError_t launch_backward_ds(const mbc_plan* p, const void* S_u, const void* S_
                               const void* W_plan, const double* grad_C, void* grad_S_u, void* grad_S_d,
                               hipStream_t st);
 
+// Hadron blocks: per timeslice and block type, chunks of nch sites; the
+// partial G matrices of the chunks live in the workspace.
+struct BlockLaunch {
+  int nch = 1;        // site chunks per timeslice
+  int64_t chunk = 1;  // sites per chunk
+};
+BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V);
+size_t block_workspace_bytes(const BlockPlanHost& h, int T, int64_t V);
+hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S_d, int s_c64, int T,
+                         const int32_t dims[3], double* blocks, void* workspace, hipStream_t st);
+hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, int T, double* C, void* workspace,
+                                 hipStream_t st);
+
 }  // namespace mbc

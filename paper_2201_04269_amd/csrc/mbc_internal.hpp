@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/mbc.h"
+#include "../../include/mbc_blocks.h"
 
 namespace mbc {
 
@@ -35,6 +36,62 @@ struct IndexSet {
 };
 
 void build_index_set(const mbc_op_desc* ops, int n_corr, IndexSet* out);
+
+// ---------------------------------------------------------------------------
+// Operator algebra used by the block-level expansion (index_set.cpp).
+struct Gauss {  // Gaussian integer
+  int64_t re = 0, im = 0;
+};
+enum : uint8_t { kFlavU = 0, kFlavD = 1 };
+// One baryon of a written product: family (MBC_FAMILY_P: q1 = u, q2 = d;
+// MBC_FAMILY_N: q1 = d, q2 = u), projector (0, +1, -1) of its Gamma, open spin.
+struct BaryonSlot {
+  int family = 0, proj = 0, spin = 0;
+};
+// The sink operator as sum coef * prod_i B_i: coef is the written relative
+// sign (+1 under MBC_SIGNS_R2) times (C gamma5)_{alpha beta} of the first two
+// baryons; the third baryon (3He) carries the open index j.
+struct SinkProduct {
+  Gauss coef;
+  int nb = 0;
+  BaryonSlot b[3];
+};
+std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den);
+// A source operator term: coefficient (not conjugated) and n antiquark
+// fields (flavour, index).  canonical: the sorted keys u..u d..d of eq. 1's
+// index set (flavour-separation and sorting signs in the coefficient);
+// otherwise the written terms in written field order.
+struct FieldTerm {
+  Gauss coef;
+  int n = 0;
+  uint8_t flav[12];
+  uint8_t idx[12];
+};
+std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical);
+// Entries (re, im) of C gamma5 (proj 0) or C gamma5 P+- (proj +-1), row-major 4x4.
+void gamma_cg5(int proj, int64_t re[16], int64_t im[16]);
+
+// ---------------------------------------------------------------------------
+// Block-level correlators (block_set.cpp): types and merged product terms.
+struct BlockType {
+  int family = 0, proj = 0;
+  int mom[3] = {0, 0, 0};
+};
+struct BlockSet {
+  int n_corr = 0, n_slots = 0;
+  std::vector<BlockType> types;
+  std::vector<int32_t> factor;         // [n_terms][n_slots], -1 in unused slots
+  std::vector<int32_t> corr;           // [n_terms]
+  std::vector<int64_t> num_re, num_im; // [n_terms]
+  std::vector<int64_t> den;            // [n_corr]
+  std::vector<int64_t> corr_begin;     // [n_corr + 1]
+};
+void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out);
+// Sec. 3 multiplicity count of one correlator (see mbc_block_multiplicities);
+// hist[m] for every multiplicity m up to the largest.  Returns false, with
+// only *n_terms set, when the expansion has more than max_terms terms.
+bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64_t* n_terms,
+                          int64_t* n_distinct, std::vector<int64_t>* hist);
 
 // ---------------------------------------------------------------------------
 // Plan layout (all int32 unless noted), mirrored to the device.
@@ -173,6 +230,27 @@ struct PlanDevice {
   int32_t* w_meta = nullptr;
 };
 
+// Block plan: per block type the non-zero entries of its Gamma and its
+// momentum (read by every workgroup of the block kernel), the terms as
+// factor indices and FP64 weights, and term chunks of one correlator each.
+struct BlockTypeDev {
+  int32_t family = 0, n_gamma = 0;
+  int32_t mom[3] = {0, 0, 0};
+  int32_t gidx[16] = {};     // beta * 4 + gamma of each non-zero entry
+  double gval[16][2] = {};   // the entry (re, im)
+};
+constexpr int kBlockTermChunk = 4096;  // terms per workgroup of the contraction
+struct BlockPlanHost {
+  int n_types = 0, n_slots = 0, n_corr = 0;
+  int64_t n_terms = 0;
+  std::vector<BlockTypeDev> types;
+  std::vector<int32_t> factor;   // [n_terms][n_slots]
+  std::vector<double> coef;      // [n_terms][2]
+  std::vector<int32_t> chunks;   // [n_chunks][3]: correlator, first term, end term
+  double block_flops_per_site = 0, contract_flops_per_t = 0;
+};
+void compile_block_plan(const BlockSet& s, BlockPlanHost* out);
+
 void set_error(const std::string& msg);
 
 }  // namespace mbc
@@ -184,5 +262,18 @@ struct mbc_index_set {
 struct mbc_plan {
   mbc::PlanHost h;
   mbc::PlanDevice d;
+  int device = 0;
+};
+
+struct mbc_block_set {
+  mbc::BlockSet s;
+};
+
+struct mbc_block_plan {
+  mbc::BlockPlanHost h;
+  mbc::BlockTypeDev* types = nullptr;
+  int32_t* factor = nullptr;
+  double* coef = nullptr;
+  int32_t* chunks = nullptr;
   int device = 0;
 };

@@ -235,19 +235,17 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
     tr[16] = sk[0];
     std::vector<RowId> order(rowset.begin(), rowset.end());
     std::map<RowId, int> op_index;
-    int n_ops = 0, phase = -1, cur_level = 0, item = 0;
+    int n_ops = 0, phase = -1, cur_level = 0;
     for (auto& r : order) {
       if (r.k != cur_level) {
         ++phase;
         if (phase >= 5) throw std::runtime_error("too many phases (at most five levels of rows per tile)");
         tr[8 + phase] = n_ops;
         cur_level = r.k;
-        item = 0;
       }
       if (tr[21 + 2 * (7 * r.f + r.k)] == 0) tr[20 + 2 * (7 * r.f + r.k)] = n_ops;
       ++tr[21 + 2 * (7 * r.f + r.k)];
       op_index[r] = n_ops;
-      item += X.ncol(r.f, r.k);
       ++n_ops;
       if (r.k >= 2 && o.exec) *o.exec += double(X.ncol(r.f, r.k)) * (8.0 * r.k - 2.0);
     }

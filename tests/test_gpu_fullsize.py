@@ -259,3 +259,37 @@ def test_autograd_example_from_the_readme():
     scl = CO.gradient_abs_scales(Su, Sd, rs, gC)
     err = np.abs(W.grad.cpu().numpy() - ref["W"])
     assert np.all(err <= np.maximum(kappa(3, 3) * 2.0 ** -53 * scl["W"], 1e-12 * np.abs(ref["W"])) + 1e-300)
+
+
+def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
+    # the bench's block leg: D_I and D_II (R2) at relative momentum 0 and
+    # +-(1, 0, 0), on the di_mixed lattice and propagators, sampled sites only
+    import bench
+    from oracle import blocks as OB
+    api = _api()
+    L, T = 16, 32
+    V = L ** 3
+    corrs = bench.block_corrs("di_mixed")
+    Su, Sd = synth.iid(T, V, seed=3)
+    picks = picks_for(T, V, n_t=3, per_t=2, seed=17)
+    Su, Sd = keep_sites(Su, Sd, picks)
+    bset = api.BlockSet(corrs)
+    plan = api.BlockPlan(bset)
+    su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
+    C, blk = api.block_correlators(plan, su, sd, (L, L, L))
+    torch.cuda.synchronize()
+    C = C.cpu().numpy()
+    blk = blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
+    names = {("p", 0): "p", ("n", 0): "n"}
+    sites = [t * V + v for t, v in picks]
+    ref = {(names[(f, p)], m): OB.block(Su, Sd, names[(f, p)], m, (L, L, L), sites=sites)
+           for f, p, m in bset.types()}
+    for k, (f, p, m) in enumerate(bset.types()):
+        want = ref[(names[(f, p)], m)]
+        scale = np.abs(want).max()
+        assert np.abs(blk[:, k] - want).max() <= 1e-13 * len(picks) * scale
+    for c, corr in enumerate(corrs):
+        want = OB.block_correlator(Su, Sd, corr["op"], 0, 0, corr["sign_mode"], corr["moms"], (L, L, L),
+                                   blocks=ref)
+        err = np.abs(C[c] - want)
+        assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
