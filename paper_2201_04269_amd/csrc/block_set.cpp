@@ -194,13 +194,16 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
     for (int k = 0; k < 3; ++k) d.mom[k] = t.mom[k];
     int64_t re[16], im[16];
     gamma_cg5(t.proj, re, im);
-    for (int e = 0; e < 16; ++e) {
-      if (re[e] == 0 && im[e] == 0) continue;
-      d.gidx[d.n_gamma] = e;
-      d.gval[d.n_gamma][0] = double(re[e]);
-      d.gval[d.n_gamma][1] = double(im[e]);
-      ++d.n_gamma;
-    }
+    for (int be = 0; be < 4; ++be)
+      for (int ga = 0; ga < 4; ++ga) {
+        const int e = 4 * be + ga;
+        if (re[e] == 0 && im[e] == 0) continue;
+        if (im[e] != 0 || (re[e] != 1 && re[e] != -1) || d.gcol[be] >= 0)
+          throw std::logic_error("Gamma row with more than one entry or an entry other than +-1");
+        d.gcol[be] = ga;
+        d.gsign[be] = double(re[e]);
+        ++d.n_gamma;
+      }
     out->types.push_back(d);
     // B: 432 entries x (2 colour pairs x n_gamma products + one phase
     // multiply); G: 48 x 144 entries x 3 colours, 8 flops per multiply-add

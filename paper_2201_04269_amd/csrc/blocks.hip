@@ -36,6 +36,7 @@ using dev::cmul;
 
 constexpr int kBT = 256;          // threads per workgroup of the block kernels
 constexpr int kBlockEntries = 6912;  // 4 x 12 x 12 x 12 per block type and timeslice
+constexpr int kBlockSitesPerRound = 2;
 
 __device__ __forceinline__ double2 load_c(const double2* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ double2 load_c(const float2* p, int64_t i) {
@@ -55,10 +56,10 @@ struct BlockGArgs {
   int L1, L2, L3;
 };
 
-// e^{-i p.x} at site v: p.x = 2 pi k / (L1 L2 L3) with k reduced exactly in
-// integers before the (correctly scaled) sincospi.
-__device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int64_t v, int L1, int L2, int L3) {
-  const int64_t x1 = v % L1, x2 = (v / L1) % L2, x3 = v / (int64_t(L1) * L2);
+// e^{-i p.x} at site v of a timeslice: p.x = 2 pi k / (L1 L2 L3) with k
+// reduced exactly in integers before the (correctly scaled) sincospi.
+__device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int v, int L1, int L2, int L3) {
+  const int x1 = v % L1, x2 = (v / L1) % L2, x3 = v / (L1 * L2);
   const int64_t n1 = ((int64_t(bt.mom[0]) * x1) % L1 + L1) % L1;
   const int64_t n2 = ((int64_t(bt.mom[1]) * x2) % L2 + L2) % L2;
   const int64_t n3 = ((int64_t(bt.mom[2]) * x3) % L3 + L3) % L3;
@@ -69,9 +70,11 @@ __device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int64_t v,
   return make_double2(c, -s);
 }
 
-template <typename SIN>
+// NS sites per round: their propagators and B matrices share the round's
+// three barriers.
+template <typename SIN, int NS>
 __global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
-  __shared__ double2 sS1[144], sS2[144], sB[432];
+  __shared__ double2 sS1[NS][144], sS2[NS][144], sB[NS][432], sPh[kBlockMaxChunk];
   const int ch = blockIdx.x, t = blockIdx.y, ty = blockIdx.z;
   const BlockTypeDev& bt = a.types[ty];
   const SIN* S1 = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_u : a.S_d);
@@ -88,58 +91,79 @@ __global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[m][k] = make_double2(0.0, 0.0);
 
-  // the 288 entries of a site: thread tid holds entry tid (S1 for tid < 144,
-  // else S2) and, for tid < 32, S2 entry tid + 112
-  double2 p0 = make_double2(0.0, 0.0), p1 = make_double2(0.0, 0.0);
+  // the 288 NS entries of a round (S1 then S2 of each site), NL per thread;
+  // sites past the chunk's end read as zero (their B vanishes)
+  constexpr int NE = 288 * NS;
+  constexpr int NL = (NE + kBT - 1) / kBT;
+  double2 pre[NL];
   auto fetch = [&](int64_t v) {
-    const int64_t s = (site0 + v) * 144;
-    p0 = tid < 144 ? load_c(S1, s + tid) : load_c(S2, s + tid - 144);
-    if (tid < 32) p1 = load_c(S2, s + tid + 112);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = tid + k * kBT;
+      pre[k] = make_double2(0.0, 0.0);
+      if (e < NE) {
+        const int s = e / 288, r = e % 288;
+        if (v + s < v1) {
+          const int64_t base = (site0 + v + s) * 144;
+          pre[k] = r < 144 ? load_c(S1, base + r) : load_c(S2, base + r - 144);
+        }
+      }
+    }
   };
   if (v0 < v1) fetch(v0);
+  // the chunk's phases, once (visible after the loop's first barrier)
+  for (int k = tid; k < int(v1 - v0); k += kBT) sPh[k] = site_phase(bt, int(v0) + k, a.L1, a.L2, a.L3);
 
-  for (int64_t v = v0; v < v1; ++v) {
-    if (tid < 144)
-      sS1[tid] = p0;
-    else
-      sS2[tid - 144] = p0;
-    if (tid < 32) sS2[tid + 112] = p1;
+  for (int64_t v = v0; v < v1; v += NS) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = tid + k * kBT;
+      if (e < NE) {
+        const int s = e / 288, r = e % 288;
+        if (r < 144)
+          sS1[s][r] = pre[k];
+        else
+          sS2[s][r - 144] = pre[k];
+      }
+    }
     __syncthreads();
-    if (v + 1 < v1) fetch(v + 1);
+    if (v + NS < v1) fetch(v + NS);
 
-    const double2 ph = site_phase(bt, v, a.L1, a.L2, a.L3);
-    for (int e = tid; e < 432; e += kBT) {
-      const int c = e / 144, X = (e / 12) % 12, Y = e % 12;
+    for (int e = tid; e < 432 * NS; e += kBT) {
+      const int s = e / 432, r = e % 432;
+      const int c = r / 144, X = (r / 12) % 12, Y = r % 12;
+      // (a, b, c) cyclic (eps = +1) and anticyclic (eps = -1)
+      const int a1 = c == 2 ? 0 : c + 1, b1 = c == 0 ? 2 : c - 1;
       double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int pr = 0; pr < 2; ++pr) {
-        // (a, b, c) cyclic: eps = +1; anticyclic: eps = -1
-        const int aa = pr == 0 ? (c + 1) % 3 : (c + 2) % 3;
-        const int bb = pr == 0 ? (c + 2) % 3 : (c + 1) % 3;
-        double2 part = make_double2(0.0, 0.0);
-        for (int g = 0; g < bt.n_gamma; ++g) {
-          const int be = bt.gidx[g] >> 2, ga = bt.gidx[g] & 3;
-          const double2 prod = cmul(sS1[(4 * aa + be) * 12 + X], sS2[(4 * bb + ga) * 12 + Y]);
-          part = cmac(make_double2(bt.gval[g][0], bt.gval[g][1]), prod, part);
-        }
-        sum = pr == 0 ? cadd(sum, part) : csub(sum, part);
+      for (int be = 0; be < 4; ++be) {
+        const int ga = bt.gcol[be];
+        if (ga < 0) continue;
+        double2 d = cmul(sS1[s][(4 * a1 + be) * 12 + X], sS2[s][(4 * b1 + ga) * 12 + Y]);
+        d = dev::cmsub(sS1[s][(4 * b1 + be) * 12 + X], sS2[s][(4 * a1 + ga) * 12 + Y], d);
+        const double sg = bt.gsign[be];
+        sum.x = fma(sg, d.x, sum.x);
+        sum.y = fma(sg, d.y, sum.y);
       }
-      sB[e] = cmul(sum, ph);
+      const double2 ph = v + s < v1 ? sPh[v + s - v0] : make_double2(0.0, 0.0);
+      sB[s][r] = cmul(sum, ph);
     }
     __syncthreads();
 
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double2 av[3], bv[9];
+    for (int s = 0; s < NS; ++s)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) av[m] = sS1[48 * c + i + 16 * m];
+      for (int c = 0; c < 3; ++c) {
+        double2 av[3], bv[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) bv[k] = sB[144 * c + j + 16 * k];
+        for (int m = 0; m < 3; ++m) av[m] = sS1[s][48 * c + i + 16 * m];
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
+        for (int k = 0; k < 9; ++k) bv[k] = sB[s][144 * c + j + 16 * k];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[m][k] = cmac(av[m], bv[k], acc[m][k]);
-    }
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) acc[m][k] = cmac(av[m], bv[k], acc[m][k]);
+      }
     __syncthreads();
   }
 
@@ -180,29 +204,47 @@ struct ContractArgs {
   int n_types, T;
 };
 
+// Each thread reads a term (weight and factor indices) once and applies it to
+// kContractT timeslices, whose blocks sit side by side in L2.
+constexpr int kContractT = 8;
+
 template <int NS>
 __global__ __launch_bounds__(kBT) void block_contract_kernel(ContractArgs a) {
-  __shared__ double2 red[kBT];
-  const int ch = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+  __shared__ double2 red[kContractT][kBT];
+  const int ch = blockIdx.x, t0 = blockIdx.y * kContractT, tid = threadIdx.x;
+  const int nt = a.T - t0 < kContractT ? a.T - t0 : kContractT;
   const int b = a.chunks[3 * ch + 1], e = a.chunks[3 * ch + 2];
-  const double2* bt = a.blocks + int64_t(t) * a.n_types * kBlockEntries;
-  double2 sum = make_double2(0.0, 0.0);
-  for (int k = b + tid; k < e; k += kBT) {
-    double2 p = a.coef[k];
+  const int64_t tstride = int64_t(a.n_types) * kBlockEntries;
+  const double2* bt = a.blocks + int64_t(t0) * tstride;
+  double2 sum[kContractT];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int f = a.factor[int64_t(k) * NS + s];
-      if (f >= 0) p = cmul(p, bt[f]);
+  for (int u = 0; u < kContractT; ++u) sum[u] = make_double2(0.0, 0.0);
+  for (int k = b + tid; k < e; k += kBT) {
+    const double2 w = a.coef[k];
+    int f[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) f[s] = a.factor[int64_t(k) * NS + s];
+#pragma unroll
+    for (int u = 0; u < kContractT; ++u) {
+      if (u < nt) {
+        double2 p = w;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (f[s] >= 0) p = cmul(p, bt[u * tstride + f[s]]);
+        sum[u] = cadd(sum[u], p);
+      }
     }
-    sum = cadd(sum, p);
   }
-  red[tid] = sum;
+#pragma unroll
+  for (int u = 0; u < kContractT; ++u) red[u][tid] = sum[u];
   __syncthreads();
   for (int w = kBT / 2; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = cadd(red[tid], red[tid + w]);
+    if (tid < w)
+#pragma unroll
+      for (int u = 0; u < kContractT; ++u) red[u][tid] = cadd(red[u][tid], red[u][tid + w]);
     __syncthreads();
   }
-  if (tid == 0) a.partial[int64_t(ch) * a.T + t] = red[0];
+  if (tid < nt) a.partial[int64_t(ch) * a.T + t0 + tid] = red[tid][0];
 }
 
 __global__ __launch_bounds__(kBT) void block_finish_kernel(const double2* __restrict__ partial,
@@ -225,6 +267,7 @@ BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V) {
   BlockLaunch L;
   const int64_t per = int64_t(T) * std::max(h.n_types, 1);
   int64_t nch = (1536 + per - 1) / per;
+  nch = std::max<int64_t>(nch, (V + kBlockMaxChunk - 1) / kBlockMaxChunk);
   if (nch > V) nch = V;
   if (nch < 1) nch = 1;
   L.chunk = (V + nch - 1) / nch;
@@ -259,9 +302,9 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
   a.L3 = dims[2];
   const dim3 grid(static_cast<unsigned>(L.nch), static_cast<unsigned>(T), static_cast<unsigned>(h.n_types));
   if (s_c64)
-    hipLaunchKernelGGL(block_g_kernel<float2>, grid, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL((block_g_kernel<float2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
   else
-    hipLaunchKernelGGL(block_g_kernel<double2>, grid, dim3(kBT), 0, st, a);
+    hipLaunchKernelGGL((block_g_kernel<double2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(block_reduce_kernel, dim3(unsigned(T), unsigned(h.n_types)), dim3(kBT), 0, st,
@@ -283,7 +326,7 @@ hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, 
   a.partial = static_cast<double2*>(workspace);
   a.n_types = h.n_types;
   a.T = T;
-  const dim3 grid(static_cast<unsigned>(n_chunks), static_cast<unsigned>(T));
+  const dim3 grid(static_cast<unsigned>(n_chunks), static_cast<unsigned>((T + kContractT - 1) / kContractT));
   switch (h.n_slots) {
     case 1: hipLaunchKernelGGL(block_contract_kernel<1>, grid, dim3(kBT), 0, st, a); break;
     case 2: hipLaunchKernelGGL(block_contract_kernel<2>, grid, dim3(kBT), 0, st, a); break;

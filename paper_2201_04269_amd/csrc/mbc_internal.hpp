@@ -233,13 +233,17 @@ struct PlanDevice {
 // Block plan: per block type the non-zero entries of its Gamma and its
 // momentum (read by every workgroup of the block kernel), the terms as
 // factor indices and FP64 weights, and term chunks of one correlator each.
+// C gamma5 and C gamma5 P+- have at most one non-zero entry per row, a real
+// +-1 in the Dirac basis: row beta is (gcol[beta], gsign[beta]), gcol = -1 for
+// a zero row.
 struct BlockTypeDev {
   int32_t family = 0, n_gamma = 0;
   int32_t mom[3] = {0, 0, 0};
-  int32_t gidx[16] = {};     // beta * 4 + gamma of each non-zero entry
-  double gval[16][2] = {};   // the entry (re, im)
+  int32_t gcol[4] = {-1, -1, -1, -1};
+  double gsign[4] = {0, 0, 0, 0};
 };
 constexpr int kBlockTermChunk = 4096;  // terms per workgroup of the contraction
+constexpr int kBlockMaxChunk = 1024;   // sites per workgroup of the block kernel (LDS phase table)
 struct BlockPlanHost {
   int n_types = 0, n_slots = 0, n_corr = 0;
   int64_t n_terms = 0;
