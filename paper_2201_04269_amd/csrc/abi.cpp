@@ -488,7 +488,7 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     }
     auto release = [](mbc_block_plan* q) {
       for (void* ptr : {static_cast<void*>(q->types), static_cast<void*>(q->factor), static_cast<void*>(q->coef),
-                        static_cast<void*>(q->chunks)})
+                        static_cast<void*>(q->chunks), static_cast<void*>(q->corr_chunk)})
         if (ptr) (void)hipFree(ptr);
       delete q;
     };
@@ -499,7 +499,8 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     mbc_status st = MBC_OK;
     if ((st = upload(p->h.types, &p->types, hs)) != MBC_OK || (st = upload(p->h.factor, &p->factor, hs)) != MBC_OK ||
-        (st = upload(p->h.coef, &p->coef, hs)) != MBC_OK || (st = upload(p->h.chunks, &p->chunks, hs)) != MBC_OK) {
+        (st = upload(p->h.coef, &p->coef, hs)) != MBC_OK || (st = upload(p->h.chunks, &p->chunks, hs)) != MBC_OK ||
+        (st = upload(p->h.corr_chunk, &p->corr_chunk, hs)) != MBC_OK) {
       release(p);
       return st;
     }
@@ -536,7 +537,7 @@ void mbc_block_plan_destroy(mbc_block_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   for (void* ptr : {static_cast<void*>(p->types), static_cast<void*>(p->factor), static_cast<void*>(p->coef),
-                    static_cast<void*>(p->chunks)})
+                    static_cast<void*>(p->chunks), static_cast<void*>(p->corr_chunk)})
     if (ptr) (void)hipFree(ptr);
   delete p;
 }

@@ -18,6 +18,7 @@
 // products merged exactly (the canonical ordering with multiplicities of
 // Sec. 3).
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <stdexcept>
 #include <unordered_map>
@@ -219,12 +220,16 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
     for (int i = 0; i < s.n_slots; ++i) used += s.factor[k * s.n_slots + i] >= 0;
     out->contract_flops_per_t += 6.0 * used + 2.0;
   }
-  for (int c = 0; c < s.n_corr; ++c)
+  if (out->n_terms > INT32_MAX - kBlockTermChunk) throw std::domain_error("more than 2^31 block terms");
+  for (int c = 0; c < s.n_corr; ++c) {
+    out->corr_chunk.push_back(int32_t(out->chunks.size() / 3));
     for (int64_t b = s.corr_begin[c]; b < s.corr_begin[c + 1]; b += kBlockTermChunk) {
       out->chunks.push_back(c);
       out->chunks.push_back(int32_t(b));
       out->chunks.push_back(int32_t(std::min<int64_t>(b + kBlockTermChunk, s.corr_begin[c + 1])));
     }
+  }
+  out->corr_chunk.push_back(int32_t(out->chunks.size() / 3));
 }
 
 bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64_t* n_terms, int64_t* n_distinct,

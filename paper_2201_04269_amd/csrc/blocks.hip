@@ -176,23 +176,22 @@ __global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
 
 // blocks[t][type][alpha][A][Y][C] = sum over chunks (in order) of
 // G[(alpha, A)][(C, Y)] - G[(alpha, C)][(A, Y)]; exactly zero for A == C.
+// One thread per entry: grid (entry blocks of kBT, T, n_types).
 __global__ __launch_bounds__(kBT) void block_reduce_kernel(const double2* __restrict__ partial,
                                                            double2* __restrict__ blocks, int T, int n_types,
                                                            int nch) {
-  const int t = blockIdx.x, ty = blockIdx.y;
+  const int e = blockIdx.x * kBT + threadIdx.x, t = blockIdx.y, ty = blockIdx.z;
+  if (e >= kBlockEntries) return;
   const double2* P = partial + (int64_t(ty) * T + t) * nch * kBlockEntries;
-  double2* out = blocks + (int64_t(t) * n_types + ty) * kBlockEntries;
-  for (int e = threadIdx.x; e < kBlockEntries; e += kBT) {
-    const int al = e / 1728, A = (e / 144) % 12, Y = (e / 12) % 12, C = e % 12;
-    double2 s = make_double2(0.0, 0.0);
-    if (A != C) {
-      const int g1 = (al * 12 + A) * 144 + C * 12 + Y;
-      const int g2 = (al * 12 + C) * 144 + A * 12 + Y;
-      for (int ch = 0; ch < nch; ++ch) s = cadd(s, csub(P[int64_t(ch) * kBlockEntries + g1],
-                                                        P[int64_t(ch) * kBlockEntries + g2]));
-    }
-    out[e] = s;
+  const int al = e / 1728, A = (e / 144) % 12, Y = (e / 12) % 12, C = e % 12;
+  double2 s = make_double2(0.0, 0.0);
+  if (A != C) {
+    const int g1 = (al * 12 + A) * 144 + C * 12 + Y;
+    const int g2 = (al * 12 + C) * 144 + A * 12 + Y;
+    for (int ch = 0; ch < nch; ++ch)
+      s = cadd(s, csub(P[int64_t(ch) * kBlockEntries + g1], P[int64_t(ch) * kBlockEntries + g2]));
   }
+  blocks[(int64_t(t) * n_types + ty) * kBlockEntries + e] = s;
 }
 
 struct ContractArgs {
@@ -247,15 +246,16 @@ __global__ __launch_bounds__(kBT) void block_contract_kernel(ContractArgs a) {
   if (tid < nt) a.partial[int64_t(ch) * a.T + t0 + tid] = red[tid][0];
 }
 
+// C[c][t] = the chunks of correlator c (consecutive, from corr_chunk[c] to
+// corr_chunk[c + 1]) added in order.
 __global__ __launch_bounds__(kBT) void block_finish_kernel(const double2* __restrict__ partial,
-                                                           const int32_t* __restrict__ chunks, int n_chunks, int T,
+                                                           const int32_t* __restrict__ corr_chunk, int T,
                                                            int n_corr, double2* __restrict__ C) {
   const int idx = blockIdx.x * kBT + threadIdx.x;
   if (idx >= n_corr * T) return;
   const int c = idx / T, t = idx % T;
   double2 s = make_double2(0.0, 0.0);
-  for (int ch = 0; ch < n_chunks; ++ch)
-    if (chunks[3 * ch] == c) s = cadd(s, partial[int64_t(ch) * T + t]);
+  for (int ch = corr_chunk[c]; ch < corr_chunk[c + 1]; ++ch) s = cadd(s, partial[int64_t(ch) * T + t]);
   C[idx] = s;
 }
 
@@ -307,7 +307,9 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
     hipLaunchKernelGGL((block_g_kernel<double2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(block_reduce_kernel, dim3(unsigned(T), unsigned(h.n_types)), dim3(kBT), 0, st,
+  const dim3 rgrid(static_cast<unsigned>((kBlockEntries + kBT - 1) / kBT), static_cast<unsigned>(T),
+                   static_cast<unsigned>(h.n_types));
+  hipLaunchKernelGGL(block_reduce_kernel, rgrid, dim3(kBT), 0, st,
                      static_cast<const double2*>(workspace), reinterpret_cast<double2*>(blocks), T, h.n_types,
                      L.nch);
   return hipGetLastError();
@@ -337,7 +339,7 @@ hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, 
   if (e != hipSuccess) return e;
   const int n_out = h.n_corr * T;
   hipLaunchKernelGGL(block_finish_kernel, dim3(unsigned((n_out + kBT - 1) / kBT)), dim3(kBT), 0, st,
-                     static_cast<const double2*>(workspace), p->chunks, n_chunks, T, h.n_corr,
+                     static_cast<const double2*>(workspace), p->corr_chunk, T, h.n_corr,
                      reinterpret_cast<double2*>(C));
   return hipGetLastError();
 }

@@ -251,6 +251,7 @@ struct BlockPlanHost {
   std::vector<int32_t> factor;   // [n_terms][n_slots]
   std::vector<double> coef;      // [n_terms][2]
   std::vector<int32_t> chunks;   // [n_chunks][3]: correlator, first term, end term
+  std::vector<int32_t> corr_chunk;  // [n_corr + 1]: first chunk of each correlator
   double block_flops_per_site = 0, contract_flops_per_t = 0;
 };
 void compile_block_plan(const BlockSet& s, BlockPlanHost* out);
@@ -279,5 +280,6 @@ struct mbc_block_plan {
   int32_t* factor = nullptr;
   double* coef = nullptr;
   int32_t* chunks = nullptr;
+  int32_t* corr_chunk = nullptr;
   int device = 0;
 };
