@@ -23,6 +23,8 @@ blocks       Hadron blocks with sink momentum projection (Sec. 2), the
              block-level correlator by the partition sum of Wick's theorem
              (Sec. 3), a site-labelled determinant brute force that pins it,
              and the multiplicity count of the expanded form (Sec. 3, Fig. 2).
+factor_tree  Linearised factor trees (Sec. 4): prefix-tree construction of a
+             sum of products and its depth-first evaluation.
 
 Every function documents the passage it follows.  Where the paper is silent the
 reading used is stated in the docstring.
