@@ -106,28 +106,33 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup):
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        api.block_contract(plan, api.blocks(plan, su, sd, dims, workspace=ws), workspace=ws)
+        blk = api.blocks(plan, su, sd, dims, workspace=ws)
+        api.block_contract(plan, blk, method="tree", workspace=ws)
+        api.block_contract(plan, blk, method="terms", workspace=ws)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     for e in ev:
         e[0].record(stream)
         blk = api.blocks(plan, su, sd, dims, workspace=ws)
         e[1].record(stream)
-        api.block_contract(plan, blk, workspace=ws)
+        api.block_contract(plan, blk, method="tree", workspace=ws)
         e[2].record(stream)
+        api.block_contract(plan, blk, method="terms", workspace=ws)
+        e[3].record(stream)
     torch.cuda.synchronize()
     ms_b = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
-    ms_c = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    ms_tree = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    ms_terms = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
     flops_b = st["block_flops_per_site"] * T * V
-    flops_c = st["contract_flops_per_t"] * T
-    print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction {ms_c:.3f} ms",
-          file=sys.stderr, flush=True)
-    return {"correlators": len(corrs), "block_types": bset.n_types, "terms": bset.n_terms, "dtype": "f64",
-            "ms_blocks": ms_b, "ms_contract": ms_c, "sites_per_s": T * V / ((ms_b + ms_c) * 1e-3),
+    print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction by factor trees "
+          f"{ms_tree:.3f} ms, by terms {ms_terms:.3f} ms", file=sys.stderr, flush=True)
+    return {"correlators": len(corrs), "block_types": bset.n_types, "terms": bset.n_terms,
+            "tree_vertices": st["tree_vertices"], "dtype": "f64",
+            "ms_blocks": ms_b, "ms_contract_tree": ms_tree, "ms_contract_terms": ms_terms,
+            "sites_per_s": T * V / ((ms_b + ms_tree) * 1e-3),
             "roofline": {"bound": "alu", "kernel": "block_g", "achieved": flops_b / (ms_b * 1e-3) / 1e12,
                          "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
-                         "frac": flops_b / (ms_b * 1e-3) / PEAK["f64"]},
-            "contract_tflops": flops_c / (ms_c * 1e-3) / 1e12}
+                         "frac": flops_b / (ms_b * 1e-3) / PEAK["f64"]}}
 
 
 _W_ISET = None

@@ -48,6 +48,10 @@ extern "C" {
 
 /* baryon families of a block type */
 enum { MBC_FAMILY_P = 0, MBC_FAMILY_N = 1 };
+/* evaluation of the block-level terms: one product per term, or the
+ * correlator's linearised factor tree (Sec. 4: terms sharing their leading
+ * factors share those multiplications) */
+enum { MBC_BLOCK_TERMS = 0, MBC_BLOCK_TREE = 1 };
 
 typedef struct {
   int32_t op;         /* MBC_OP_* */
@@ -86,6 +90,18 @@ mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t*
  * den [n_corr]. */
 mbc_status mbc_block_set_export(const mbc_block_set* s, int32_t* factor, int32_t* corr_id, int64_t* num_re,
                                 int64_t* num_im, int64_t* den);
+/* Linearised factor tree (Sec. 4) of correlator `corr` of a block set: the
+ * prefix tree of its terms' factor strings in depth-first order, as the
+ * paper's three arrays.  factors[v] is the block factor of vertex v (-1 for
+ * the root, vertex 0), children[v] its number of children; the leaves, in
+ * depth-first order, are the correlator's terms in export order, so the
+ * coefficients array is that correlator's num_re/num_im over den.  The
+ * correlator's value is the sum over root-to-leaf paths of the leaf
+ * coefficient times the product of the factors on the path.  *n_vertices
+ * receives the vertex count; factors and children (caller-allocated host
+ * arrays of that length) may be NULL.  MBC_ERR_INVALID for a bad corr. */
+mbc_status mbc_block_set_factor_tree(const mbc_block_set* s, int32_t corr, int64_t* n_vertices, int32_t* factors,
+                                     int32_t* children);
 /* Frees a block set (NULL-safe). */
 void mbc_block_set_free(mbc_block_set* s);
 
@@ -115,6 +131,9 @@ typedef struct {
   double block_flops_per_site; /* per site, all types: per type 432 entries x (2 x nnz(Gamma)
                                   products + phase) + 6912 x 3 complex multiply-adds */
   double contract_flops_per_t; /* per timeslice: 8 per complex multiply or add of the terms */
+  int64_t tree_vertices;       /* factor-tree vertices over all correlators (roots included) */
+  double tree_flops_per_t;     /* per timeslice, factor trees: 8 per non-root vertex (its
+                                  factor times its children's sum, added into its parent) */
 } mbc_block_plan_stats;
 mbc_status mbc_block_plan_get_stats(const mbc_block_plan* p, mbc_block_plan_stats* out);
 
@@ -135,9 +154,10 @@ mbc_status mbc_blocks_compute(const mbc_block_plan* p, const void* S_u, const vo
                               size_t ws_bytes, void* stream);
 /* Block-level correlators from blocks (Sec. 3 expanded form).
  * blocks     device [T][n_types][4][1728] complex128 (mbc_blocks_compute)
+ * method     MBC_BLOCK_TERMS or MBC_BLOCK_TREE (same value up to rounding)
  * C          device output [n_corr][T] complex128
  * workspace  device, >= mbc_block_workspace_bytes(p, T, dims) */
-mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int32_t T, double* C,
+mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int32_t T, int32_t method, double* C,
                               void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus

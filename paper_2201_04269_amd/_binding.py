@@ -47,10 +47,12 @@ class BlockCorrDesc(ctypes.Structure):
 class BlockPlanStats(ctypes.Structure):
     _fields_ = [("n_types", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("n_corr", ctypes.c_int32),
                 ("n_terms", ctypes.c_int64), ("block_flops_per_site", ctypes.c_double),
-                ("contract_flops_per_t", ctypes.c_double)]
+                ("contract_flops_per_t", ctypes.c_double), ("tree_vertices", ctypes.c_int64),
+                ("tree_flops_per_t", ctypes.c_double)]
 
 
 FAMILIES = {0: "p", 1: "n"}
+BLOCK_METHODS = {"terms": 0, "tree": 1}
 
 _lib = None
 
@@ -77,6 +79,7 @@ SIGNATURES = [
                                   ctypes.POINTER(_I64)]),
     ("mbc_block_set_types", _I32, [_P, _P, _P, _P]),
     ("mbc_block_set_export", _I32, [_P] * 6),
+    ("mbc_block_set_factor_tree", _I32, [_P, _I32, ctypes.POINTER(_I64), _P, _P]),
     ("mbc_block_set_free", None, [_P]),
     ("mbc_block_multiplicities", _I32, [ctypes.POINTER(BlockCorrDesc), _I64, ctypes.POINTER(_I64),
                                         ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P, _I32]),
@@ -85,7 +88,7 @@ SIGNATURES = [
     ("mbc_block_workspace_bytes", _I32, [_P, _I32, _P, ctypes.POINTER(_SZ)]),
     ("mbc_block_plan_destroy", None, [_P]),
     ("mbc_blocks_compute", _I32, [_P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
-    ("mbc_block_contract", _I32, [_P, _P, _I32, _P, _P, _SZ, _P]),
+    ("mbc_block_contract", _I32, [_P, _P, _I32, _I32, _P, _P, _SZ, _P]),
 ]
 
 

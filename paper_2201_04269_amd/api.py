@@ -238,6 +238,18 @@ class BlockSet:
         B.check(B.lib().mbc_block_set_export(self._h, *ptr))
         return out
 
+    def factor_tree(self, corr):
+        """(factors, children) of correlator ``corr``'s linearised factor tree;
+        its leaves are the correlator's terms in export order."""
+        n = ctypes.c_int64()
+        B.check(B.lib().mbc_block_set_factor_tree(self._h, int(corr), ctypes.byref(n), None, None))
+        fac = np.zeros(n.value, np.int32)
+        ch = np.zeros(n.value, np.int32)
+        B.check(B.lib().mbc_block_set_factor_tree(self._h, int(corr), ctypes.byref(n),
+                                                  fac.ctypes.data_as(ctypes.c_void_p),
+                                                  ch.ctypes.data_as(ctypes.c_void_p)))
+        return fac, ch
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -302,19 +314,20 @@ def blocks(plan, S_u, S_d, dims, workspace=None, stream=None):
     return out
 
 
-def block_contract(plan, blk, workspace=None, stream=None):
-    """C [n_corr, T] complex128 from blocks (mbc_block_contract)."""
+def block_contract(plan, blk, method="tree", workspace=None, stream=None):
+    """C [n_corr, T] complex128 from blocks (mbc_block_contract); method
+    "tree" (linearised factor trees) or "terms" (one product per term)."""
     if not (blk.is_cuda and blk.dtype == torch.complex128 and blk.is_contiguous()):
         raise ValueError("blocks must be a contiguous CUDA complex128 tensor")
     T = blk.shape[0]
     C = torch.empty((plan.bset.n_corr, T), dtype=torch.complex128, device=blk.device)
     ws = workspace if workspace is not None else _workspace(plan, T, (1, 1, 1), blk.device)
-    B.check(B.lib().mbc_block_contract(plan._h, _ptr(blk), int(T), _ptr(C), _ptr(ws),
+    B.check(B.lib().mbc_block_contract(plan._h, _ptr(blk), int(T), B.BLOCK_METHODS[method], _ptr(C), _ptr(ws),
                                        ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
     return C
 
 
-def block_correlators(plan, S_u, S_d, dims, stream=None):
+def block_correlators(plan, S_u, S_d, dims, method="tree", stream=None):
     """(C [n_corr, T], blocks): the blocks of every type, then their contraction."""
     blk = blocks(plan, S_u, S_d, dims, stream=stream)
-    return block_contract(plan, blk, stream=stream), blk
+    return block_contract(plan, blk, method=method, stream=stream), blk

@@ -455,6 +455,17 @@ mbc_status mbc_block_set_export(const mbc_block_set* s, int32_t* factor, int32_t
   return MBC_OK;
 }
 
+mbc_status mbc_block_set_factor_tree(const mbc_block_set* s, int32_t corr, int64_t* n_vertices, int32_t* factors,
+                                     int32_t* children) {
+  if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
+  if (corr < 0 || corr >= s->s.n_corr) return fail(MBC_ERR_INVALID, "correlator index out of range");
+  const int64_t b = s->s.tree_vertex[corr], e = s->s.tree_vertex[corr + 1];
+  if (n_vertices) *n_vertices = e - b;
+  if (factors) std::copy(s->s.tree_factor.begin() + b, s->s.tree_factor.begin() + e, factors);
+  if (children) std::copy(s->s.tree_children.begin() + b, s->s.tree_children.begin() + e, children);
+  return MBC_OK;
+}
+
 void mbc_block_set_free(mbc_block_set* s) { delete s; }
 
 mbc_status mbc_block_multiplicities(const mbc_block_corr_desc* corr, int64_t max_terms, int64_t* n_terms,
@@ -488,7 +499,9 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     }
     auto release = [](mbc_block_plan* q) {
       for (void* ptr : {static_cast<void*>(q->types), static_cast<void*>(q->factor), static_cast<void*>(q->coef),
-                        static_cast<void*>(q->chunks), static_cast<void*>(q->corr_chunk)})
+                        static_cast<void*>(q->chunks), static_cast<void*>(q->corr_chunk),
+                        static_cast<void*>(q->tree_factor), static_cast<void*>(q->items),
+                        static_cast<void*>(q->corr_wg)})
         if (ptr) (void)hipFree(ptr);
       delete q;
     };
@@ -500,7 +513,9 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     mbc_status st = MBC_OK;
     if ((st = upload(p->h.types, &p->types, hs)) != MBC_OK || (st = upload(p->h.factor, &p->factor, hs)) != MBC_OK ||
         (st = upload(p->h.coef, &p->coef, hs)) != MBC_OK || (st = upload(p->h.chunks, &p->chunks, hs)) != MBC_OK ||
-        (st = upload(p->h.corr_chunk, &p->corr_chunk, hs)) != MBC_OK) {
+        (st = upload(p->h.corr_chunk, &p->corr_chunk, hs)) != MBC_OK ||
+        (st = upload(p->h.tree_factor, &p->tree_factor, hs)) != MBC_OK ||
+        (st = upload(p->h.items, &p->items, hs)) != MBC_OK || (st = upload(p->h.corr_wg, &p->corr_wg, hs)) != MBC_OK) {
       release(p);
       return st;
     }
@@ -522,6 +537,8 @@ mbc_status mbc_block_plan_get_stats(const mbc_block_plan* p, mbc_block_plan_stat
   out->n_terms = p->h.n_terms;
   out->block_flops_per_site = p->h.block_flops_per_site;
   out->contract_flops_per_t = p->h.contract_flops_per_t;
+  out->tree_vertices = p->h.tree_vertices;
+  out->tree_flops_per_t = p->h.tree_flops_per_t;
   return MBC_OK;
 }
 
@@ -537,7 +554,9 @@ void mbc_block_plan_destroy(mbc_block_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   for (void* ptr : {static_cast<void*>(p->types), static_cast<void*>(p->factor), static_cast<void*>(p->coef),
-                    static_cast<void*>(p->chunks), static_cast<void*>(p->corr_chunk)})
+                    static_cast<void*>(p->chunks), static_cast<void*>(p->corr_chunk),
+                    static_cast<void*>(p->tree_factor), static_cast<void*>(p->items),
+                    static_cast<void*>(p->corr_wg)})
     if (ptr) (void)hipFree(ptr);
   delete p;
 }
@@ -565,12 +584,13 @@ mbc_status mbc_blocks_compute(const mbc_block_plan* p, const void* S_u, const vo
   return MBC_OK;
 }
 
-mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int32_t T, double* C, void* workspace,
-                              size_t ws_bytes, void* stream) {
+mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int32_t T, int32_t method, double* C,
+                              void* workspace, size_t ws_bytes, void* stream) {
   if (!p) return fail(MBC_ERR_INVALID, "plan is NULL");
   if (T <= 0) return fail(MBC_ERR_INVALID, "T must be positive");
+  if (method != MBC_BLOCK_TERMS && method != MBC_BLOCK_TREE) return fail(MBC_ERR_INVALID, "unknown method");
   if (!is_device_ptr(C) || !aligned16(C)) return fail(MBC_ERR_INVALID, "C must be an aligned device pointer");
-  const size_t need = align256(size_t(p->h.chunks.size() / 3) * size_t(T) * 16);
+  const size_t need = block_contract_workspace_bytes(p->h, T);
   if (p->h.n_terms > 0) {
     if (!is_device_ptr(blocks) || !aligned16(blocks))
       return fail(MBC_ERR_INVALID, "blocks must be an aligned device pointer");
@@ -581,7 +601,7 @@ mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int
   int dev = -1;
   MBC_HIP(hipGetDevice(&dev));
   if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
-  MBC_HIP(launch_block_contract(p, blocks, T, C, workspace, reinterpret_cast<hipStream_t>(stream)));
+  MBC_HIP(launch_block_contract(p, blocks, T, method, C, workspace, reinterpret_cast<hipStream_t>(stream)));
   return MBC_OK;
 }
 

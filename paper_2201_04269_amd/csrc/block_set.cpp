@@ -19,6 +19,7 @@
 // Sec. 3).
 #include <algorithm>
 #include <climits>
+#include <functional>
 #include <array>
 #include <stdexcept>
 #include <unordered_map>
@@ -181,6 +182,35 @@ void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out
     }
     out->corr_begin[c + 1] = int64_t(out->corr.size());
   }
+  // Factor trees: the prefix tree of each correlator's sorted factor strings.
+  // A term shares its first p factors with the previous term and opens new
+  // vertices for the rest, so creation order is depth-first order and the
+  // leaves come in term order.
+  for (int c = 0; c < n_corr; ++c) {
+    out->tree_vertex.push_back(int64_t(out->tree_factor.size()));
+    const int32_t root = int32_t(out->tree_factor.size());
+    out->tree_factor.push_back(-1);
+    out->tree_children.push_back(0);
+    int32_t path[3] = {-1, -1, -1};
+    for (int64_t k = out->corr_begin[c]; k < out->corr_begin[c + 1]; ++k) {
+      const int32_t* f = &out->factor[size_t(k) * out->n_slots];
+      int A = 0;
+      while (A < out->n_slots && f[A] >= 0) ++A;
+      int p = 0;
+      if (k > out->corr_begin[c]) {
+        const int32_t* g = &out->factor[size_t(k - 1) * out->n_slots];
+        while (p < A && f[p] == g[p]) ++p;
+        if (p == A) throw std::logic_error("repeated factor string after merging");
+      }
+      for (int l = p; l < A; ++l) {
+        ++out->tree_children[l == 0 ? root : path[l - 1]];
+        path[l] = int32_t(out->tree_factor.size());
+        out->tree_factor.push_back(f[l]);
+        out->tree_children.push_back(0);
+      }
+    }
+  }
+  out->tree_vertex.push_back(int64_t(out->tree_factor.size()));
 }
 
 void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
@@ -220,6 +250,7 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
     for (int i = 0; i < s.n_slots; ++i) used += s.factor[k * s.n_slots + i] >= 0;
     out->contract_flops_per_t += 6.0 * used + 2.0;
   }
+  out->tree_flops_per_t = 8.0 * double(int64_t(s.tree_factor.size()) - s.n_corr);
   if (out->n_terms > INT32_MAX - kBlockTermChunk) throw std::domain_error("more than 2^31 block terms");
   for (int c = 0; c < s.n_corr; ++c) {
     out->corr_chunk.push_back(int32_t(out->chunks.size() / 3));
@@ -230,6 +261,88 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
     }
   }
   out->corr_chunk.push_back(int32_t(out->chunks.size() / 3));
+
+  // Factor-tree work items: the tree cut above its leaves.  Every vertex whose
+  // children are leaves (a leaf parent) gives runs of at most kTreeLeafRun of
+  // its leaves; an item also names the parent and grandparent (the factors
+  // its run shares).  Trees are at most kTreeMaxDepth levels deep, so these
+  // are all the factors of a path.
+  if (int64_t(s.tree_factor.size()) > INT32_MAX) throw std::domain_error("factor tree too large");
+  out->tree_factor = s.tree_factor;
+  out->tree_vertices = int64_t(s.tree_factor.size());
+  const std::vector<int32_t>& nch = s.tree_children;
+  std::vector<size_t> corr_items(s.n_corr + 1, 0);
+  for (int c = 0; c < s.n_corr; ++c) {
+    corr_items[c] = out->items.size() / kTreeItemInts;
+    const size_t first_item = corr_items[c];
+    const int64_t root = s.tree_vertex[c], vend = s.tree_vertex[c + 1];
+    int64_t leaf = s.corr_begin[c];
+    // depth-first walk with the path of ancestors: path[l] = vertex at level l
+    int64_t path[kTreeMaxDepth + 1] = {-1, -1, -1, -1};
+    std::function<void(int64_t, int)> walk = [&](int64_t v, int level) -> void {
+      if (level > kTreeMaxDepth - 1) throw std::domain_error("factor tree deeper than the GPU evaluator");
+      path[level] = v;
+      const int n = nch[size_t(v)];
+      int64_t w = v + 1;
+      if (n > 0 && nch[size_t(w)] == 0) {
+        for (int k = 1; k < n; ++k)
+          if (nch[size_t(w + k)] != 0) throw std::domain_error("factor tree with leaves at several depths");
+        for (int k0 = 0; k0 < n; k0 += kTreeLeafRun) {
+          const int cnt = std::min(kTreeLeafRun, n - k0);
+          const int32_t parent = level >= 1 ? int32_t(v) : -1;
+          const int32_t grand = level >= 2 ? int32_t(path[level - 1]) : -1;
+          out->items.insert(out->items.end(), {grand, parent, int32_t(w + k0), cnt, int32_t(leaf), 0});
+          leaf += cnt;
+        }
+        return;
+      }
+      for (int k = 0; k < n; ++k) {
+        const int64_t child = w;
+        walk(child, level + 1);
+        // skip the child's subtree: the next sibling follows it
+        int64_t open = 1;
+        while (open > 0) {
+          open += nch[size_t(w)] - 1;
+          ++w;
+        }
+      }
+    };
+    if (nch[size_t(root)] > 0) walk(root, 0);
+    // the items must hold every leaf of the tree once, in term order
+    if (leaf != s.corr_begin[c + 1]) throw std::logic_error("factor-tree items miss leaves");
+    int64_t expect = s.corr_begin[c];
+    for (size_t it = first_item; it < out->items.size() / kTreeItemInts; ++it) {
+      const int32_t* r = &out->items[kTreeItemInts * it];
+      if (r[4] != expect || r[2] <= root || r[2] + r[3] > vend) throw std::logic_error("factor-tree item out of range");
+      for (int k = 0; k < r[3]; ++k)
+        if (nch[size_t(r[2] + k)] != 0 || out->tree_factor[size_t(r[2] + k)] < 0)
+          throw std::logic_error("factor-tree item holds a non-leaf");
+      for (int k = 0; k < 2; ++k)
+        if (r[k] >= 0 && (r[k] <= root || r[k] >= vend)) throw std::logic_error("factor-tree item ancestor out of range");
+      expect += r[3];
+    }
+  }
+  corr_items[s.n_corr] = out->items.size() / kTreeItemInts;
+  // items per thread: 1 up to 256 x 1024 items, doubling to at most
+  // kTreeMaxItemsPerThread, then each correlator padded to whole workgroups
+  const size_t total = corr_items[s.n_corr];
+  out->tree_ipt = 1;
+  while (out->tree_ipt < kTreeMaxItemsPerThread && total > size_t(256) * 1024 * size_t(out->tree_ipt))
+    out->tree_ipt *= 2;
+  const size_t per_wg = size_t(256) * out->tree_ipt;
+  std::vector<int32_t> padded_items;
+  int wg = 0;
+  for (int c = 0; c < s.n_corr; ++c) {
+    out->corr_wg.push_back(wg);
+    const size_t n_items = corr_items[c + 1] - corr_items[c];
+    padded_items.insert(padded_items.end(), out->items.begin() + corr_items[c] * kTreeItemInts,
+                        out->items.begin() + corr_items[c + 1] * kTreeItemInts);
+    const size_t padded = (n_items + per_wg - 1) / per_wg * per_wg;
+    for (size_t k = n_items; k < padded; ++k) padded_items.insert(padded_items.end(), {-1, -1, 0, 0, 0, 0});
+    wg += int(padded / per_wg);
+  }
+  out->items.swap(padded_items);
+  out->corr_wg.push_back(wg);
 }
 
 bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64_t* n_terms, int64_t* n_distinct,

@@ -246,6 +246,66 @@ __global__ __launch_bounds__(kBT) void block_contract_kernel(ContractArgs a) {
   if (tid < nt) a.partial[int64_t(ch) * a.T + t0 + tid] = red[tid][0];
 }
 
+// Factor-tree contraction (Sec. 4).  A correlator's terms are the root-to-leaf
+// paths of its linearised factor tree, and its value the sum over leaf
+// parents P of (the factors above P) x f(P) x sum_{leaves l of P} w_l f(l).
+// Each thread takes a few runs of sibling leaves (items), forms
+// each run's inner sum for the workgroup's kContractT timeslices, and
+// multiplies it once by the factors of the parent and grandparent the run
+// shares.
+struct TreeArgs {
+  const double2* blocks;
+  const int32_t* factor;    // block factor of each vertex
+  const double2* coef;      // leaf weights in term order
+  const int32_t* items;     // [n_wg * ipt * kBT][kTreeItemInts]
+  double2* partial;         // [n_wg][T]
+  int n_types, T, ipt;
+};
+
+__global__ __launch_bounds__(kBT) void tree_contract_kernel(TreeArgs a) {
+  __shared__ double2 red[kContractT][kBT];
+  const int wg = blockIdx.x, t0 = blockIdx.y * kContractT, tid = threadIdx.x;
+  const int nt = a.T - t0 < kContractT ? a.T - t0 : kContractT;
+  const int64_t tstride = int64_t(a.n_types) * kBlockEntries;
+  const double2* bt = a.blocks + int64_t(t0) * tstride;
+  double2 tot[kContractT];
+#pragma unroll
+  for (int u = 0; u < kContractT; ++u) tot[u] = make_double2(0.0, 0.0);
+  for (int m = 0; m < a.ipt; ++m) {
+    const int32_t* it = a.items + ((int64_t(wg) * a.ipt + m) * kBT + tid) * kTreeItemInts;
+    const int grand = it[0], parent = it[1], lv = it[2], nl = it[3], lb = it[4];
+    double2 s[kContractT];
+#pragma unroll
+    for (int u = 0; u < kContractT; ++u) s[u] = make_double2(0.0, 0.0);
+    for (int k = 0; k < nl; ++k) {
+      const int f = a.factor[lv + k];
+      const double2 w = a.coef[lb + k];
+#pragma unroll
+      for (int u = 0; u < kContractT; ++u)
+        if (u < nt) s[u] = cmac(w, bt[u * tstride + f], s[u]);
+    }
+    for (const int anc : {parent, grand}) {
+      if (anc < 0) continue;
+      const int f = a.factor[anc];
+#pragma unroll
+      for (int u = 0; u < kContractT; ++u)
+        if (u < nt) s[u] = cmul(bt[u * tstride + f], s[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kContractT; ++u) tot[u] = cadd(tot[u], s[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kContractT; ++u) red[u][tid] = tot[u];
+  __syncthreads();
+  for (int w = kBT / 2; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int u = 0; u < kContractT; ++u) red[u][tid] = cadd(red[u][tid], red[u][tid + w]);
+    __syncthreads();
+  }
+  if (tid < nt) a.partial[int64_t(wg) * a.T + t0 + tid] = red[tid][0];
+}
+
 // C[c][t] = the chunks of correlator c (consecutive, from corr_chunk[c] to
 // corr_chunk[c + 1]) added in order.
 __global__ __launch_bounds__(kBT) void block_finish_kernel(const double2* __restrict__ partial,
@@ -278,8 +338,13 @@ BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V) {
 size_t block_workspace_bytes(const BlockPlanHost& h, int T, int64_t V) {
   const BlockLaunch L = block_launch_shape(h, T, V);
   const size_t g = align256(size_t(h.n_types) * size_t(T) * size_t(L.nch) * kBlockEntries * 16);
+  return std::max(g, block_contract_workspace_bytes(h, T));
+}
+
+size_t block_contract_workspace_bytes(const BlockPlanHost& h, int T) {
   const size_t c = align256(size_t(h.chunks.size() / 3) * size_t(T) * 16);
-  return std::max(g, c);
+  const size_t tr = align256(size_t(h.corr_wg.empty() ? 0 : h.corr_wg.back()) * size_t(T) * 16);
+  return std::max(c, tr);
 }
 
 hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S_d, int s_c64, int T,
@@ -315,11 +380,30 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
   return hipGetLastError();
 }
 
-hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, int T, double* C, void* workspace,
-                                 hipStream_t st) {
+hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, int T, int method, double* C,
+                                 void* workspace, hipStream_t st) {
   const BlockPlanHost& h = p->h;
   const int n_chunks = int(h.chunks.size() / 3);
   if (n_chunks == 0) return launch_zero(C, size_t(h.n_corr) * size_t(T) * 16, st);
+  const int n_out = h.n_corr * T;
+  if (method == MBC_BLOCK_TREE) {
+    TreeArgs a;
+    a.blocks = reinterpret_cast<const double2*>(blocks);
+    a.factor = p->tree_factor;
+    a.coef = reinterpret_cast<const double2*>(p->coef);
+    a.items = p->items;
+    a.partial = static_cast<double2*>(workspace);
+    a.n_types = h.n_types;
+    a.T = T;
+    a.ipt = h.tree_ipt;
+    const dim3 grid(static_cast<unsigned>(h.corr_wg.back()), static_cast<unsigned>((T + kContractT - 1) / kContractT));
+    hipLaunchKernelGGL(tree_contract_kernel, grid, dim3(kBT), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(block_finish_kernel, dim3(unsigned((n_out + kBT - 1) / kBT)), dim3(kBT), 0, st,
+                       static_cast<const double2*>(workspace), p->corr_wg, T, h.n_corr, reinterpret_cast<double2*>(C));
+    return hipGetLastError();
+  }
   ContractArgs a;
   a.blocks = reinterpret_cast<const double2*>(blocks);
   a.factor = p->factor;
@@ -337,7 +421,6 @@ hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n_out = h.n_corr * T;
   hipLaunchKernelGGL(block_finish_kernel, dim3(unsigned((n_out + kBT - 1) / kBT)), dim3(kBT), 0, st,
                      static_cast<const double2*>(workspace), p->corr_chunk, T, h.n_corr,
                      reinterpret_cast<double2*>(C));

@@ -49,9 +49,11 @@ struct BlockLaunch {
 };
 BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V);
 size_t block_workspace_bytes(const BlockPlanHost& h, int T, int64_t V);
+size_t block_contract_workspace_bytes(const BlockPlanHost& h, int T);
 hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S_d, int s_c64, int T,
                          const int32_t dims[3], double* blocks, void* workspace, hipStream_t st);
-hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, int T, double* C, void* workspace,
-                                 hipStream_t st);
+// method: MBC_BLOCK_TERMS (one product per term) or MBC_BLOCK_TREE (factor trees)
+hipError_t launch_block_contract(const mbc_block_plan* p, const double* blocks, int T, int method, double* C,
+                                 void* workspace, hipStream_t st);
 
 }  // namespace mbc

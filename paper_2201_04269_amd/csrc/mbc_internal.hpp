@@ -85,6 +85,11 @@ struct BlockSet {
   std::vector<int64_t> num_re, num_im; // [n_terms]
   std::vector<int64_t> den;            // [n_corr]
   std::vector<int64_t> corr_begin;     // [n_corr + 1]
+  // Linearised factor tree of each correlator (Sec. 4), vertices in
+  // depth-first order: the block factor of each vertex (-1 for the root) and
+  // its number of children; the leaves are the correlator's terms, in order.
+  std::vector<int32_t> tree_factor, tree_children;
+  std::vector<int64_t> tree_vertex;    // [n_corr + 1] first vertex of each tree
 };
 void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out);
 // Sec. 3 multiplicity count of one correlator (see mbc_block_multiplicities);
@@ -243,6 +248,10 @@ struct BlockTypeDev {
   double gsign[4] = {0, 0, 0, 0};
 };
 constexpr int kBlockTermChunk = 4096;  // terms per workgroup of the contraction
+constexpr int kTreeLeafRun = 16;       // leaves per thread of the factor-tree contraction
+constexpr int kTreeMaxDepth = 3;       // levels below a correlator's root the GPU evaluates
+constexpr int kTreeItemInts = 6;
+constexpr int kTreeMaxItemsPerThread = 8;
 constexpr int kBlockMaxChunk = 1024;   // sites per workgroup of the block kernel (LDS phase table)
 struct BlockPlanHost {
   int n_types = 0, n_slots = 0, n_corr = 0;
@@ -252,7 +261,16 @@ struct BlockPlanHost {
   std::vector<double> coef;      // [n_terms][2]
   std::vector<int32_t> chunks;   // [n_chunks][3]: correlator, first term, end term
   std::vector<int32_t> corr_chunk;  // [n_corr + 1]: first chunk of each correlator
-  double block_flops_per_site = 0, contract_flops_per_t = 0;
+  // factor-tree contraction: the trees' vertex factors, leaf weights in term order, and work
+  // items [n_items][kTreeItemInts] = (grandparent vertex or -1, parent vertex
+  // or -1, first leaf vertex, leaf count, first leaf weight, 0): a run of at
+  // most kTreeLeafRun sibling leaves and the vertices above them; each
+  // correlator's items padded to whole workgroups of tree_ipt x 256 items
+  // (corr_wg: first workgroup of each correlator)
+  std::vector<int32_t> tree_factor, items, corr_wg;
+  int64_t tree_vertices = 0;
+  int tree_ipt = 1;  // items per thread: enough workgroups for small sets, fewer reductions for large
+  double block_flops_per_site = 0, contract_flops_per_t = 0, tree_flops_per_t = 0;
 };
 void compile_block_plan(const BlockSet& s, BlockPlanHost* out);
 
@@ -281,5 +299,8 @@ struct mbc_block_plan {
   double* coef = nullptr;
   int32_t* chunks = nullptr;
   int32_t* corr_chunk = nullptr;
+  int32_t* tree_factor = nullptr;
+  int32_t* items = nullptr;
+  int32_t* corr_wg = nullptr;
   int device = 0;
 };

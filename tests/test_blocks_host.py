@@ -115,4 +115,40 @@ def test_multiplicity_guard_and_errors():
     L.mbc_block_set_free(None)
     L.mbc_block_plan_destroy(None)
     assert L.mbc_blocks_compute(None, None, None, 0, 1, None, None, None, 0, None) == 1
-    assert L.mbc_block_contract(None, None, 1, None, None, 0, None) == 1
+    assert L.mbc_block_contract(None, None, 1, 1, None, None, 0, None) == 1
+    s = api.BlockSet([dict(op="DI", moms=[(0, 0, 0)] * 2)])
+    n = ctypes.c_int64()
+    assert L.mbc_block_set_factor_tree(s._h, 1, ctypes.byref(n), None, None) == 1
+    assert L.mbc_block_set_factor_tree(s._h, -1, ctypes.byref(n), None, None) == 1
+
+
+@pytest.mark.parametrize("corrs", [
+    [dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)])],
+    [dict(op="proton", moms=[(0, 0, 0)]), dict(op="DII", sign_mode="r2", moms=[(0, 1, 0), (0, 0, 0)]),
+     dict(op="DII", moms=[(0, 0, 0)] * 2), dict(op="HE3_I", snk_spin=1, src_spin=2, moms=[(0, 0, 0)] * 3)],
+])
+def test_factor_trees_equal_the_oracle_construction_and_value(corrs):
+    # the library's linearised trees (Sec. 4) against the oracle's prefix-tree
+    # construction on the same terms, and their depth-first value against the
+    # flat sum over the terms, with oracle blocks as factor values
+    from oracle import factor_tree as FT
+    dims, T = (2, 1, 1), 1
+    S_u, S_d = synth.iid(T, 2, seed=33)
+    bset = api.BlockSet(corrs)
+    e = bset.export()
+    blk = np.stack([OB.block(S_u, S_d, NAME[(fam, proj)], mom, dims) for fam, proj, mom in bset.types()],
+                   axis=1).reshape(T, -1)[0]
+    flat = contract_terms_with_oracle_blocks(bset, S_u, S_d, dims)[:, 0]
+    for c in range(bset.n_corr):
+        m = e["corr_id"] == c
+        w = (e["num_re"][m] + 1j * e["num_im"][m]) / e["den"][c]
+        terms = [(wk, tuple(int(x) for x in f if x >= 0)) for wk, f in zip(w, e["factor"][m])]
+        factors, children, coefficients = FT.build(terms)
+        fac, ch = bset.factor_tree(c)
+        assert [None if x < 0 else int(x) for x in fac] == factors
+        assert list(ch) == children
+        val = FT.evaluate(factors, children, coefficients, lambda f: blk[f])
+        assert abs(val - flat[c]) <= 1e-13 * max(1.0, abs(flat[c]))
+        if m.any():
+            A = int((e["factor"][m][0] >= 0).sum())
+            assert len(fac) == 1 + len({tuple(f[:k]) for f in e["factor"][m].tolist() for k in range(1, A + 1)})

@@ -1,5 +1,6 @@
 """GPU parity of the hadron blocks and block-level correlators (through the C
-ABI) against the oracle.
+ABI) against the oracle; correlators by factor trees (Sec. 4) and by the flat
+term sum.
 
 Tolerances (FP64 throughout):
 * a block entry is a sum over sites; the kernel's and the oracle's sums differ
@@ -31,6 +32,8 @@ def _api():
 
 
 def gpu_blocks(corrs, Su, Sd, dims, c64=False):
+    """(C by factor trees, blocks, block set); C by the flat term sum must agree
+    with the trees to rounding (checked here)."""
     api = _api()
     bset = api.BlockSet(corrs)
     plan = api.BlockPlan(bset)
@@ -38,8 +41,11 @@ def gpu_blocks(corrs, Su, Sd, dims, c64=False):
     su = torch.from_numpy(Su).to(dt).cuda()
     sd = torch.from_numpy(Sd).to(dt).cuda()
     C, blk = api.block_correlators(plan, su, sd, dims)
+    Ct = api.block_contract(plan, blk, method="terms")
     torch.cuda.synchronize()
-    return C.cpu().numpy(), blk.cpu().numpy().reshape(Su.shape[0], bset.n_types, 4, 1728), bset
+    C, Ct = C.cpu().numpy(), Ct.cpu().numpy()
+    assert np.all(np.abs(C - Ct) <= 1e-12 * np.abs(Ct).max(axis=1, keepdims=True) + 1e-300)
+    return C, blk.cpu().numpy().reshape(Su.shape[0], bset.n_types, 4, 1728), bset
 
 
 def oracle_blocks(bset, Su, Sd, dims):

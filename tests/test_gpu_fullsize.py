@@ -277,8 +277,9 @@ def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
     plan = api.BlockPlan(bset)
     su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
     C, blk = api.block_correlators(plan, su, sd, (L, L, L))
+    Ct = api.block_contract(plan, blk, method="terms")
     torch.cuda.synchronize()
-    C = C.cpu().numpy()
+    C, Ct = C.cpu().numpy(), Ct.cpu().numpy()
     blk = blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
     names = {("p", 0): "p", ("n", 0): "n"}
     sites = [t * V + v for t, v in picks]
@@ -291,5 +292,6 @@ def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
     for c, corr in enumerate(corrs):
         want = OB.block_correlator(Su, Sd, corr["op"], 0, 0, corr["sign_mode"], corr["moms"], (L, L, L),
                                    blocks=ref)
-        err = np.abs(C[c] - want)
-        assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
+        for got in (C[c], Ct[c]):  # factor trees, flat terms
+            err = np.abs(got - want)
+            assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
