@@ -171,3 +171,19 @@ def test_bad_arguments_are_rejected():
     d = (ctypes.c_int32 * 3)(2, 2, 1)
     assert api.B.lib().mbc_blocks_compute(plan._h, ctypes.c_void_p(host.data_ptr()),
                                           ctypes.c_void_p(host.data_ptr()), 0, 1, d, None, None, 0, None) == 1
+
+
+def test_block_example_from_the_readme():
+    # the README's block-path snippet, checked against the oracle
+    api = _api()
+    bset = api.BlockSet([dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)])])
+    bplan = api.BlockPlan(bset)
+    Su, Sd = synth.iid(T=4, V=64, seed=2)
+    C, blocks = api.block_correlators(bplan, torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda(),
+                                      dims=(4, 4, 4))
+    factors, children = bset.factor_tree(0)
+    assert factors[0] == -1 and children.sum() == len(factors) - 1
+    n_terms, n_distinct, hist = api.block_multiplicities(dict(op="DI", moms=[(0, 0, 0)] * 2))
+    assert n_terms == 4 * 2304 * 9 and (np.arange(hist.shape[0]) * hist).sum() == n_terms
+    ref = OB.block_correlator(Su, Sd, "DI", 0, 0, "exact", [(1, 0, 0), (-1, 0, 0)], (4, 4, 4))
+    assert np.abs(C.cpu().numpy()[0] - ref).max() <= 1e-12 * np.abs(ref).max()
