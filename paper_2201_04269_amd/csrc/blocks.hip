@@ -36,7 +36,9 @@ using dev::cmul;
 
 constexpr int kBT = 256;          // threads per workgroup of the block kernels
 constexpr int kBlockEntries = 6912;  // 4 x 12 x 12 x 12 per block type and timeslice
-constexpr int kBlockSitesPerRound = 2;
+constexpr int kBlockSitesPerRound = 2;  // K = 6 per site: two sites fill three 16x16x4 MFMA steps
+constexpr int kTilesPerWave = 7;        // ceil(27 tiles / 4 waves)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 load_c(const double2* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ double2 load_c(const float2* p, int64_t i) {
@@ -70,26 +72,31 @@ __device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int v, int
   return make_double2(c, -s);
 }
 
-// NS sites per round: their propagators and B matrices share the round's
-// three barriers.
+// NS sites per round: their propagators (staged in LDS, the next round's
+// prefetched into registers meanwhile), B matrices and G updates share the
+// round's three barriers.  (Building B for the next round while the matrix
+// cores work on this one, over two LDS buffers, measured no faster.)
 template <typename SIN, int NS>
-__global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
+__global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
   __shared__ double2 sS1[NS][144], sS2[NS][144], sB[NS][432], sPh[kBlockMaxChunk];
   const int ch = blockIdx.x, t = blockIdx.y, ty = blockIdx.z;
   const BlockTypeDev& bt = a.types[ty];
   const SIN* S1 = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_u : a.S_d);
   const SIN* S2 = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_d : a.S_u);
   const int tid = threadIdx.x;
-  const int i = tid >> 4, j = tid & 15;
+  const int wave = tid >> 6, lane = tid & 63;
   const int64_t v0 = int64_t(ch) * a.chunk;
   const int64_t v1 = v0 + a.chunk < a.V ? v0 + a.chunk : a.V;
   const int64_t site0 = int64_t(t) * a.V;
 
-  double2 acc[3][9];
+  // G's 27 tiles of 16 x 16 (row block tile / 9, column block tile % 9):
+  // wave w accumulates tiles w, w + 4, .., real and imaginary parts apart
+  f64x4 accr[kTilesPerWave], acci[kTilesPerWave];
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
-#pragma unroll
-    for (int k = 0; k < 9; ++k) acc[m][k] = make_double2(0.0, 0.0);
+  for (int m = 0; m < kTilesPerWave; ++m) {
+    accr[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+    acci[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+  }
 
   // the 288 NS entries of a round (S1 then S2 of each site), NL per thread;
   // sites past the chunk's end read as zero (their B vanishes)
@@ -110,11 +117,7 @@ __global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
       }
     }
   };
-  if (v0 < v1) fetch(v0);
-  // the chunk's phases, once (visible after the loop's first barrier)
-  for (int k = tid; k < int(v1 - v0); k += kBT) sPh[k] = site_phase(bt, int(v0) + k, a.L1, a.L2, a.L3);
-
-  for (int64_t v = v0; v < v1; v += NS) {
+  auto store = [&]() {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int e = tid + k * kBT;
@@ -126,52 +129,95 @@ __global__ __launch_bounds__(kBT) void block_g_kernel(BlockGArgs a) {
           sS2[s][r - 144] = pre[k];
       }
     }
-    __syncthreads();
-    if (v + NS < v1) fetch(v + NS);
-
-    for (int e = tid; e < 432 * NS; e += kBT) {
-      const int s = e / 432, r = e % 432;
-      const int c = r / 144, X = (r / 12) % 12, Y = r % 12;
+  };
+  // B of the round starting at site v: one thread per (site, colour c, row
+  // X, four columns Y); the eight S1 entries of (c, X) serve the four columns
+  auto build_b = [&](int64_t v) {
+    for (int e = tid; e < 108 * NS; e += kBT) {
+      const int s = e / 108, r = e % 108;
+      const int c = r / 36, X = (r / 3) % 12, Y0 = 4 * (r % 3);
       // (a, b, c) cyclic (eps = +1) and anticyclic (eps = -1)
       const int a1 = c == 2 ? 0 : c + 1, b1 = c == 0 ? 2 : c - 1;
-      double2 sum = make_double2(0.0, 0.0);
+      double2 x1[4], x2[4];
 #pragma unroll
       for (int be = 0; be < 4; ++be) {
-        const int ga = bt.gcol[be];
-        if (ga < 0) continue;
-        double2 d = cmul(sS1[s][(4 * a1 + be) * 12 + X], sS2[s][(4 * b1 + ga) * 12 + Y]);
-        d = dev::cmsub(sS1[s][(4 * b1 + be) * 12 + X], sS2[s][(4 * a1 + ga) * 12 + Y], d);
-        const double sg = bt.gsign[be];
-        sum.x = fma(sg, d.x, sum.x);
-        sum.y = fma(sg, d.y, sum.y);
+        x1[be] = sS1[s][(4 * a1 + be) * 12 + X];
+        x2[be] = sS1[s][(4 * b1 + be) * 12 + X];
       }
       const double2 ph = v + s < v1 ? sPh[v + s - v0] : make_double2(0.0, 0.0);
-      sB[s][r] = cmul(sum, ph);
-    }
-    __syncthreads();
-
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+      for (int y = 0; y < 4; ++y) {
+        double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double2 av[3], bv[9];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) av[m] = sS1[s][48 * c + i + 16 * m];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) bv[k] = sB[s][144 * c + j + 16 * k];
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-          for (int k = 0; k < 9; ++k) acc[m][k] = cmac(av[m], bv[k], acc[m][k]);
+        for (int be = 0; be < 4; ++be) {
+          const int ga = bt.gcol[be];
+          if (ga < 0) continue;
+          double2 d = cmul(x1[be], sS2[s][(4 * b1 + ga) * 12 + Y0 + y]);
+          d = dev::cmsub(x2[be], sS2[s][(4 * a1 + ga) * 12 + Y0 + y], d);
+          const double sg = bt.gsign[be];
+          sum.x = fma(sg, d.x, sum.x);
+          sum.y = fma(sg, d.y, sum.y);
+        }
+        sB[s][c * 144 + X * 12 + Y0 + y] = cmul(sum, ph);
       }
+    }
+  };
+  // G += sum over the round's (site, colour) of S1 x B on the matrix cores:
+  // real K index k = 6 s + 2 c + part (12 per round, three 16x16x4 steps);
+  // Re G takes (a.x, -a.y) x (b.x, b.y), Im G (a.x, a.y) x (b.y, b.x).  Lane
+  // l holds A[row l % 16][k l / 16] and B[k l / 16][column l % 16].
+  auto accumulate_g = [&]() {
+#pragma unroll
+    for (int st = 0; st < 3 * NS / 2; ++st) {
+      const int kk = 4 * st + (lane >> 4);
+      const int s = kk / 6, c = (kk % 6) >> 1, part = kk & 1;
+      double ar[3], ai[3];
+#pragma unroll
+      for (int rb = 0; rb < 3; ++rb) {
+        const double2 av = sS1[s][48 * c + 16 * rb + (lane & 15)];
+        ar[rb] = part ? -av.y : av.x;
+        ai[rb] = part ? av.y : av.x;
+      }
+#pragma unroll
+      for (int m = 0; m < kTilesPerWave; ++m) {
+        const int tile = wave + 4 * m;
+        if (tile < 27) {
+          const double2 bv = sB[s][144 * c + 16 * (tile % 9) + (lane & 15)];
+          const int rb = tile / 9;
+          accr[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rb], part ? bv.y : bv.x, accr[m], 0, 0, 0);
+          acci[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[rb], part ? bv.x : bv.y, acci[m], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  if (v0 < v1) fetch(v0);
+  // the chunk's phases, once (visible after the loop's first barrier)
+  for (int k = tid; k < int(v1 - v0); k += kBT) sPh[k] = site_phase(bt, int(v0) + k, a.L1, a.L2, a.L3);
+  for (int64_t v = v0; v < v1; v += NS) {
+    store();
+    __syncthreads();
+    if (v + NS < v1) fetch(v + NS);
+    build_b(v);
+    __syncthreads();
+    accumulate_g();
     __syncthreads();
   }
 
+  // lane l, register r of a tile's accumulator: G row 16 rb + l / 16 + 4 r,
+  // column 16 cb + l % 16
   double2* out = a.partial + ((int64_t(ty) * a.T + t) * a.nch + ch) * kBlockEntries;
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
+  for (int m = 0; m < kTilesPerWave; ++m) {
+    const int tile = wave + 4 * m;
+    if (tile < 27) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out[(i + 16 * m) * 144 + j + 16 * k] = acc[m][k];
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * (tile / 9) + (lane >> 4) + 4 * r, col = 16 * (tile % 9) + (lane & 15);
+        out[row * 144 + col] = make_double2(accr[m][r], acci[m][r]);
+      }
+    }
+  }
 }
 
 // blocks[t][type][alpha][A][Y][C] = sum over chunks (in order) of
