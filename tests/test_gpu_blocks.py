@@ -187,3 +187,18 @@ def test_block_example_from_the_readme():
     assert n_terms == 4 * 2304 * 9 and (np.arange(hist.shape[0]) * hist).sum() == n_terms
     ref = OB.block_correlator(Su, Sd, "DI", 0, 0, "exact", [(1, 0, 0), (-1, 0, 0)], (4, 4, 4))
     assert np.abs(C.cpu().numpy()[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_blocks_and_correlators_are_bitwise_reproducible():
+    api = _api()
+    corrs = [dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)]), dict(op="HE3_I", moms=[(0, 0, 0)] * 3)]
+    plan = api.BlockPlan(api.BlockSet(corrs))
+    Su, Sd = synth.iid(3, 60, seed=46)
+    su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
+    runs = []
+    for _ in range(2):
+        blk = api.blocks(plan, su, sd, (5, 4, 3))
+        runs.append([blk.cpu().numpy(), api.block_contract(plan, blk, method="tree").cpu().numpy(),
+                     api.block_contract(plan, blk, method="terms").cpu().numpy()])
+    for x, y in zip(*runs):
+        assert np.array_equal(x.view(np.float64), y.view(np.float64))

@@ -295,3 +295,39 @@ def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
         for got in (C[c], Ct[c]):  # factor trees, flat terms
             err = np.abs(got - want)
             assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
+
+
+def test_blocks_helium3_32x32x32x8_on_sampled_sites():
+    # the bench's 3He block leg (8 correlators, 3 block types, 14.75M terms)
+    # at its full shape; two correlators are checked against the oracle
+    import bench
+    from oracle import blocks as OB
+    api = _api()
+    L, T = 32, 8
+    V = L ** 3
+    corrs = bench.block_corrs("he3_shard")
+    Su, Sd = synth.iid(T, V, seed=4)
+    picks = picks_for(T, V, n_t=2, per_t=2, seed=19)
+    Su, Sd = keep_sites(Su, Sd, picks)
+    bset = api.BlockSet(corrs)
+    plan = api.BlockPlan(bset)
+    su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
+    C, blk = api.block_correlators(plan, su, sd, (L, L, L))
+    Ct = api.block_contract(plan, blk, method="terms")
+    torch.cuda.synchronize()
+    C, Ct = C.cpu().numpy(), Ct.cpu().numpy()
+    blk = blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
+    names = {("p", 1): "p+", ("p", -1): "p-", ("n", 1): "n+"}
+    sites = [t * V + v for t, v in picks]
+    ref = {(names[(f, p)], m): OB.block(Su, Sd, names[(f, p)], m, (L, L, L), sites=sites)
+           for f, p, m in bset.types()}
+    for k, (f, p, m) in enumerate(bset.types()):
+        want = ref[(names[(f, p)], m)]
+        assert np.abs(blk[:, k] - want).max() <= 1e-13 * len(picks) * np.abs(want).max()
+    for c in (0, 4):  # 3He_I j = 0 and 3He_II (R2) j = 0
+        corr = corrs[c]
+        want = OB.block_correlator(Su, Sd, corr["op"], corr["snk_spin"], corr["src_spin"],
+                                   corr.get("sign_mode", "exact"), corr["moms"], (L, L, L), blocks=ref)
+        for got in (C[c], Ct[c]):
+            err = np.abs(got - want)
+            assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
