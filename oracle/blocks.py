@@ -82,20 +82,28 @@ def _all_source_triples():
     return np.stack([A.ravel(), Y.ravel(), C.ravel()], axis=1)  # xi = (A*12 + Y)*12 + C
 
 
-def _projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites=None):
+def _points(S):
+    """Propagators as [P, T, V, 12, 12]: one set per source point (P = 1 for [T, V, 12, 12])."""
+    return S[None] if S.ndim == 4 else S
+
+
+def _projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites=None, srcs=(0, 0, 0)):
     """[T, len(src)]: sum_x e^{-i p.x} < h_alpha(x) q1bar(A) q2bar(Y) q1bar(C) > for src rows (A, Y, C).
 
     ``sites``: optional flat site indices t*V + v to sum over (the others are
-    taken to be zero); default every site.
+    taken to be zero); default every site.  ``srcs``: the source points of
+    the three antiquarks (A, Y, C): a quark paired with antiquark k propagates
+    from source point srcs[k].
     """
-    T, V = S_u.shape[:2]
+    S_u, S_d = _points(S_u), _points(S_d)
+    T, V = S_u.shape[1:3]
     if V != dims[0] * dims[1] * dims[2]:
         raise ValueError("sites per timeslice do not match dims")
     kind, proj = kind_of(name)
     flav = _FLAV[kind]
     pairs = wick.pairings(flav, flav)
     ph = phases(mom, dims)
-    S_of = {U: S_u.reshape(T * V, 12, 12), D: S_d.reshape(T * V, 12, 12)}
+    S_of = {U: S_u.reshape(S_u.shape[0], T * V, 12, 12), D: S_d.reshape(S_d.shape[0], T * V, 12, 12)}
     terms = O.baryon_terms(kind, alpha, proj)
     coef = np.array([complex(c[0], c[1]) for c, _ in terms])
     snk = np.array([[i for _, i in f] for _, f in terms])
@@ -107,7 +115,7 @@ def _projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites=None):
         for pi, sgn in pairs:
             term = np.full(E.shape, float(sgn), dtype=np.complex128)
             for i, f in enumerate(flav):
-                term *= S_of[f][sl][:, snk[:, i][:, None], src[:, pi[i]][None, :]]
+                term *= S_of[f][srcs[pi[i]]][sl][:, snk[:, i][:, None], src[:, pi[i]][None, :]]
             E += term
         vals = np.einsum("r,brx->bx", coef, E)
         w = ph[sl % V]
@@ -117,50 +125,65 @@ def _projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites=None):
     return out
 
 
-def block(S_u, S_d, name, mom, dims, batch=16, sites=None):
+def block(S_u, S_d, name, mom, dims, batch=16, sites=None, srcs=(0, 0, 0)):
     """f^h_p[t, alpha, xi] for baryon ``name``, xi = (A*12 + Y)*12 + C.
 
-    S_u, S_d: [T, V, 12, 12] complex128 with V = L1 L2 L3.  Returns
-    [T, 4, 1728] complex128.  Every entry is the pairing sum of ``wick`` over
-    the baryon's written terms (Sec. 1), summed over sites with e^{-i p.x}
-    (over the flat sites t*V + v listed in ``sites`` only, if given).
+    S_u, S_d: [T, V, 12, 12] complex128 with V = L1 L2 L3, or [P, T, V, 12,
+    12] for P source points, with ``srcs`` the source points of the
+    antiquarks (A, Y, C).  Returns [T, 4, 1728] complex128.  Every entry is
+    the pairing sum of ``wick`` over the baryon's written terms (Sec. 1),
+    summed over sites with e^{-i p.x} (over the flat sites t*V + v listed in
+    ``sites`` only, if given).
     """
     src = _all_source_triples()
-    return np.stack([_projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites) for alpha in range(4)],
+    return np.stack([_projected(S_u, S_d, name, mom, dims, alpha, src, batch, sites, srcs) for alpha in range(4)],
                     axis=1)
 
 
-def block_entries(S_u, S_d, name, mom, dims, entries, batch=512):
+def block_entries(S_u, S_d, name, mom, dims, entries, batch=512, srcs=(0, 0, 0)):
     """Selected block entries [T, len(entries)] for entries (alpha, A, Y, C).
 
     The same definition as ``block``, evaluated for a few entries only, so
     that large lattices stay cheap.
     """
     entries = [tuple(int(v) for v in e) for e in entries]
-    out = np.zeros((S_u.shape[0], len(entries)), dtype=np.complex128)
+    out = np.zeros((_points(S_u).shape[1], len(entries)), dtype=np.complex128)
     for alpha in sorted({e[0] for e in entries}):
         cols = [k for k, e in enumerate(entries) if e[0] == alpha]
         src = np.array([entries[k][1:] for k in cols])
-        out[:, cols] = _projected(S_u, S_d, name, mom, dims, alpha, src, batch)
+        out[:, cols] = _projected(S_u, S_d, name, mom, dims, alpha, src, batch, srcs=srcs)
     return out
 
 
-def _source_terms(op, spin, sign_mode, form):
-    """Source operator terms as (coef, flavours, indices), coefficients not yet conjugated.
+def _labelled(terms, pts):
+    """Written terms with field i of baryon slot i // 3 at source point pts[i // 3],
+    encoded as index 12 * point + a (a field's point and index sort together)."""
+    return [(c, tuple((f, 12 * pts[i // 3] + a) for i, (f, a) in enumerate(fl))) for c, fl in terms]
 
+
+def _source_terms(op, spin, sign_mode, form, src_pts=None):
+    """Source operator terms as (coef, flavours, indices, points), coefficients not yet conjugated.
+
+    Baryon slot i of the source (written order) sits at source point
+    src_pts[i] (default: every slot at point 0, a local source).
     form "raw": the written terms of eq. "ops" (fields in written order);
-    form "canonical": the canonical keys (ubar..ubar dbar..dbar, each sorted),
-    with the flavour-separation and sorting signs in the coefficient.  Both
-    are the same Grassmann polynomial.
+    form "canonical": the canonical keys (ubar..ubar dbar..dbar, each sorted
+    by (point, index)), with the flavour-separation and sorting signs in the
+    coefficient.  Both are the same Grassmann polynomial.
     """
     terms, _ = O.operator_terms(op, spin, sign_mode)
+    A = len(terms[0][1]) // 3 if terms else 0
+    pts = tuple(src_pts) if src_pts is not None else (0,) * A
+    lab = _labelled(terms, pts)
     if form == "raw":
-        return [(c, tuple(f for f, _ in fl), tuple(i for _, i in fl)) for c, fl in terms]
+        return [(c, tuple(f for f, _ in fl), tuple(v % 12 for _, v in fl), tuple(v // 12 for _, v in fl))
+                for c, fl in lab]
     if form != "canonical":
         raise ValueError(form)
     out = []
-    for (u, d), c in sorted(O.canonical_tensor(O.flavour_separate(terms)).items()):
-        out.append((c, (U,) * len(u) + (D,) * len(d), tuple(u) + tuple(d)))
+    for (u, d), c in sorted(O.canonical_tensor(O.flavour_separate(lab)).items()):
+        v = tuple(u) + tuple(d)
+        out.append((c, (U,) * len(u) + (D,) * len(d), tuple(x % 12 for x in v), tuple(x // 12 for x in v)))
     return out
 
 
@@ -195,59 +218,61 @@ def partitions(slot_kinds, src_flav):
 
 
 def block_correlator(S_u, S_d, op, snk_spin, src_spin, sign_mode, moms, dims, source="canonical",
-                     blocks=None):
+                     blocks=None, src_pts=None):
     """C[t] of one block-level correlator, from blocks and the partition sum.
 
-    moms: one integer momentum triple per baryon slot.  ``blocks`` may hold
-    precomputed {(name, mom): block(...)} arrays.  Returns [T] complex128.
+    moms: one integer momentum triple per sink baryon slot; src_pts: the
+    source point of each source baryon slot (default all 0, a local source),
+    with S_u, S_d [P, T, V, 12, 12] for P points.  ``blocks`` may hold
+    precomputed {(name, mom, srcs): block(...)} arrays.  Returns [T] complex128.
     """
     products, s2 = O.baryon_products(op, snk_spin, sign_mode)
-    src = _source_terms(op, src_spin, sign_mode, source)
-    T = S_u.shape[0]
+    src = _source_terms(op, src_spin, sign_mode, source, src_pts)
+    T = _points(S_u).shape[1]
     blocks = {} if blocks is None else blocks
     C = np.zeros(T, dtype=np.complex128)
-    by_flav = {}
-    for c, fl, idx in src:
-        by_flav.setdefault(fl, []).append((c, idx))
+    groups_of = {}
+    for c, fl, idx, pts in src:
+        groups_of.setdefault((fl, pts), []).append((c, idx))
     for coef_s, slots in products:
         if len(slots) != len(moms):
             raise ValueError("one momentum per baryon slot")
         names = [nm for nm, _ in slots]
-        blk = []
-        for (nm, _), mom in zip(slots, moms):
-            key = (nm, tuple(mom))
-            if key not in blocks:
-                blocks[key] = block(S_u, S_d, nm, mom, dims)
-            blk.append(blocks[key])
-        for fl, items in by_flav.items():
+        for (fl, pts), items in groups_of.items():
             cw = np.conj(np.array([complex(c[0], c[1]) for c, _ in items]))
             idx = np.array([i for _, i in items])
             for groups, sgn in partitions([kind_of(nm)[0] for nm in names], fl):
                 prod = np.ones((T, len(items)), dtype=np.complex128)
                 for i, (a, y, c) in enumerate(groups):
+                    key = (names[i], tuple(moms[i]), (pts[a], pts[y], pts[c]))
+                    if key not in blocks:
+                        blocks[key] = block(S_u, S_d, names[i], moms[i], dims, srcs=key[2])
                     xi = (idx[:, a] * 12 + idx[:, y]) * 12 + idx[:, c]
-                    prod *= blk[i][:, slots[i][1], xi]
+                    prod *= blocks[key][:, slots[i][1], xi]
                 C += complex(coef_s[0], coef_s[1]) * sgn * (prod @ cw)
     return complex(s2) * C
 
 
-def block_correlator_bruteforce(S_u, S_d, op, snk_spin, src_spin, sign_mode, moms, dims):
+def block_correlator_bruteforce(S_u, S_d, op, snk_spin, src_spin, sign_mode, moms, dims, src_pts=None):
     """The same correlator without blocks: sum over every tuple of sink points.
 
     For each (x_1, .., x_A) the sink fields of baryon slot i are labelled with
-    x_i and the expectation is taken in the determinant form (rows
-    12*i + a of the stacked propagators S(x_1), .., S(x_A)), summed with
+    x_i and the source fields of slot i with source point src_pts[i]; the
+    expectation is taken in the determinant form, rows 12 i + a and columns
+    12 p + a' of the stacked propagators S^(p)(x_i), summed with
     e^{-i sum_i p_i.x_i}.  Cost V^A determinant sums: tiny lattices only.
     """
+    S_u, S_d = _points(S_u), _points(S_d)
+    P = S_u.shape[0]
     terms, s2 = O.operator_terms(op, snk_spin, sign_mode)
     A = len(terms[0][1]) // 3
     if len(moms) != A:
         raise ValueError("one momentum per baryon slot")
-    lab = [(c, tuple((f, 12 * (i // 3) + a) for i, (f, a) in enumerate(fl))) for c, fl in terms]
-    snk = sorted(O.canonical_tensor(O.flavour_separate(lab)).items())
+    pts = tuple(src_pts) if src_pts is not None else (0,) * A
+    snk = sorted(O.canonical_tensor(O.flavour_separate(_labelled(terms, tuple(range(A))))).items())
     src_terms, _ = O.operator_terms(op, src_spin, sign_mode)
-    src = sorted(O.canonical_tensor(O.flavour_separate(src_terms)).items())
-    T, V = S_u.shape[:2]
+    src = sorted(O.canonical_tensor(O.flavour_separate(_labelled(src_terms, pts))).items())
+    T, V = S_u.shape[1:3]
     C = np.zeros(T, dtype=np.complex128)
     if not snk or not src:
         return C
@@ -273,12 +298,14 @@ def block_correlator_bruteforce(S_u, S_d, op, snk_spin, src_spin, sign_mode, mom
         Cc = np.tile(cols, (rows.shape[0], 1))
         return _dets(S, R, Cc).reshape(rows.shape[0], cols.shape[0])
 
+    def stacked(S, t, xs):
+        # [12 A, 12 P]: block (i, p) = S^(p)(x_i)
+        return np.concatenate([np.concatenate([S[p, t, x] for p in range(P)], axis=1) for x in xs], axis=0)
+
     for t in range(T):
         for xs in iproduct(range(V), repeat=A):
-            Su = np.concatenate([S_u[t, x] for x in xs], axis=0)
-            Sd = np.concatenate([S_d[t, x] for x in xs], axis=0)
-            Du = grid_dets(Su, ru, cu)[iru][:, icu]
-            Dd = grid_dets(Sd, rd, cd)[ird][:, icd]
+            Du = grid_dets(stacked(S_u, t, xs), ru, cu)[iru][:, icu]
+            Dd = grid_dets(stacked(S_d, t, xs), rd, cd)[ird][:, icd]
             val = wr @ (Du * Dd) @ wc
             w = np.prod([ph[i][x] for i, x in enumerate(xs)])
             C[t] += w * val
@@ -304,7 +331,7 @@ def multiplicity_histogram(op, snk_spin, src_spin, sign_mode, moms=None):
     part_cache = {}
     for _, slots in products:
         kinds = tuple(kind_of(nm)[0] for nm, _ in slots)
-        for _, fl, idx in src:
+        for _, fl, idx, _pts in src:
             key = (kinds, fl)
             if key not in part_cache:
                 part_cache[key] = partitions(list(kinds), fl)

@@ -136,3 +136,40 @@ def test_multiplicity_histogram_counts(op, mode, n_src, n_prod, n_part):
     assert n == n_src * n_prod * n_part
     assert sum(m * k for m, k in hist.items()) == n
     assert min(hist) >= 1
+
+
+def _two_points(T, V, seed):
+    S = [synth.iid(T, V, seed=seed + p) for p in range(2)]
+    return np.stack([s[0] for s in S]), np.stack([s[1] for s in S])
+
+
+def test_displaced_sources_equal_the_labelled_bruteforce_and_revive_dii():
+    # each source baryon at its own point (its own propagator set): the
+    # partition sum with mixed-source blocks against the determinant brute
+    # force with stacked (sink point, source point) propagators; exact-sign
+    # D_II no longer vanishes, and swapping the two source points flips its sign
+    Su, Sd = _two_points(1, 3, 70)
+    moms = [(1, 0, 0), (-1, 0, 0)]
+    dii = B.block_correlator(Su, Sd, "DII", 0, 0, "exact", moms, (3, 1, 1), src_pts=(0, 1))
+    bf = B.block_correlator_bruteforce(Su, Sd, "DII", 0, 0, "exact", moms, (3, 1, 1), src_pts=(0, 1))
+    assert abs(dii[0] - bf[0]) <= 1e-13 * abs(bf[0])
+    assert abs(bf[0]) > 1.0
+    swapped = B.block_correlator(Su, Sd, "DII", 0, 0, "exact", moms, (3, 1, 1), src_pts=(1, 0))
+    assert abs(swapped[0] + dii[0]) <= 1e-13 * abs(dii[0])
+    di = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (3, 1, 1), src_pts=(0, 1))
+    di_bf = B.block_correlator_bruteforce(Su, Sd, "DI", 0, 0, "exact", moms, (3, 1, 1), src_pts=(0, 1))
+    assert abs(di[0] - di_bf[0]) <= 1e-13 * abs(di_bf[0])
+    raw = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (3, 1, 1), src_pts=(0, 1), source="raw")
+    assert abs(raw[0] - di_bf[0]) <= 1e-13 * abs(di_bf[0])
+
+
+def test_one_source_point_set_reproduces_the_local_source():
+    Su, Sd = _two_points(2, 2, 72)
+    moms = [(1, 0, 0), (-1, 0, 0)]
+    a = B.block_correlator(Su[0], Sd[0], "DI", 0, 0, "exact", moms, (2, 1, 1))
+    b = B.block_correlator(Su, Sd, "DI", 0, 0, "exact", moms, (2, 1, 1), src_pts=(0, 0))
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+    # a mixed-source block is the plain block when every antiquark uses one set
+    f = B.block(Su, Sd, "p", (1, 0, 0), (2, 1, 1), srcs=(1, 1, 1))
+    g = B.block(Su[1], Sd[1], "p", (1, 0, 0), (2, 1, 1))
+    assert np.array_equal(f, g)
