@@ -15,10 +15,16 @@
  * Sec. 3 writes a multi-baryon correlator as a sum of products of blocks.  A
  * block-level correlator here places baryon i of every written product of
  * the sink operator of eq. "ops" at its own sink point, projected to its own
- * momentum p_i, with the source operator local at the source point:
+ * momentum p_i, with source baryon i at source point z_i (a local source
+ * when all z_i coincide; the general block form of Sec. 3 lets the blocks'
+ * source points differ):
  *
- *   C[t] = sum_{x_1..x_A in t} e^{-i sum_i p_i.x_i} < O_snk(x_1, .., x_A) Obar_src >
+ *   C[t] = sum_{x_1..x_A in t} e^{-i sum_i p_i.x_i} < O_snk(x_1, .., x_A) Obar_src(z_1, .., z_A) >
  *        = sum_k w_k prod_i f^{h_i}_{p_i}[t][eta_{i,k}]
+ *
+ * A block's three antiquarks may then come from different source points:
+ * f^h_p[t][alpha][A][Y][C] for source points (z_A, z_Y, z_C), its quarks
+ * propagating from those points.
  *
  * The host expands the Wick contraction by the set partitions of the source
  * antiquarks among the baryons (D_I: N_w = 9 partitions, Sec. 3), over the
@@ -31,6 +37,7 @@
  *   sites         V = L1 L2 L3 sites per timeslice, site v at coordinates
  *                 (x1, x2, x3) with v = x1 + L1 (x2 + L2 x3)
  *   momenta       integer triples n: p.x = 2 pi (n1 x1/L1 + n2 x2/L2 + n3 x3/L3)
+ *   propagators   S[n_points][T][V][12][12]: one set per source point
  *   blocks        device [T][n_types][4][12][12][12] complex128 (re/im
  *                 interleaved doubles); type order as mbc_block_set_types
  *   arithmetic    FP64 throughout; block sums over sites and term sums are
@@ -60,31 +67,37 @@ typedef struct {
   int32_t sign_mode;  /* MBC_SIGNS_EXACT or MBC_SIGNS_R2 */
   int32_t mom[3][3];  /* sink momentum of baryon slot i (written order); slots
                          beyond the operator's baryon count are ignored */
+  int32_t src_pt[3];  /* source point (0..2) of source baryon slot i (written
+                         order): all 0 is a local source; distinct points
+                         displace the source baryons, each point with its own
+                         propagator set (see mbc_blocks_compute) */
 } mbc_block_corr_desc;
 
 typedef struct mbc_block_set mbc_block_set;   /* opaque, host, library-owned */
 typedef struct mbc_block_plan mbc_block_plan; /* opaque, owns its device arrays */
 
 /* ---- block sets (host only; Sec. 3 expanded form) ----
- * Builds the block types (distinct (family, projector, momentum) over every
- * baryon slot of every correlator, in order of first use) and the merged
+ * Builds the block types (distinct (family, projector, momentum, source
+ * points of A, Y, C) over the expansion of every correlator, in order of
+ * first use) and the merged
  * product terms of n_corr >= 1 correlators.  Term k of correlator c is
  * w_k prod_i blocks[t][factor[k][i]] with factor = (type*4 + alpha)*1728 +
- * (A*12 + Y)*12 + C and A < C; the weights are exact: w_k = (num_re[k] +
+ * (A*12 + Y)*12 + C and (z_A, A) < (z_C, C); the weights are exact: w_k = (num_re[k] +
  * i num_im[k]) / den[c] (den = 1, 2, 6 for the I, D_II, 3He_II operators).
  * A term of a correlator with fewer baryons than n_slots has factor -1 in
  * the unused slots.  Terms are ordered by correlator, then by factors.
  * Errors: MBC_ERR_INVALID for a NULL pointer, n_corr < 1, an unknown
- * operator or sign mode, a spin outside 0..3. */
+ * operator or sign mode, a spin outside 0..3, a source point outside 0..2. */
 mbc_status mbc_block_set_build(const mbc_block_corr_desc* corrs, int32_t n_corr, mbc_block_set** out);
 /* Sizes (any output may be NULL): correlators, slots per term (the largest
- * baryon count), block types, terms. */
+ * baryon count), block types, terms, source points (1 + the largest src_pt). */
 mbc_status mbc_block_set_dims(const mbc_block_set* s, int32_t* n_corr, int32_t* n_slots, int32_t* n_types,
-                              int64_t* n_terms);
+                              int64_t* n_terms, int32_t* n_points);
 /* Block types into caller-allocated host arrays (any may be NULL):
  * family [n_types] (MBC_FAMILY_*), projector [n_types] (0, +1, -1),
- * mom [n_types][3]. */
-mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t* projector, int32_t* mom);
+ * mom [n_types][3], src [n_types][3] (source points of A, Y, C). */
+mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t* projector, int32_t* mom,
+                               int32_t* src);
 /* Terms into caller-allocated host arrays (any may be NULL):
  * factor [n_terms][n_slots], corr_id [n_terms], num_re/num_im [n_terms],
  * den [n_corr]. */
@@ -108,7 +121,7 @@ void mbc_block_set_free(mbc_block_set* s);
 /* ---- multiplicity analytics (host only; Sec. 3, Fig. 2) ----
  * Expands one correlator in the paper's way: every written source term x
  * every sink product x every partition is a string of block factors
- * (hadron, momentum, source point, index bundle (A, Y, C, alpha)), with no
+ * (hadron, momentum, source points, index bundle (A, Y, C, alpha)), with no
  * merging of the source and no use of block antisymmetry.  Each string's
  * factors are put in lexicographic order and identical strings are counted.
  * On return *n_terms is the length of the expansion, *n_distinct the number
@@ -126,10 +139,13 @@ mbc_status mbc_block_multiplicities(const mbc_block_corr_desc* corr, int64_t max
 mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block_plan** out);
 
 typedef struct {
-  int32_t n_types, n_slots, n_corr;
+  int32_t n_types, n_slots, n_corr, n_points;
   int64_t n_terms;
-  double block_flops_per_site; /* per site, all types: per type 432 entries x (2 x nnz(Gamma)
-                                  products + phase) + 6912 x 3 complex multiply-adds */
+  int32_t n_gmats;             /* G matrices the block kernel forms per site (one per block
+                                  type, two for a type whose like antiquarks come from
+                                  different source points) */
+  double block_flops_per_site; /* per site, all G matrices: 432 entries x (2 x nnz(Gamma)
+                                  products + phase) + 6912 x 3 complex multiply-adds each */
   double contract_flops_per_t; /* per timeslice: 8 per complex multiply or add of the terms */
   int64_t tree_vertices;       /* factor-tree vertices over all correlators (roots included) */
   double tree_flops_per_t;     /* per timeslice, factor trees: 8 per non-root vertex (its
@@ -144,7 +160,8 @@ mbc_status mbc_block_workspace_bytes(const mbc_block_plan* p, int32_t T, const i
 void mbc_block_plan_destroy(mbc_block_plan* p);
 
 /* Blocks of every type (Sec. 2, momentum projected).
- * S_u, S_d   device [T][V][12][12] complex (s_dtype), 16-byte aligned,
+ * S_u, S_d   device [n_points][T][V][12][12] complex (s_dtype), 16-byte
+ *            aligned, set p the propagators from source point p;
  *            V = dims[0] dims[1] dims[2] (dims: host array, each >= 1)
  * blocks     device output [T][n_types][4][1728] complex128, both halves of
  *            the A <-> C antisymmetry written (zero where A == C)

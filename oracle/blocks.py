@@ -312,17 +312,17 @@ def block_correlator_bruteforce(S_u, S_d, op, snk_spin, src_spin, sign_mode, mom
     return complex(sig) * complex(s2) * C
 
 
-def multiplicity_histogram(op, snk_spin, src_spin, sign_mode, moms=None):
+def multiplicity_histogram(op, snk_spin, src_spin, sign_mode, moms=None, src_pts=None):
     """Sec. 3's multiplicity count of the expanded block-level correlator.
 
     Every term of the expansion (written source term x sink product x
-    partition) is a string of block factors (hadron, momentum, source point,
+    partition) is a string of block factors (hadron, momentum, source points,
     index bundle (A, Y, C, alpha)); the string's factors are put in
     lexicographic order and identical strings are counted.  Returns
     (n_terms, Counter{multiplicity: number of distinct strings}).
     """
     products, _ = O.baryon_products(op, snk_spin, sign_mode)
-    src = _source_terms(op, src_spin, sign_mode, "raw")
+    src = _source_terms(op, src_spin, sign_mode, "raw", src_pts)
     A = len(products[0][1])
     moms = [(0, 0, 0)] * A if moms is None else [tuple(m) for m in moms]
     names = sorted(O._B)
@@ -331,7 +331,7 @@ def multiplicity_histogram(op, snk_spin, src_spin, sign_mode, moms=None):
     part_cache = {}
     for _, slots in products:
         kinds = tuple(kind_of(nm)[0] for nm, _ in slots)
-        for _, fl, idx, _pts in src:
+        for _, fl, idx, pts in src:
             key = (kinds, fl)
             if key not in part_cache:
                 part_cache[key] = partitions(list(kinds), fl)
@@ -339,7 +339,7 @@ def multiplicity_histogram(op, snk_spin, src_spin, sign_mode, moms=None):
                 fac = []
                 for i, (a, y, c) in enumerate(groups):
                     nm, al = slots[i]
-                    fac.append((names.index(nm), moms[i], 0, (idx[a], idx[y], idx[c], al)))
+                    fac.append((names.index(nm), moms[i], (pts[a], pts[y], pts[c]), (idx[a], idx[y], idx[c], al)))
                 strings[tuple(sorted(fac))] += 1
                 n_terms += 1
     return n_terms, Counter(strings.values())

@@ -41,12 +41,13 @@ class PlanStats(ctypes.Structure):
 
 class BlockCorrDesc(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("snk_spin", ctypes.c_int32), ("src_spin", ctypes.c_int32),
-                ("sign_mode", ctypes.c_int32), ("mom", (ctypes.c_int32 * 3) * 3)]
+                ("sign_mode", ctypes.c_int32), ("mom", (ctypes.c_int32 * 3) * 3), ("src_pt", ctypes.c_int32 * 3)]
 
 
 class BlockPlanStats(ctypes.Structure):
     _fields_ = [("n_types", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("n_corr", ctypes.c_int32),
-                ("n_terms", ctypes.c_int64), ("block_flops_per_site", ctypes.c_double),
+                ("n_points", ctypes.c_int32), ("n_terms", ctypes.c_int64), ("n_gmats", ctypes.c_int32),
+                ("block_flops_per_site", ctypes.c_double),
                 ("contract_flops_per_t", ctypes.c_double), ("tree_vertices", ctypes.c_int64),
                 ("tree_flops_per_t", ctypes.c_double)]
 
@@ -76,8 +77,8 @@ SIGNATURES = [
     ("mbc_debug_backward_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, _P, _P, _P]),
     ("mbc_block_set_build", _I32, [ctypes.POINTER(BlockCorrDesc), _I32, ctypes.POINTER(_P)]),
     ("mbc_block_set_dims", _I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
-                                  ctypes.POINTER(_I64)]),
-    ("mbc_block_set_types", _I32, [_P, _P, _P, _P]),
+                                  ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    ("mbc_block_set_types", _I32, [_P, _P, _P, _P, _P]),
     ("mbc_block_set_export", _I32, [_P] * 6),
     ("mbc_block_set_factor_tree", _I32, [_P, _I32, ctypes.POINTER(_I64), _P, _P]),
     ("mbc_block_set_free", None, [_P]),

@@ -195,15 +195,18 @@ def _block_descs(corrs):
         for s, mom in enumerate(c.get("moms", [])):
             for d in range(3):
                 arr[i].mom[s][d] = int(mom[d])
+        for s, pt in enumerate(c.get("src_pts", [])):
+            arr[i].src_pt[s] = int(pt)
     return arr
 
 
 class BlockSet:
     """Block types and merged product terms of block-level correlators (host).
 
-    ``corrs``: list of dicts with keys op, snk_spin, src_spin, sign_mode and
-    moms (one integer momentum triple per baryon slot, written order).
-    Mirrors mbc_block_set_build.
+    ``corrs``: list of dicts with keys op, snk_spin, src_spin, sign_mode,
+    moms (one integer momentum triple per baryon slot, written order) and
+    optionally src_pts (the source point, 0..2, of each source baryon slot;
+    default all 0, a local source).  Mirrors mbc_block_set_build.
     """
 
     def __init__(self, corrs):
@@ -212,21 +215,30 @@ class BlockSet:
         B.check(B.lib().mbc_block_set_build(_block_descs(self.corrs), len(self.corrs), ctypes.byref(h)))
         self._h = h
         self._free = B.lib().mbc_block_set_free
-        nc, ns, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nc, ns, nt, npt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         nterms = ctypes.c_int64()
         B.check(B.lib().mbc_block_set_dims(h, ctypes.byref(nc), ctypes.byref(ns), ctypes.byref(nt),
-                                           ctypes.byref(nterms)))
+                                           ctypes.byref(nterms), ctypes.byref(npt)))
         self.n_corr, self.n_slots, self.n_types, self.n_terms = nc.value, ns.value, nt.value, nterms.value
+        self.n_points = npt.value
 
-    def types(self):
-        """List of (family "p"/"n", projector, momentum triple) in block order."""
+    def types(self, with_points=False):
+        """List of (family "p"/"n", projector, momentum triple) in block order,
+        each with the source points of its antiquarks (A, Y, C) appended when
+        ``with_points``."""
         fam = np.zeros(self.n_types, np.int32)
         proj = np.zeros(self.n_types, np.int32)
         mom = np.zeros((self.n_types, 3), np.int32)
+        src = np.zeros((self.n_types, 3), np.int32)
         B.check(B.lib().mbc_block_set_types(self._h, fam.ctypes.data_as(ctypes.c_void_p),
                                             proj.ctypes.data_as(ctypes.c_void_p),
-                                            mom.ctypes.data_as(ctypes.c_void_p)))
-        return [(B.FAMILIES[int(f)], int(p), tuple(int(v) for v in m)) for f, p, m in zip(fam, proj, mom)]
+                                            mom.ctypes.data_as(ctypes.c_void_p),
+                                            src.ctypes.data_as(ctypes.c_void_p)))
+        out = []
+        for f, p, m, z in zip(fam, proj, mom, src):
+            rec = (B.FAMILIES[int(f)], int(p), tuple(int(v) for v in m))
+            out.append(rec + (tuple(int(v) for v in z),) if with_points else rec)
+        return out
 
     def export(self):
         """dict of numpy arrays: factor [n_terms, n_slots], corr_id, num_re, num_im, den."""
@@ -301,9 +313,23 @@ def _workspace(plan, T, dims, device):
 
 
 def blocks(plan, S_u, S_d, dims, workspace=None, stream=None):
-    """Momentum-projected blocks [T, n_types, 4, 12, 12, 12] complex128 (mbc_blocks_compute)."""
-    dt = _check_S(S_u, S_d)
-    T, V = S_u.shape[:2]
+    """Momentum-projected blocks [T, n_types, 4, 12, 12, 12] complex128 (mbc_blocks_compute).
+
+    S_u, S_d: [T, V, 12, 12], or [n_points, T, V, 12, 12] with one set per
+    source point."""
+    npts = plan.bset.n_points
+    if S_u.dim() == 5 and S_d.dim() == 5:
+        if S_u.shape[0] != npts or S_d.shape[0] != npts:
+            raise ValueError(f"propagators must hold {npts} source-point sets")
+        dt = _check_S(S_u[0], S_d[0])
+        if not (S_u.is_contiguous() and S_d.is_contiguous()):
+            raise ValueError("S must be contiguous")
+        T, V = S_u.shape[1:3]
+    else:
+        if npts != 1:
+            raise ValueError(f"the block set uses {npts} source points: pass [n_points, T, V, 12, 12]")
+        dt = _check_S(S_u, S_d)
+        T, V = S_u.shape[:2]
     if V != dims[0] * dims[1] * dims[2]:
         raise ValueError("sites per timeslice must equal L1 L2 L3")
     out = torch.empty((T, plan.bset.n_types, 4, 12, 12, 12), dtype=torch.complex128, device=S_u.device)

@@ -422,23 +422,27 @@ mbc_status mbc_block_set_build(const mbc_block_corr_desc* corrs, int32_t n_corr,
 }
 
 mbc_status mbc_block_set_dims(const mbc_block_set* s, int32_t* n_corr, int32_t* n_slots, int32_t* n_types,
-                              int64_t* n_terms) {
+                              int64_t* n_terms, int32_t* n_points) {
   if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
   if (n_corr) *n_corr = s->s.n_corr;
   if (n_slots) *n_slots = s->s.n_slots;
   if (n_types) *n_types = int32_t(s->s.types.size());
   if (n_terms) *n_terms = int64_t(s->s.corr.size());
+  if (n_points) *n_points = s->s.n_points;
   return MBC_OK;
 }
 
-mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t* projector, int32_t* mom) {
+mbc_status mbc_block_set_types(const mbc_block_set* s, int32_t* family, int32_t* projector, int32_t* mom,
+                               int32_t* src) {
   if (!s) return fail(MBC_ERR_INVALID, "block set is NULL");
   for (size_t k = 0; k < s->s.types.size(); ++k) {
     const BlockType& t = s->s.types[k];
     if (family) family[k] = t.family;
     if (projector) projector[k] = t.proj;
-    if (mom)
-      for (int d = 0; d < 3; ++d) mom[3 * k + d] = t.mom[d];
+    for (int d = 0; d < 3; ++d) {
+      if (mom) mom[3 * k + d] = t.mom[d];
+      if (src) src[3 * k + d] = t.src[d];
+    }
   }
   return MBC_OK;
 }
@@ -500,6 +504,7 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     auto release = [](mbc_block_plan* q) {
       for (void* ptr : {static_cast<void*>(q->types), static_cast<void*>(q->factor), static_cast<void*>(q->coef),
                         static_cast<void*>(q->chunks), static_cast<void*>(q->corr_chunk),
+                        static_cast<void*>(q->block_g),
                         static_cast<void*>(q->tree_factor), static_cast<void*>(q->items),
                         static_cast<void*>(q->corr_wg)})
         if (ptr) (void)hipFree(ptr);
@@ -514,6 +519,7 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
     if ((st = upload(p->h.types, &p->types, hs)) != MBC_OK || (st = upload(p->h.factor, &p->factor, hs)) != MBC_OK ||
         (st = upload(p->h.coef, &p->coef, hs)) != MBC_OK || (st = upload(p->h.chunks, &p->chunks, hs)) != MBC_OK ||
         (st = upload(p->h.corr_chunk, &p->corr_chunk, hs)) != MBC_OK ||
+        (st = upload(p->h.block_g, &p->block_g, hs)) != MBC_OK ||
         (st = upload(p->h.tree_factor, &p->tree_factor, hs)) != MBC_OK ||
         (st = upload(p->h.items, &p->items, hs)) != MBC_OK || (st = upload(p->h.corr_wg, &p->corr_wg, hs)) != MBC_OK) {
       release(p);
@@ -534,7 +540,9 @@ mbc_status mbc_block_plan_get_stats(const mbc_block_plan* p, mbc_block_plan_stat
   out->n_types = p->h.n_types;
   out->n_slots = p->h.n_slots;
   out->n_corr = p->h.n_corr;
+  out->n_points = p->h.n_points;
   out->n_terms = p->h.n_terms;
+  out->n_gmats = int32_t(p->h.types.size());
   out->block_flops_per_site = p->h.block_flops_per_site;
   out->contract_flops_per_t = p->h.contract_flops_per_t;
   out->tree_vertices = p->h.tree_vertices;
@@ -555,6 +563,7 @@ void mbc_block_plan_destroy(mbc_block_plan* p) {
   (void)hipDeviceSynchronize();
   for (void* ptr : {static_cast<void*>(p->types), static_cast<void*>(p->factor), static_cast<void*>(p->coef),
                     static_cast<void*>(p->chunks), static_cast<void*>(p->corr_chunk),
+                    static_cast<void*>(p->block_g),
                     static_cast<void*>(p->tree_factor), static_cast<void*>(p->items),
                     static_cast<void*>(p->corr_wg)})
     if (ptr) (void)hipFree(ptr);

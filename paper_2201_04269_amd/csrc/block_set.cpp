@@ -88,23 +88,31 @@ std::vector<Partition> partitions(const int* family, int A, const uint8_t* flav,
   return out;
 }
 
+int baryons_of(int op) { return op <= MBC_OP_NEUTRON ? 1 : (op <= MBC_OP_DII ? 2 : 3); }
+
 void check_desc(const mbc_block_corr_desc& d) {
   if (d.op < MBC_OP_PROTON || d.op > MBC_OP_HE3_II) throw std::invalid_argument("unknown operator");
   if (d.sign_mode != MBC_SIGNS_EXACT && d.sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
   if (d.snk_spin < 0 || d.snk_spin > 3 || d.src_spin < 0 || d.src_spin > 3)
     throw std::invalid_argument("spin index out of range");
+  for (int i = 0; i < baryons_of(d.op); ++i)
+    if (d.src_pt[i] < 0 || d.src_pt[i] > 2) throw std::invalid_argument("source point out of range (0..2)");
 }
 
-int type_index(std::vector<BlockType>* types, int family, int proj, const int32_t* mom) {
+int type_index(std::vector<BlockType>* types, int family, int proj, const int32_t* mom, const int* src) {
   for (size_t k = 0; k < types->size(); ++k) {
     const BlockType& t = (*types)[k];
-    if (t.family == family && t.proj == proj && t.mom[0] == mom[0] && t.mom[1] == mom[1] && t.mom[2] == mom[2])
+    if (t.family == family && t.proj == proj && t.mom[0] == mom[0] && t.mom[1] == mom[1] && t.mom[2] == mom[2] &&
+        t.src[0] == src[0] && t.src[1] == src[1] && t.src[2] == src[2])
       return int(k);
   }
   BlockType t;
   t.family = family;
   t.proj = proj;
-  for (int d = 0; d < 3; ++d) t.mom[d] = mom[d];
+  for (int d = 0; d < 3; ++d) {
+    t.mom[d] = mom[d];
+    t.src[d] = src[d];
+  }
   types->push_back(t);
   return int(types->size()) - 1;
 }
@@ -129,17 +137,15 @@ void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out
     check_desc(d);
     int den = 1;
     const std::vector<SinkProduct> prods = sink_products(d.op, d.snk_spin, d.sign_mode, &den);
-    const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, true);
+    const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, true, d.src_pt);
     out->den[c] = den;
+    for (int i = 0; i < baryons_of(d.op); ++i) out->n_points = std::max(out->n_points, d.src_pt[i] + 1);
     const int A = prods.empty() ? 0 : prods[0].nb;
     out->n_slots = std::max(out->n_slots, A);
     std::vector<Pending> terms;
     for (const SinkProduct& sp : prods) {
-      int family[3], type[3];
-      for (int i = 0; i < sp.nb; ++i) {
-        family[i] = sp.b[i].family;
-        type[i] = type_index(&out->types, sp.b[i].family, sp.b[i].proj, d.mom[i]);
-      }
+      int family[3];
+      for (int i = 0; i < sp.nb; ++i) family[i] = sp.b[i].family;
       if (src.empty()) continue;
       // every canonical key has the same flavour sequence u..u d..d
       const std::vector<Partition> parts = partitions(family, sp.nb, src[0].flav, src[0].n);
@@ -150,9 +156,13 @@ void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out
           if (P.sign < 0) t.w = {-t.w.re, -t.w.im};
           t.f = {-1, -1, -1};
           for (int i = 0; i < sp.nb; ++i) {
-            const int a = key.idx[P.grp[i][0]], y = key.idx[P.grp[i][1]], cc = key.idx[P.grp[i][2]];
-            if (a >= cc) throw std::logic_error("like antiquarks of a canonical key out of order");
-            t.f[i] = ((type[i] * 4 + sp.b[i].spin) * 12 + a) * 144 + y * 12 + cc;
+            const int ga = P.grp[i][0], gy = P.grp[i][1], gc = P.grp[i][2];
+            const int a = key.idx[ga], y = key.idx[gy], cc = key.idx[gc];
+            if (12 * key.pt[ga] + a >= 12 * key.pt[gc] + cc)
+              throw std::logic_error("like antiquarks of a canonical key out of order");
+            const int srcs[3] = {key.pt[ga], key.pt[gy], key.pt[gc]};
+            const int type = type_index(&out->types, sp.b[i].family, sp.b[i].proj, d.mom[i], srcs);
+            t.f[i] = ((type * 4 + sp.b[i].spin) * 12 + a) * 144 + y * 12 + cc;
           }
           std::sort(t.f.begin(), t.f.begin() + sp.nb);
           terms.push_back(t);
@@ -218,11 +228,29 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
   out->n_types = int(s.types.size());
   out->n_slots = s.n_slots;
   out->n_corr = s.n_corr;
+  out->n_points = s.n_points;
   out->n_terms = int64_t(s.corr.size());
+  // G types: a block type with source points (zA, zY, zC) is
+  // G(zA; zC, zY)[(alpha, A)][(C, Y)] - G(zC; zA, zY)[(alpha, C)][(A, Y)]
+  // (rows from S1 at the first point, B from S1 and S2 at the other two);
+  // one G when zA == zC
+  std::vector<BlockType> gt;  // src = (row point, B's S1 point, B's S2 point)
   for (const BlockType& t : s.types) {
+    for (int w = 0; w < 2; ++w) {
+      BlockType g = t;
+      g.src[0] = w == 0 ? t.src[0] : t.src[2];
+      g.src[1] = w == 0 ? t.src[2] : t.src[0];
+      g.src[2] = t.src[1];
+      out->block_g.push_back(type_index(&gt, g.family, g.proj, g.mom, g.src));
+    }
+  }
+  for (const BlockType& t : gt) {
     BlockTypeDev d;
     d.family = t.family;
-    for (int k = 0; k < 3; ++k) d.mom[k] = t.mom[k];
+    for (int k = 0; k < 3; ++k) {
+      d.mom[k] = t.mom[k];
+      d.pt[k] = t.src[k];
+    }
     int64_t re[16], im[16];
     gamma_cg5(t.proj, re, im);
     for (int be = 0; be < 4; ++be)
@@ -350,7 +378,7 @@ bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64
   check_desc(d);
   int den = 1;
   const std::vector<SinkProduct> prods = sink_products(d.op, d.snk_spin, d.sign_mode, &den);
-  const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, false);
+  const std::vector<FieldTerm> src = source_terms(d.op, d.src_spin, d.sign_mode, false, d.src_pt);
   // partitions depend on the slots' families and the source term's flavour
   // sequence only: count the expansion before forming any string
   std::unordered_map<uint64_t, std::vector<Partition>> cache;
@@ -378,12 +406,11 @@ bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64
   std::vector<Factors> strings;
   strings.reserve(size_t(total));
   for (const SinkProduct& sp : prods) {
-    int family[3], id[3];
+    int family[3];
     uint64_t fkey = 0;
     for (int i = 0; i < sp.nb; ++i) {
       family[i] = sp.b[i].family;
       fkey = fkey * 2 + uint64_t(family[i]);
-      id[i] = type_index(&ids, sp.b[i].family, sp.b[i].proj, d.mom[i]);
     }
     for (const FieldTerm& t : src) {
       uint64_t key = fkey;
@@ -392,8 +419,11 @@ bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64
       for (const Partition& P : cache.at(key)) {
         Factors f = {-1, -1, -1};
         for (int i = 0; i < sp.nb; ++i) {
-          const int a = t.idx[P.grp[i][0]], y = t.idx[P.grp[i][1]], cc = t.idx[P.grp[i][2]];
-          f[i] = (((id[i] * 12 + a) * 12 + y) * 12 + cc) * 4 + sp.b[i].spin;
+          const int ga = P.grp[i][0], gy = P.grp[i][1], gc = P.grp[i][2];
+          const int a = t.idx[ga], y = t.idx[gy], cc = t.idx[gc];
+          const int srcs[3] = {t.pt[ga], t.pt[gy], t.pt[gc]};
+          const int id = type_index(&ids, sp.b[i].family, sp.b[i].proj, d.mom[i], srcs);
+          f[i] = (((id * 12 + a) * 12 + y) * 12 + cc) * 4 + sp.b[i].spin;
         }
         std::sort(f.begin(), f.begin() + sp.nb);
         strings.push_back(f);

@@ -51,9 +51,10 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 struct BlockGArgs {
   const void* S_u;
   const void* S_d;
-  const BlockTypeDev* types;
-  double2* partial;  // [n_types][T][nch][48][144]
+  const BlockTypeDev* types;  // G types
+  double2* partial;           // [n_gtypes][T][nch][48][144]
   int64_t V, chunk;
+  int64_t pstride;            // complex entries per source point's propagator set
   int T, nch;
   int L1, L2, L3;
 };
@@ -78,11 +79,16 @@ __device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int v, int
 // cores work on this one, over two LDS buffers, measured no faster.)
 template <typename SIN, int NS>
 __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
-  __shared__ double2 sS1[NS][144], sS2[NS][144], sB[NS][432], sPh[kBlockMaxChunk];
+  __shared__ double2 sS1[NS][144], sS2[NS][144], sS1b[NS][144], sB[NS][432], sPh[kBlockMaxChunk];
   const int ch = blockIdx.x, t = blockIdx.y, ty = blockIdx.z;
   const BlockTypeDev& bt = a.types[ty];
-  const SIN* S1 = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_u : a.S_d);
-  const SIN* S2 = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_d : a.S_u);
+  // S1 of the rows, S1 and S2 of B, each from its own source point's set
+  const SIN* S1q = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_u : a.S_d);
+  const SIN* S2q = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_d : a.S_u);
+  const SIN* S1 = S1q + bt.pt[0] * a.pstride;
+  const SIN* S1B = S1q + bt.pt[1] * a.pstride;
+  const SIN* S2 = S2q + bt.pt[2] * a.pstride;
+  const bool mixed = bt.pt[1] != bt.pt[0];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int64_t v0 = int64_t(ch) * a.chunk;
@@ -98,21 +104,24 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
     acci[m] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
 
-  // the 288 NS entries of a round (S1 then S2 of each site), NL per thread;
-  // sites past the chunk's end read as zero (their B vanishes)
-  constexpr int NE = 288 * NS;
+  // the entries of a round (S1, S2 and, for mixed source points, the S1 of
+  // B, of each site), NL per thread; sites past the chunk's end read as zero
+  // (their B vanishes)
+  constexpr int NE = 432 * NS;
   constexpr int NL = (NE + kBT - 1) / kBT;
+  const int ne = (mixed ? 432 : 288) * NS;
   double2 pre[NL];
   auto fetch = [&](int64_t v) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int e = tid + k * kBT;
       pre[k] = make_double2(0.0, 0.0);
-      if (e < NE) {
-        const int s = e / 288, r = e % 288;
+      if (e < ne) {
+        const int per = mixed ? 432 : 288;
+        const int s = e / per, r = e % per;
         if (v + s < v1) {
           const int64_t base = (site0 + v + s) * 144;
-          pre[k] = r < 144 ? load_c(S1, base + r) : load_c(S2, base + r - 144);
+          pre[k] = r < 144 ? load_c(S1, base + r) : (r < 288 ? load_c(S2, base + r - 144) : load_c(S1B, base + r - 288));
         }
       }
     }
@@ -121,12 +130,15 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int e = tid + k * kBT;
-      if (e < NE) {
-        const int s = e / 288, r = e % 288;
+      if (e < ne) {
+        const int per = mixed ? 432 : 288;
+        const int s = e / per, r = e % per;
         if (r < 144)
           sS1[s][r] = pre[k];
-        else
+        else if (r < 288)
           sS2[s][r - 144] = pre[k];
+        else
+          sS1b[s][r - 288] = pre[k];
       }
     }
   };
@@ -138,11 +150,12 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
       const int c = r / 36, X = (r / 3) % 12, Y0 = 4 * (r % 3);
       // (a, b, c) cyclic (eps = +1) and anticyclic (eps = -1)
       const int a1 = c == 2 ? 0 : c + 1, b1 = c == 0 ? 2 : c - 1;
+      const double2* s1b = mixed ? sS1b[s] : sS1[s];
       double2 x1[4], x2[4];
 #pragma unroll
       for (int be = 0; be < 4; ++be) {
-        x1[be] = sS1[s][(4 * a1 + be) * 12 + X];
-        x2[be] = sS1[s][(4 * b1 + be) * 12 + X];
+        x1[be] = s1b[(4 * a1 + be) * 12 + X];
+        x2[be] = s1b[(4 * b1 + be) * 12 + X];
       }
       const double2 ph = v + s < v1 ? sPh[v + s - v0] : make_double2(0.0, 0.0);
 #pragma unroll
@@ -221,21 +234,25 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
 }
 
 // blocks[t][type][alpha][A][Y][C] = sum over chunks (in order) of
-// G[(alpha, A)][(C, Y)] - G[(alpha, C)][(A, Y)]; exactly zero for A == C.
-// One thread per entry: grid (entry blocks of kBT, T, n_types).
+// G1[(alpha, A)][(C, Y)] - G2[(alpha, C)][(A, Y)], with (G1, G2) the type's
+// two G types (equal when its like antiquarks share a source point: then
+// exactly zero for A == C).  One thread per entry: grid (entry blocks of
+// kBT, T, n_types).
 __global__ __launch_bounds__(kBT) void block_reduce_kernel(const double2* __restrict__ partial,
+                                                           const int32_t* __restrict__ block_g,
                                                            double2* __restrict__ blocks, int T, int n_types,
                                                            int nch) {
   const int e = blockIdx.x * kBT + threadIdx.x, t = blockIdx.y, ty = blockIdx.z;
   if (e >= kBlockEntries) return;
-  const double2* P = partial + (int64_t(ty) * T + t) * nch * kBlockEntries;
+  const double2* P1 = partial + (int64_t(block_g[2 * ty]) * T + t) * nch * kBlockEntries;
+  const double2* P2 = partial + (int64_t(block_g[2 * ty + 1]) * T + t) * nch * kBlockEntries;
   const int al = e / 1728, A = (e / 144) % 12, Y = (e / 12) % 12, C = e % 12;
   double2 s = make_double2(0.0, 0.0);
-  if (A != C) {
+  if (A != C || P1 != P2) {
     const int g1 = (al * 12 + A) * 144 + C * 12 + Y;
     const int g2 = (al * 12 + C) * 144 + A * 12 + Y;
     for (int ch = 0; ch < nch; ++ch)
-      s = cadd(s, csub(P[int64_t(ch) * kBlockEntries + g1], P[int64_t(ch) * kBlockEntries + g2]));
+      s = cadd(s, csub(P1[int64_t(ch) * kBlockEntries + g1], P2[int64_t(ch) * kBlockEntries + g2]));
   }
   blocks[(int64_t(t) * n_types + ty) * kBlockEntries + e] = s;
 }
@@ -371,7 +388,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V) {
   BlockLaunch L;
-  const int64_t per = int64_t(T) * std::max(h.n_types, 1);
+  const int64_t per = int64_t(T) * std::max<int64_t>(int64_t(h.types.size()), 1);
   int64_t nch = (1536 + per - 1) / per;
   nch = std::max<int64_t>(nch, (V + kBlockMaxChunk - 1) / kBlockMaxChunk);
   if (nch > V) nch = V;
@@ -383,7 +400,7 @@ BlockLaunch block_launch_shape(const BlockPlanHost& h, int T, int64_t V) {
 
 size_t block_workspace_bytes(const BlockPlanHost& h, int T, int64_t V) {
   const BlockLaunch L = block_launch_shape(h, T, V);
-  const size_t g = align256(size_t(h.n_types) * size_t(T) * size_t(L.nch) * kBlockEntries * 16);
+  const size_t g = align256(h.types.size() * size_t(T) * size_t(L.nch) * kBlockEntries * 16);
   return std::max(g, block_contract_workspace_bytes(h, T));
 }
 
@@ -405,13 +422,14 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
   a.types = p->types;
   a.partial = static_cast<double2*>(workspace);
   a.V = V;
+  a.pstride = int64_t(T) * V * 144;
   a.chunk = L.chunk;
   a.T = T;
   a.nch = L.nch;
   a.L1 = dims[0];
   a.L2 = dims[1];
   a.L3 = dims[2];
-  const dim3 grid(static_cast<unsigned>(L.nch), static_cast<unsigned>(T), static_cast<unsigned>(h.n_types));
+  const dim3 grid(static_cast<unsigned>(L.nch), static_cast<unsigned>(T), static_cast<unsigned>(h.types.size()));
   if (s_c64)
     hipLaunchKernelGGL((block_g_kernel<float2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
   else
@@ -420,9 +438,8 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
   if (e != hipSuccess) return e;
   const dim3 rgrid(static_cast<unsigned>((kBlockEntries + kBT - 1) / kBT), static_cast<unsigned>(T),
                    static_cast<unsigned>(h.n_types));
-  hipLaunchKernelGGL(block_reduce_kernel, rgrid, dim3(kBT), 0, st,
-                     static_cast<const double2*>(workspace), reinterpret_cast<double2*>(blocks), T, h.n_types,
-                     L.nch);
+  hipLaunchKernelGGL(block_reduce_kernel, rgrid, dim3(kBT), 0, st, static_cast<const double2*>(workspace),
+                     p->block_g, reinterpret_cast<double2*>(blocks), T, h.n_types, L.nch);
   return hipGetLastError();
 }
 

@@ -333,12 +333,24 @@ std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den
   return out;
 }
 
-std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical_form) {
+std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical_form, const int32_t* pts) {
   if (sign_mode != MBC_SIGNS_EXACT && sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
   if (spin < 0 || spin > 3) throw std::invalid_argument("spin index out of range");
   int den = 1;
-  const std::vector<Term> terms = operator_terms(op, spin, sign_mode, &den);
+  std::vector<Term> terms = operator_terms(op, spin, sign_mode, &den);
+  // field i of slot i / 3 at point pts[i / 3], carried as index 12 * point + a
+  // so that sorting orders the fields of one flavour by (point, index)
+  for (Term& t : terms)
+    for (int i = 0; i < t.n; ++i) {
+      const int p = pts ? pts[i / 3] : 0;
+      if (p < 0 || p > 2) throw std::invalid_argument("source point out of range (0..2)");
+      t.idx[i] = uint8_t(12 * p + t.idx[i]);
+    }
   std::vector<FieldTerm> out;
+  auto split = [](FieldTerm& f, int i, int v) {
+    f.idx[i] = uint8_t(v % 12);
+    f.pt[i] = uint8_t(v / 12);
+  };
   if (!canonical_form) {
     out.reserve(terms.size());
     for (const Term& t : terms) {
@@ -347,7 +359,7 @@ std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canoni
       f.n = t.n;
       for (int i = 0; i < t.n; ++i) {
         f.flav[i] = t.flav[i];
-        f.idx[i] = t.idx[i];
+        split(f, i, t.idx[i]);
       }
       out.push_back(f);
     }
@@ -362,11 +374,11 @@ std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canoni
     f.n = u.n + d.n;
     for (int i = 0; i < u.n; ++i) {
       f.flav[i] = kFlavU;
-      f.idx[i] = u.v[i];
+      split(f, i, u.v[i]);
     }
     for (int i = 0; i < d.n; ++i) {
       f.flav[u.n + i] = kFlavD;
-      f.idx[u.n + i] = d.v[i];
+      split(f, u.n + i, d.v[i]);
     }
     out.push_back(f);
   }

@@ -58,27 +58,33 @@ struct SinkProduct {
 };
 std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den);
 // A source operator term: coefficient (not conjugated) and n antiquark
-// fields (flavour, index).  canonical: the sorted keys u..u d..d of eq. 1's
-// index set (flavour-separation and sorting signs in the coefficient);
+// fields (flavour, index, source point).  Baryon slot i of the written
+// source sits at source point pts[i] (pts == nullptr: all at point 0).
+// canonical: the sorted keys u..u d..d, each flavour ordered by (point,
+// index), flavour-separation and sorting signs in the coefficient;
 // otherwise the written terms in written field order.
 struct FieldTerm {
   Gauss coef;
   int n = 0;
   uint8_t flav[12];
   uint8_t idx[12];
+  uint8_t pt[12];
 };
-std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical);
+std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical, const int32_t* pts);
 // Entries (re, im) of C gamma5 (proj 0) or C gamma5 P+- (proj +-1), row-major 4x4.
 void gamma_cg5(int proj, int64_t re[16], int64_t im[16]);
 
 // ---------------------------------------------------------------------------
 // Block-level correlators (block_set.cpp): types and merged product terms.
+// A block type: family, projector, sink momentum and the source points of
+// its antiquarks (A, Y, C) in block order.
 struct BlockType {
   int family = 0, proj = 0;
   int mom[3] = {0, 0, 0};
+  int src[3] = {0, 0, 0};
 };
 struct BlockSet {
-  int n_corr = 0, n_slots = 0;
+  int n_corr = 0, n_slots = 0, n_points = 1;
   std::vector<BlockType> types;
   std::vector<int32_t> factor;         // [n_terms][n_slots], -1 in unused slots
   std::vector<int32_t> corr;           // [n_terms]
@@ -238,12 +244,15 @@ struct PlanDevice {
 // Block plan: per block type the non-zero entries of its Gamma and its
 // momentum (read by every workgroup of the block kernel), the terms as
 // factor indices and FP64 weights, and term chunks of one correlator each.
-// C gamma5 and C gamma5 P+- have at most one non-zero entry per row, a real
-// +-1 in the Dirac basis: row beta is (gcol[beta], gsign[beta]), gcol = -1 for
-// a zero row.
+// One G matrix of the block kernel (a "G type"): family, Gamma, momentum and
+// the source points of its three propagator factors: pt[0] for the S1 rows,
+// pt[1] and pt[2] for the S1 and S2 of B.  C gamma5 and C gamma5 P+- have at
+// most one non-zero entry per row, a real +-1 in the Dirac basis: row beta
+// is (gcol[beta], gsign[beta]), gcol = -1 for a zero row.
 struct BlockTypeDev {
   int32_t family = 0, n_gamma = 0;
   int32_t mom[3] = {0, 0, 0};
+  int32_t pt[3] = {0, 0, 0};
   int32_t gcol[4] = {-1, -1, -1, -1};
   double gsign[4] = {0, 0, 0, 0};
 };
@@ -254,9 +263,12 @@ constexpr int kTreeItemInts = 6;
 constexpr int kTreeMaxItemsPerThread = 8;
 constexpr int kBlockMaxChunk = 1024;   // sites per workgroup of the block kernel (LDS phase table)
 struct BlockPlanHost {
-  int n_types = 0, n_slots = 0, n_corr = 0;
+  int n_types = 0, n_slots = 0, n_corr = 0, n_points = 1;
   int64_t n_terms = 0;
+  // G types, and for each block type the two G types whose difference it is:
+  // f(A, Y, C) = G_g1[(alpha, A)][(C, Y)] - G_g2[(alpha, C)][(A, Y)]
   std::vector<BlockTypeDev> types;
+  std::vector<int32_t> block_g;  // [n_types][2]
   std::vector<int32_t> factor;   // [n_terms][n_slots]
   std::vector<double> coef;      // [n_terms][2]
   std::vector<int32_t> chunks;   // [n_chunks][3]: correlator, first term, end term
@@ -299,6 +311,7 @@ struct mbc_block_plan {
   double* coef = nullptr;
   int32_t* chunks = nullptr;
   int32_t* corr_chunk = nullptr;
+  int32_t* block_g = nullptr;
   int32_t* tree_factor = nullptr;
   int32_t* items = nullptr;
   int32_t* corr_wg = nullptr;

@@ -18,10 +18,12 @@ NAME = {("p", 0): "p", ("n", 0): "n", ("p", 1): "p+", ("p", -1): "p-", ("n", 1):
 
 
 def contract_terms_with_oracle_blocks(bset, S_u, S_d, dims):
-    """C [n_corr, T] = sum over the library's terms of w_k prod_i f[t][factor_i]."""
-    T = S_u.shape[0]
-    blk = np.stack([OB.block(S_u, S_d, NAME[(fam, proj)], mom, dims) for fam, proj, mom in bset.types()],
-                   axis=1).reshape(T, -1)
+    """C [n_corr, T] = sum over the library's terms of w_k prod_i f[t][factor_i].
+
+    S_u, S_d: [T, V, 12, 12] or [P, T, V, 12, 12] (one set per source point)."""
+    T = S_u.shape[-4]
+    blk = np.stack([OB.block(S_u, S_d, NAME[(fam, proj)], mom, dims, srcs=z)
+                    for fam, proj, mom, z in bset.types(with_points=True)], axis=1).reshape(T, -1)
     e = bset.export()
     w = (e["num_re"] + 1j * e["num_im"]) / e["den"][e["corr_id"]]
     prod = np.ones((T, bset.n_terms), dtype=np.complex128) * w[None, :]
@@ -84,13 +86,13 @@ def test_dinucleon_terms_are_products_of_nine_partitions():
 
 @pytest.mark.parametrize("corr", [dict(op="proton", snk_spin=2, src_spin=1),
                                   dict(op="DI"), dict(op="DII", sign_mode="exact"),
-                                  dict(op="DII", sign_mode="r2")])
+                                  dict(op="DII", sign_mode="r2"), dict(op="DI", src_pts=(0, 1))])
 def test_multiplicity_histogram_matches_the_oracle_exactly(corr):
     A = 1 if corr["op"] == "proton" else 2
     c = dict(corr, moms=[(0, 0, 0)] * A)
     n, n_distinct, hist = api.block_multiplicities(c)
     on, ohist = OB.multiplicity_histogram(corr["op"], corr.get("snk_spin", 0), corr.get("src_spin", 0),
-                                          corr.get("sign_mode", "exact"))
+                                          corr.get("sign_mode", "exact"), src_pts=corr.get("src_pts"))
     assert n == on
     assert n_distinct == sum(ohist.values())
     assert {m: int(k) for m, k in enumerate(hist) if k} == dict(ohist)
@@ -111,7 +113,10 @@ def test_multiplicity_guard_and_errors():
     assert L.mbc_block_set_build(api._block_descs([dict(op="DI")]), 0, ctypes.byref(h)) == 1
     bad = api._block_descs([dict(op="proton", snk_spin=4)])
     assert L.mbc_block_set_build(bad, 1, ctypes.byref(h)) == 1
-    assert L.mbc_block_set_dims(None, None, None, None, None) == 1
+    assert L.mbc_block_set_dims(None, None, None, None, None, None) == 1
+    bad = api._block_descs([dict(op="DI", src_pts=(0, 3))])
+    assert L.mbc_block_set_build(bad, 1, ctypes.byref(h)) == 1
+    assert b"source point" in L.mbc_last_error()
     L.mbc_block_set_free(None)
     L.mbc_block_plan_destroy(None)
     assert L.mbc_blocks_compute(None, None, None, 0, 1, None, None, None, 0, None) == 1
@@ -152,3 +157,25 @@ def test_factor_trees_equal_the_oracle_construction_and_value(corrs):
         if m.any():
             A = int((e["factor"][m][0] >= 0).sum())
             assert len(fac) == 1 + len({tuple(f[:k]) for f in e["factor"][m].tolist() for k in range(1, A + 1)})
+
+
+@pytest.mark.parametrize("corr", [
+    dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)], src_pts=(0, 1)),
+    dict(op="DII", moms=[(1, 0, 0), (-1, 0, 0)], src_pts=(1, 0)),
+    dict(op="proton", snk_spin=2, src_spin=1, moms=[(1, 0, 0)], src_pts=(1,)),
+])
+def test_displaced_sources_reproduce_the_oracle_correlator(corr):
+    # one propagator set per source point; mixed-source block types
+    dims, T = (3, 1, 1), 1
+    P = 1 + max(corr["src_pts"])
+    S = [synth.iid(T, 3, seed=80 + p) for p in range(P)]
+    S_u, S_d = np.stack([x[0] for x in S]), np.stack([x[1] for x in S])
+    bset = api.BlockSet([corr])
+    assert bset.n_points == P
+    got = contract_terms_with_oracle_blocks(bset, S_u, S_d, dims)[0]
+    ref = OB.block_correlator(S_u, S_d, corr["op"], corr.get("snk_spin", 0), corr.get("src_spin", 0), "exact",
+                              corr["moms"], dims, src_pts=corr["src_pts"])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    if corr["op"] == "DII":
+        assert np.abs(ref).max() > 1.0
+        assert any(z[0] != z[2] for *_, z in bset.types(with_points=True))  # mixed-source types occur

@@ -202,3 +202,34 @@ def test_blocks_and_correlators_are_bitwise_reproducible():
                      api.block_contract(plan, blk, method="terms").cpu().numpy()])
     for x, y in zip(*runs):
         assert np.array_equal(x.view(np.float64), y.view(np.float64))
+
+
+def test_displaced_sources_mixed_source_blocks_and_correlators():
+    # two source points (a propagator set each); D_I and exact-sign D_II with
+    # the source baryons displaced, and a proton from the second point
+    api = _api()
+    dims, T = (3, 2, 1), 2
+    corrs = [dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)], src_pts=(0, 1)),
+             dict(op="DII", moms=[(1, 0, 0), (-1, 0, 0)], src_pts=(0, 1)),
+             dict(op="proton", snk_spin=1, src_spin=3, moms=[(0, 1, 0)], src_pts=(1,))]
+    S = [synth.iid(T, 6, seed=90 + p) for p in range(2)]
+    Su, Sd = np.stack([x[0] for x in S]), np.stack([x[1] for x in S])
+    bset = api.BlockSet(corrs)
+    assert bset.n_points == 2
+    plan = api.BlockPlan(bset)
+    assert plan.stats["n_gmats"] > bset.n_types  # mixed-source types take two G matrices
+    C, blk = api.block_correlators(plan, torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda(), dims)
+    Ct = api.block_contract(plan, blk, method="terms")
+    torch.cuda.synchronize()
+    C, Ct, blk = C.cpu().numpy(), Ct.cpu().numpy(), blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
+    ref = {}
+    for k, (f, p, m, z) in enumerate(bset.types(with_points=True)):
+        want = OB.block(Su, Sd, NAME[(f, p)], m, dims, srcs=z)
+        ref[(NAME[(f, p)], m, z)] = want
+        assert np.abs(blk[:, k] - want).max() <= 1e-13 * 6 * np.abs(want).max(), (f, p, m, z)
+    for c, corr in enumerate(corrs):
+        want = OB.block_correlator(Su, Sd, corr["op"], corr.get("snk_spin", 0), corr.get("src_spin", 0), "exact",
+                                   corr["moms"], dims, src_pts=corr["src_pts"], blocks=ref)
+        for got in (C[c], Ct[c]):
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (c, np.abs(got - want).max())
+    assert np.abs(C[1]).max() > 1.0  # exact-sign D_II survives displaced sources
