@@ -218,13 +218,15 @@ def partitions(slot_kinds, src_flav):
 
 
 def block_correlator(S_u, S_d, op, snk_spin, src_spin, sign_mode, moms, dims, source="canonical",
-                     blocks=None, src_pts=None):
+                     blocks=None, src_pts=None, compute_missing=True):
     """C[t] of one block-level correlator, from blocks and the partition sum.
 
     moms: one integer momentum triple per sink baryon slot; src_pts: the
     source point of each source baryon slot (default all 0, a local source),
     with S_u, S_d [P, T, V, 12, 12] for P points.  ``blocks`` may hold
-    precomputed {(name, mom, srcs): block(...)} arrays.  Returns [T] complex128.
+    precomputed {(name, mom, srcs): block(...)} arrays; a missing one is
+    computed over every site, or raises KeyError if not compute_missing.
+    Returns [T] complex128.
     """
     products, s2 = O.baryon_products(op, snk_spin, sign_mode)
     src = _source_terms(op, src_spin, sign_mode, source, src_pts)
@@ -246,6 +248,8 @@ def block_correlator(S_u, S_d, op, snk_spin, src_spin, sign_mode, moms, dims, so
                 for i, (a, y, c) in enumerate(groups):
                     key = (names[i], tuple(moms[i]), (pts[a], pts[y], pts[c]))
                     if key not in blocks:
+                        if not compute_missing:
+                            raise KeyError(key)
                         blocks[key] = block(S_u, S_d, names[i], moms[i], dims, srcs=key[2])
                     xi = (idx[:, a] * 12 + idx[:, y]) * 12 + idx[:, c]
                     prod *= blocks[key][:, slots[i][1], xi]

@@ -49,7 +49,8 @@ def gpu_blocks(corrs, Su, Sd, dims, c64=False):
 
 
 def oracle_blocks(bset, Su, Sd, dims):
-    return {(NAME[(f, p)], m): OB.block(Su, Sd, NAME[(f, p)], m, dims) for f, p, m in bset.types()}
+    return {(NAME[(f, p)], m, z): OB.block(Su, Sd, NAME[(f, p)], m, dims, srcs=z)
+            for f, p, m, z in bset.types(with_points=True)}
 
 
 def abs_scale(bset, blocks):
@@ -68,7 +69,7 @@ def abs_scale(bset, blocks):
 
 def check_blocks(blk, ref, bset, V):
     for k, (f, p, m) in enumerate(bset.types()):
-        want = ref[(NAME[(f, p)], m)]
+        want = ref[(NAME[(f, p)], m, (0, 0, 0))]
         for t in range(blk.shape[0]):
             scale = np.abs(want[t]).max()
             err = np.abs(blk[t, k] - want[t]).max()
