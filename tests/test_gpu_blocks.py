@@ -57,7 +57,8 @@ def abs_scale(bset, blocks):
     """A[c, t] = sum_k |w_k| prod_i |f_i| over the library's terms."""
     e = bset.export()
     T = next(iter(blocks.values())).shape[0]
-    flat = np.stack([np.abs(blocks[(NAME[(f, p)], m)]) for f, p, m in bset.types()], axis=1).reshape(T, -1)
+    flat = np.stack([np.abs(blocks[(NAME[(f, p)], m, z)]) for f, p, m, z in bset.types(with_points=True)],
+                    axis=1).reshape(T, -1)
     w = np.abs((e["num_re"] + 1j * e["num_im"]) / e["den"][e["corr_id"]])
     prod = np.ones((T, bset.n_terms)) * w[None, :]
     for s in range(bset.n_slots):
