@@ -20,7 +20,9 @@ Workloads (synthetic inputs, the paper's propagators are not available):
 
 Beside each workload the hadron-block path (Sec. 2 blocks with sink
 momentum projection, Sec. 3 block-level correlators; FP64) is timed on the
-same propagators and reported under "blocks" (--no-blocks skips it).
+same propagators and reported under "blocks" (--no-blocks skips it); for
+di_mixed also with displaced sources (a second propagator set), under
+"blocks"/"displaced".
 
 Prints one JSON line (rank 0).  `value` is index entries contracted per
 second, sum over correlators of |I_c| times the number of sites, divided by
@@ -89,17 +91,28 @@ def block_corrs(name):
     return None
 
 
-def bench_blocks(api, torch, name, su, sd, L, steps, warmup):
+def displaced_corrs(name):
+    """Block-level correlators with displaced sources timed beside a workload:
+    di_mixed: D_I and exact-sign D_II with the source nucleons at two points
+    (the second point's propagators drawn with seed 5) and the sink nucleons
+    back to back at +-(1, 0, 0)."""
+    if name == "di_mixed":
+        return [dict(op=op, moms=[(1, 0, 0), (-1, 0, 0)], src_pts=(0, 1)) for op in ("DI", "DII")], 5
+    return None, None
+
+
+def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
     """Hadron blocks (one launch pair) and their contraction, timed with HIP
-    events on the launch stream; FP64."""
-    corrs = block_corrs(name)
+    events on the launch stream; FP64.  su, sd: [T, V, 12, 12] or
+    [n_points, T, V, 12, 12]."""
+    corrs = block_corrs(name) if corrs is None else corrs
     if corrs is None:
         return None
     t0 = time.perf_counter()
     bset = api.BlockSet(corrs)
     plan = api.BlockPlan(bset)
     st = plan.stats
-    T, V = su.shape[:2]
+    T, V = su.shape[-4:-2]
     dims = (L, L, L)
     ws = torch.empty(plan.workspace_bytes(T, dims), dtype=torch.uint8, device=su.device)
     print(f"[bench] blocks: {bset.n_types} types, {bset.n_terms} terms ({time.perf_counter() - t0:.1f}s)",
@@ -126,7 +139,8 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup):
     flops_b = st["block_flops_per_site"] * T * V
     print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction by factor trees "
           f"{ms_tree:.3f} ms, by terms {ms_terms:.3f} ms", file=sys.stderr, flush=True)
-    return {"correlators": len(corrs), "block_types": bset.n_types, "terms": bset.n_terms,
+    return {"correlators": len(corrs), "block_types": bset.n_types, "g_matrices": st["n_gmats"],
+            "source_points": bset.n_points, "terms": bset.n_terms,
             "tree_vertices": st["tree_vertices"], "dtype": "f64",
             "ms_blocks": ms_b, "ms_contract_tree": ms_tree, "ms_contract_terms": ms_terms,
             "sites_per_s": T * V / ((ms_b + ms_tree) * 1e-3),
@@ -353,6 +367,16 @@ def main():
         blk = bench_blocks(api, torch, wl["name"], su, sd, wl["L"], args.steps, args.warmup)
         if blk is not None:
             out["blocks"] = blk
+            dcorrs, seed2 = displaced_corrs(wl["name"])
+            if dcorrs is not None:
+                from paper_2201_04269_amd import synth
+                Su2, Sd2 = synth.iid(T, V, seed=seed2)
+                su2 = torch.stack([su, torch.from_numpy(Su2).to(dev)])
+                sd2 = torch.stack([sd, torch.from_numpy(Sd2).to(dev)])
+                del Su2, Sd2
+                out["blocks"]["displaced"] = bench_blocks(api, torch, wl["name"], su2, sd2, wl["L"], args.steps,
+                                                          args.warmup, corrs=dcorrs)
+                del su2, sd2
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, Su, Sd, nnz)
     print(json.dumps(out), flush=True)

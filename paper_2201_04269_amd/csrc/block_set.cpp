@@ -244,6 +244,21 @@ void compile_block_plan(const BlockSet& s, BlockPlanHost* out) {
       out->block_g.push_back(type_index(&gt, g.family, g.proj, g.mom, g.src));
     }
   }
+  // G types whose two S1 factors share a source point first (the kernel's
+  // common case), then the mixed ones
+  std::vector<int32_t> order, where(gt.size());
+  for (int mixed = 0; mixed < 2; ++mixed)
+    for (size_t k = 0; k < gt.size(); ++k)
+      if ((gt[k].src[0] != gt[k].src[1]) == bool(mixed)) {
+        where[k] = int32_t(order.size());
+        order.push_back(int32_t(k));
+      }
+  out->n_single = 0;
+  for (const BlockType& g : gt) out->n_single += g.src[0] == g.src[1];
+  for (int32_t& g : out->block_g) g = where[g];
+  std::vector<BlockType> sorted;
+  for (int32_t k : order) sorted.push_back(gt[k]);
+  gt.swap(sorted);
   for (const BlockType& t : gt) {
     BlockTypeDev d;
     d.family = t.family;

@@ -57,6 +57,7 @@ struct BlockGArgs {
   int64_t pstride;            // complex entries per source point's propagator set
   int T, nch;
   int L1, L2, L3;
+  int g0;                     // first G type of this launch (blockIdx.z counts from it)
 };
 
 // e^{-i p.x} at site v of a timeslice: p.x = 2 pi k / (L1 L2 L3) with k
@@ -77,10 +78,12 @@ __device__ __forceinline__ double2 site_phase(const BlockTypeDev& bt, int v, int
 // prefetched into registers meanwhile), B matrices and G updates share the
 // round's three barriers.  (Building B for the next round while the matrix
 // cores work on this one, over two LDS buffers, measured no faster.)
-template <typename SIN, int NS>
+// MIXED: the S1 of B comes from another source point than the S1 of the
+// rows (a third propagator matrix per site is staged).
+template <typename SIN, int NS, bool MIXED>
 __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
-  __shared__ double2 sS1[NS][144], sS2[NS][144], sS1b[NS][144], sB[NS][432], sPh[kBlockMaxChunk];
-  const int ch = blockIdx.x, t = blockIdx.y, ty = blockIdx.z;
+  __shared__ double2 sS1[NS][144], sS2[NS][144], sS1b[MIXED ? NS : 1][144], sB[NS][432], sPh[kBlockMaxChunk];
+  const int ch = blockIdx.x, t = blockIdx.y, ty = a.g0 + int(blockIdx.z);
   const BlockTypeDev& bt = a.types[ty];
   // S1 of the rows, S1 and S2 of B, each from its own source point's set
   const SIN* S1q = reinterpret_cast<const SIN*>(bt.family == MBC_FAMILY_P ? a.S_u : a.S_d);
@@ -88,7 +91,6 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
   const SIN* S1 = S1q + bt.pt[0] * a.pstride;
   const SIN* S1B = S1q + bt.pt[1] * a.pstride;
   const SIN* S2 = S2q + bt.pt[2] * a.pstride;
-  const bool mixed = bt.pt[1] != bt.pt[0];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int64_t v0 = int64_t(ch) * a.chunk;
@@ -107,18 +109,17 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
   // the entries of a round (S1, S2 and, for mixed source points, the S1 of
   // B, of each site), NL per thread; sites past the chunk's end read as zero
   // (their B vanishes)
-  constexpr int NE = 432 * NS;
+  constexpr int PER = MIXED ? 432 : 288;
+  constexpr int NE = PER * NS;
   constexpr int NL = (NE + kBT - 1) / kBT;
-  const int ne = (mixed ? 432 : 288) * NS;
   double2 pre[NL];
   auto fetch = [&](int64_t v) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int e = tid + k * kBT;
       pre[k] = make_double2(0.0, 0.0);
-      if (e < ne) {
-        const int per = mixed ? 432 : 288;
-        const int s = e / per, r = e % per;
+      if (e < NE) {
+        const int s = e / PER, r = e % PER;
         if (v + s < v1) {
           const int64_t base = (site0 + v + s) * 144;
           pre[k] = r < 144 ? load_c(S1, base + r) : (r < 288 ? load_c(S2, base + r - 144) : load_c(S1B, base + r - 288));
@@ -130,14 +131,13 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       const int e = tid + k * kBT;
-      if (e < ne) {
-        const int per = mixed ? 432 : 288;
-        const int s = e / per, r = e % per;
+      if (e < NE) {
+        const int s = e / PER, r = e % PER;
         if (r < 144)
           sS1[s][r] = pre[k];
         else if (r < 288)
           sS2[s][r - 144] = pre[k];
-        else
+        else if constexpr (MIXED)
           sS1b[s][r - 288] = pre[k];
       }
     }
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBT, 2) void block_g_kernel(BlockGArgs a) {
       const int c = r / 36, X = (r / 3) % 12, Y0 = 4 * (r % 3);
       // (a, b, c) cyclic (eps = +1) and anticyclic (eps = -1)
       const int a1 = c == 2 ? 0 : c + 1, b1 = c == 0 ? 2 : c - 1;
-      const double2* s1b = mixed ? sS1b[s] : sS1[s];
+      const double2* s1b = MIXED ? sS1b[s] : sS1[s];
       double2 x1[4], x2[4];
 #pragma unroll
       for (int be = 0; be < 4; ++be) {
@@ -429,13 +429,24 @@ hipError_t launch_blocks(const mbc_block_plan* p, const void* S_u, const void* S
   a.L1 = dims[0];
   a.L2 = dims[1];
   a.L3 = dims[2];
-  const dim3 grid(static_cast<unsigned>(L.nch), static_cast<unsigned>(T), static_cast<unsigned>(h.types.size()));
-  if (s_c64)
-    hipLaunchKernelGGL((block_g_kernel<float2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
-  else
-    hipLaunchKernelGGL((block_g_kernel<double2, kBlockSitesPerRound>), grid, dim3(kBT), 0, st, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // G types with one source point first (h.n_single of them), then mixed ones
+  constexpr int NS = kBlockSitesPerRound;
+  for (int mixed = 0; mixed < 2; ++mixed) {
+    a.g0 = mixed ? h.n_single : 0;
+    const int n = mixed ? int(h.types.size()) - h.n_single : h.n_single;
+    if (n == 0) continue;
+    const dim3 grid(static_cast<unsigned>(L.nch), static_cast<unsigned>(T), static_cast<unsigned>(n));
+    if (s_c64 && mixed)
+      hipLaunchKernelGGL((block_g_kernel<float2, NS, true>), grid, dim3(kBT), 0, st, a);
+    else if (s_c64)
+      hipLaunchKernelGGL((block_g_kernel<float2, NS, false>), grid, dim3(kBT), 0, st, a);
+    else if (mixed)
+      hipLaunchKernelGGL((block_g_kernel<double2, NS, true>), grid, dim3(kBT), 0, st, a);
+    else
+      hipLaunchKernelGGL((block_g_kernel<double2, NS, false>), grid, dim3(kBT), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const dim3 rgrid(static_cast<unsigned>((kBlockEntries + kBT - 1) / kBT), static_cast<unsigned>(T),
                    static_cast<unsigned>(h.n_types));
   hipLaunchKernelGGL(block_reduce_kernel, rgrid, dim3(kBT), 0, st, static_cast<const double2*>(workspace),

@@ -267,7 +267,8 @@ struct BlockPlanHost {
   int64_t n_terms = 0;
   // G types, and for each block type the two G types whose difference it is:
   // f(A, Y, C) = G_g1[(alpha, A)][(C, Y)] - G_g2[(alpha, C)][(A, Y)]
-  std::vector<BlockTypeDev> types;
+  std::vector<BlockTypeDev> types;  // the first n_single use one source point
+  int n_single = 0;
   std::vector<int32_t> block_g;  // [n_types][2]
   std::vector<int32_t> factor;   // [n_terms][n_slots]
   std::vector<double> coef;      // [n_terms][2]
