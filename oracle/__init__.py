@@ -25,6 +25,11 @@ blocks       Hadron blocks with sink momentum projection (Sec. 2), the
              and the multiplicity count of the expanded form (Sec. 3, Fig. 2).
 factor_tree  Linearised factor trees (Sec. 4): prefix-tree construction of a
              sum of products and its depth-first evaluation.
+egraph       Tensor e-graphs (Sec. 5): canonical forms of tensor products under
+             signed slot symmetries (brute force), the e-graph (union-find,
+             class map, hash-cons) with the paper's two re-write conditions,
+             extraction and plan evaluation, and block-level correlators
+             written as sums of tensor expressions.
 
 Every function documents the passage it follows.  Where the paper is silent the
 reading used is stated in the docstring.
