@@ -1,4 +1,4 @@
-"""ctypes binding of libmbc (include/mbc.h, include/mbc_blocks.h): argument marshalling only.
+"""ctypes binding of libmbc (include/mbc.h, mbc_blocks.h, mbc_egraph.h): argument marshalling only.
 
 Every step of the contraction runs in the library; this module only converts
 Python/torch arguments to pointers and sizes and raises on a non-zero status.
@@ -52,6 +52,24 @@ class BlockPlanStats(ctypes.Structure):
                 ("tree_flops_per_t", ctypes.c_double)]
 
 
+class TensorDecl(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("ext", ctypes.c_int32 * 8), ("n_sym", ctypes.c_int32),
+                ("perm", (ctypes.c_int32 * 8) * 4), ("sign", ctypes.c_int32 * 4)]
+
+
+class TensorFactor(ctypes.Structure):
+    _fields_ = [("tensor", ctypes.c_int32), ("label", ctypes.c_int32 * 8)]
+
+
+class EGraphStats(ctypes.Structure):
+    _fields_ = [("n_tensors", ctypes.c_int32), ("n_terms", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int32), ("saturated", ctypes.c_int32), ("n_roots", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_open", ctypes.c_int32), ("out_ext", ctypes.c_int32 * 64),
+                ("out_elems", ctypes.c_int64), ("ws_elems", ctypes.c_int64),
+                ("flops_direct", ctypes.c_double), ("flops_plan", ctypes.c_double)]
+
+
+EXTRACT = {"reuse": 0, "flops": 1}
 FAMILIES = {0: "p", 1: "n"}
 BLOCK_METHODS = {"terms": 0, "tree": 1}
 
@@ -90,6 +108,15 @@ SIGNATURES = [
     ("mbc_block_plan_destroy", None, [_P]),
     ("mbc_blocks_compute", _I32, [_P, _P, _P, _I32, _I32, _P, _P, _P, _SZ, _P]),
     ("mbc_block_contract", _I32, [_P, _P, _I32, _I32, _P, _P, _SZ, _P]),
+    ("mbc_egraph_build", _I32, [ctypes.POINTER(TensorDecl), _I32, ctypes.POINTER(TensorFactor), _P, _P, _I32,
+                                _I64, _I32, ctypes.POINTER(_P)]),
+    ("mbc_egraph_build_blocks", _I32, [_P, _I32, _I64, _I32, ctypes.POINTER(_P)]),
+    ("mbc_egraph_get_stats", _I32, [_P, ctypes.POINTER(EGraphStats)]),
+    ("mbc_egraph_export", _I32, [_P, _P, _I64, ctypes.POINTER(_I64)]),
+    ("mbc_egraph_term_coefs", _I32, [_P, _P]),
+    ("mbc_egraph_workspace_bytes", _I32, [_P, _I64, ctypes.POINTER(_SZ)]),
+    ("mbc_egraph_execute", _I32, [_P, _P, _P, _I64, _P, _P, _SZ, _P]),
+    ("mbc_egraph_free", None, [_P]),
 ]
 
 

@@ -357,3 +357,150 @@ def block_correlators(plan, S_u, S_d, dims, method="tree", stream=None):
     """(C [n_corr, T], blocks): the blocks of every type, then their contraction."""
     blk = blocks(plan, S_u, S_d, dims, stream=stream)
     return block_contract(plan, blk, method=method, stream=stream), blk
+
+
+# ----------------------------------------------------------------------------
+# Tensor e-graphs (mbc_egraph.h)
+# ----------------------------------------------------------------------------
+class TensorEGraph:
+    """E-graph of a sum of tensor products and its extracted plan (Sec. 5).
+
+    tensors: list of (extents, symmetries) with symmetries a list of
+    (slot permutation, sign); terms: list of (coef, [(tensor, labels)]).
+    Use ``TensorEGraph.for_blocks`` for a block-level correlator."""
+
+    def __init__(self, tensors=None, terms=None, node_limit=100000, objective="reuse", _handle=None):
+        L = B.lib()
+        if _handle is None:
+            decl = (B.TensorDecl * len(tensors))()
+            for i, (ext, syms) in enumerate(tensors):
+                decl[i].rank = len(ext)
+                for k, e in enumerate(ext):
+                    decl[i].ext[k] = int(e)
+                decl[i].n_sym = len(syms)
+                for g, (perm, sign) in enumerate(syms):
+                    for k, p in enumerate(perm):
+                        decl[i].perm[g][k] = int(p)
+                    decl[i].sign[g] = int(sign)
+            nf = sum(len(f) for _, f in terms)
+            fac = (B.TensorFactor * max(nf, 1))()
+            begin = np.zeros(len(terms) + 1, dtype=np.int32)
+            coef = np.zeros((len(terms), 2))
+            q = 0
+            for k, (c, factors) in enumerate(terms):
+                coef[k] = (complex(c).real, complex(c).imag)
+                for t, labels in factors:
+                    fac[q].tensor = int(t)
+                    for s, x in enumerate(labels):
+                        fac[q].label[s] = int(x)
+                    q += 1
+                begin[k + 1] = q
+            h = ctypes.c_void_p()
+            B.check(L.mbc_egraph_build(decl, len(tensors), fac, begin.ctypes.data_as(ctypes.c_void_p),
+                                       coef.ctypes.data_as(ctypes.c_void_p), len(terms), int(node_limit),
+                                       B.EXTRACT[objective], ctypes.byref(h)))
+            _handle = h
+        self._h = _handle
+        self._free = L.mbc_egraph_free
+        st = B.EGraphStats()
+        B.check(L.mbc_egraph_get_stats(self._h, ctypes.byref(st)))
+        self.stats = {k: getattr(st, k) for k, _ in B.EGraphStats._fields_ if k != "out_ext"}
+        self.out_shape = tuple(st.out_ext[k] for k in range(st.n_open))
+
+    @classmethod
+    def for_blocks(cls, bset, corr=0, node_limit=100000, objective="reuse"):
+        """The block-level correlator `corr` of a BlockSet (mbc_egraph_build_blocks)."""
+        h = ctypes.c_void_p()
+        B.check(B.lib().mbc_egraph_build_blocks(bset._h, int(corr), int(node_limit), B.EXTRACT[objective],
+                                                ctypes.byref(h)))
+        g = cls(_handle=h)
+        g.n_block_types = bset.n_types
+        return g
+
+    def export(self):
+        """Parsed mbc_egraph_export: classes, terms (with coefficients) and plan steps."""
+        L = B.lib()
+        n = ctypes.c_int64()
+        B.check(L.mbc_egraph_export(self._h, None, 0, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.int32)
+        B.check(L.mbc_egraph_export(self._h, buf.ctypes.data_as(ctypes.c_void_p), n.value, ctypes.byref(n)))
+        v = buf.tolist()
+        p = 0
+
+        def take(k):
+            nonlocal p
+            out = v[p:p + k]
+            p += k
+            return out
+
+        classes = []
+        for _ in range(take(1)[0]):
+            rep, nf, no, lc = take(4)
+            code = tuple(take(lc))
+            nodes = []
+            for _ in range(take(1)[0]):
+                c1, c2, sign, n1 = take(4)
+                o1 = tuple(take(n1))
+                o2 = tuple(take(take(1)[0]))
+                nodes.append((c1, c2, sign, o1, o2))
+            classes.append(dict(rep=rep, n_factors=nf, n_open=no, code=code, nodes=nodes))
+        terms = []
+        for _ in range(take(1)[0]):
+            c, no = take(2)
+            terms.append((c, tuple(take(no))))
+        steps = [tuple(take(2)) for _ in range(take(1)[0])]
+        coef = np.zeros((len(terms), 2))
+        if terms:
+            B.check(L.mbc_egraph_term_coefs(self._h, coef.ctypes.data_as(ctypes.c_void_p)))
+        return dict(classes=classes, terms=terms, coefs=coef[:, 0] + 1j * coef[:, 1], steps=steps)
+
+    def workspace_bytes(self, batch=1):
+        n = ctypes.c_size_t()
+        B.check(B.lib().mbc_egraph_workspace_bytes(self._h, int(batch), ctypes.byref(n)))
+        return n.value
+
+    def execute(self, inputs, batch=1, batch_strides=None, stream=None):
+        """[batch, *out_shape] complex128: inputs is a list (one per tensor id) of
+        CUDA complex128 tensors, or None for a library constant; batch_strides
+        in complex elements (default: 0, shared)."""
+        nt = self.stats["n_tensors"]
+        if len(inputs) != nt:
+            raise ValueError(f"{nt} inputs expected")
+        dev = next(t.device for t in inputs if t is not None)
+        for t in inputs:
+            if t is not None and not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+                raise ValueError("inputs must be contiguous CUDA complex128 tensors")
+        ptrs = (ctypes.c_void_p * nt)(*[t.data_ptr() if t is not None else 0 for t in inputs])
+        bs = np.zeros(nt, dtype=np.int64) if batch_strides is None else np.asarray(batch_strides, dtype=np.int64)
+        out = torch.empty((int(batch),) + self.out_shape, dtype=torch.complex128, device=dev)
+        ws = torch.empty(max(self.workspace_bytes(batch), 16), dtype=torch.uint8, device=dev)
+        B.check(B.lib().mbc_egraph_execute(self._h, ptrs, bs.ctypes.data_as(ctypes.c_void_p), int(batch), _ptr(out),
+                                           _ptr(ws), ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+        return out
+
+    def execute_blocks(self, blk, stream=None):
+        """C[t] (complex128 [T]) of a for_blocks graph from blocks [T, n_types, 4, 12, 12, 12]."""
+        T, nty = blk.shape[0], blk.shape[1]
+        if nty != self.n_block_types:
+            raise ValueError("blocks of another block set")
+        flat = blk.reshape(T, nty, 6912)
+        inputs = [flat[0, y] for y in range(nty)] + [None] * (self.stats["n_tensors"] - nty)
+        strides = [nty * 6912] * nty + [0] * (self.stats["n_tensors"] - nty)
+        # inputs[y] views the first timeslice of type y; entry t is t * n_types * 6912 further on
+        return self._execute_views(inputs, blk, T, strides, stream)
+
+    def _execute_views(self, inputs, base, batch, strides, stream):
+        nt = self.stats["n_tensors"]
+        ptrs = (ctypes.c_void_p * nt)(*[t.data_ptr() if t is not None else 0 for t in inputs])
+        bs = np.asarray(strides, dtype=np.int64)
+        out = torch.empty((int(batch),) + self.out_shape, dtype=torch.complex128, device=base.device)
+        ws = torch.empty(max(self.workspace_bytes(batch), 16), dtype=torch.uint8, device=base.device)
+        B.check(B.lib().mbc_egraph_execute(self._h, ptrs, bs.ctypes.data_as(ctypes.c_void_p), int(batch), _ptr(out),
+                                           _ptr(ws), ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._free(h)
+            self._h = None

@@ -11,6 +11,7 @@
 
 #include "../../include/mbc_debug.h"
 #include "kernels.hpp"
+#include "egraph.hpp"
 #include "mbc_internal.hpp"
 
 namespace mbc {
@@ -612,6 +613,204 @@ mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int
   if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
   MBC_HIP(launch_block_contract(p, blocks, T, method, C, workspace, reinterpret_cast<hipStream_t>(stream)));
   return MBC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Tensor e-graphs (mbc_egraph.h)
+// ---------------------------------------------------------------------------
+struct mbc_egraph {
+  mbc::EGraphHost g;
+  std::vector<double*> dconst;  // device copies of the library-defined constants
+  int device = -1;
+};
+
+namespace {
+
+mbc_status finish_egraph(const mbc::TensorProblem& prob, int64_t node_limit, int32_t objective, mbc_egraph** out) {
+  auto* e = new mbc_egraph();
+  try {
+    mbc::egraph_build(prob, node_limit, objective, &e->g);
+  } catch (...) {
+    delete e;
+    throw;
+  }
+  *out = e;
+  return MBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbc_status mbc_egraph_build(const mbc_tensor_decl* tensors, int32_t n_tensors, const mbc_tensor_factor* factors,
+                            const int32_t* term_begin, const double* coef, int32_t n_terms, int64_t node_limit,
+                            int32_t objective, mbc_egraph** out) {
+  if (!tensors || !factors || !term_begin || !coef || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (n_tensors < 1 || n_terms < 1) return fail(MBC_ERR_INVALID, "n_tensors and n_terms must be >= 1");
+  *out = nullptr;
+  return guarded([&]() {
+    mbc::TensorProblem prob;
+    prob.decls.assign(tensors, tensors + n_tensors);
+    prob.constant.resize(n_tensors);
+    if (term_begin[0] != 0) throw std::invalid_argument("term_begin[0] must be 0");
+    for (int k = 0; k < n_terms; ++k)
+      if (term_begin[k + 1] <= term_begin[k]) throw std::invalid_argument("every term needs a factor");
+    prob.term_begin.assign(term_begin, term_begin + n_terms + 1);
+    prob.factors.assign(factors, factors + term_begin[n_terms]);
+    prob.coef.assign(coef, coef + 2 * size_t(n_terms));
+    return finish_egraph(prob, node_limit, objective, out);
+  });
+}
+
+mbc_status mbc_egraph_build_blocks(const mbc_block_set* s, int32_t corr, int64_t node_limit, int32_t objective,
+                                   mbc_egraph** out) {
+  if (!s || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  return guarded([&]() {
+    mbc::TensorProblem prob;
+    mbc::block_expressions(s->s, corr, &prob);
+    return finish_egraph(prob, node_limit, objective, out);
+  });
+}
+
+mbc_status mbc_egraph_get_stats(const mbc_egraph* e, mbc_egraph_stats* out) {
+  if (!e || !out) return fail(MBC_ERR_INVALID, "NULL argument");
+  const mbc::EGraphHost& g = e->g;
+  std::memset(out, 0, sizeof(*out));
+  out->n_tensors = int32_t(g.tensors.size());
+  out->n_terms = g.n_input_terms;
+  for (size_t c = 0; c < g.cls.size(); ++c) out->n_classes += g.parent[c] == int(c);
+  out->n_nodes = int32_t(g.n_nodes);
+  out->saturated = g.saturated ? 1 : 0;
+  out->n_roots = int32_t(g.roots.size());
+  out->n_steps = int32_t(g.steps.size());
+  out->n_open = int32_t(g.out_labels.size());
+  for (size_t j = 0; j < g.out_ext.size(); ++j) out->out_ext[j] = g.out_ext[j];
+  out->out_elems = g.out_elems;
+  out->ws_elems = g.ws_elems;
+  out->flops_direct = g.flops_direct;
+  out->flops_plan = g.flops_plan;
+  return MBC_OK;
+}
+
+mbc_status mbc_egraph_export(const mbc_egraph* e, int32_t* buf, int64_t cap, int64_t* len) {
+  if (!e || !len) return fail(MBC_ERR_INVALID, "NULL argument");
+  return guarded([&]() {
+    const mbc::EGraphHost& g = e->g;
+    std::vector<int32_t> v;
+    v.push_back(int32_t(g.cls.size()));
+    for (size_t c = 0; c < g.cls.size(); ++c) {
+      const mbc::EClass& k = g.cls[c];
+      v.push_back(g.parent[c]);
+      v.push_back(int32_t(k.factors.size()));
+      v.push_back(k.n_open);
+      v.push_back(int32_t(k.code.size()));
+      v.insert(v.end(), k.code.begin(), k.code.end());
+      v.push_back(int32_t(k.nodes.size()));
+      for (const mbc::ENode& n : k.nodes) {
+        v.push_back(n.c1);
+        v.push_back(n.c2);
+        v.push_back(n.sign);
+        v.push_back(int32_t(n.o1.size()));
+        v.insert(v.end(), n.o1.begin(), n.o1.end());
+        v.push_back(int32_t(n.o2.size()));
+        v.insert(v.end(), n.o2.begin(), n.o2.end());
+      }
+    }
+    v.push_back(int32_t(g.terms.size()));
+    for (const mbc::TermRoot& r : g.terms) {
+      v.push_back(r.cls);
+      v.push_back(int32_t(r.opens.size()));
+      v.insert(v.end(), r.opens.begin(), r.opens.end());
+    }
+    v.push_back(int32_t(g.steps.size()));
+    for (const mbc::Step& s : g.steps) {
+      v.push_back(s.cls);
+      v.push_back(s.node);
+    }
+    *len = int64_t(v.size());
+    if (buf) {
+      if (cap < *len) return fail(MBC_ERR_INVALID, "buffer too small");
+      std::copy(v.begin(), v.end(), buf);
+    }
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_egraph_term_coefs(const mbc_egraph* e, double* coef) {
+  if (!e || !coef) return fail(MBC_ERR_INVALID, "NULL argument");
+  for (size_t k = 0; k < e->g.terms.size(); ++k) {
+    coef[2 * k] = e->g.terms[k].re;
+    coef[2 * k + 1] = e->g.terms[k].im;
+  }
+  return MBC_OK;
+}
+
+mbc_status mbc_egraph_workspace_bytes(const mbc_egraph* e, int64_t batch, size_t* bytes) {
+  if (!e || !bytes) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (batch < 1) return fail(MBC_ERR_INVALID, "batch must be >= 1");
+  *bytes = size_t(e->g.ws_elems) * size_t(batch) * 16;
+  return MBC_OK;
+}
+
+mbc_status mbc_egraph_execute(mbc_egraph* e, const double* const* inputs, const int64_t* batch_stride, int64_t batch,
+                              double* out, void* workspace, size_t ws_bytes, void* stream) {
+  if (!e || !inputs || !batch_stride) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (batch < 1) return fail(MBC_ERR_INVALID, "batch must be >= 1");
+  if (!is_device_ptr(out) || !aligned16(out)) return fail(MBC_ERR_INVALID, "out must be an aligned device pointer");
+  const size_t need = size_t(e->g.ws_elems) * size_t(batch) * 16;
+  if (need > 0) {
+    if (!workspace || !is_device_ptr(workspace) || !aligned16(workspace))
+      return fail(MBC_ERR_INVALID, "workspace must be an aligned device pointer");
+    if (ws_bytes < need) return fail(MBC_ERR_INVALID, "workspace too small");
+  }
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  const int nt = int(e->g.tensors.size());
+  if (e->dconst.empty()) {
+    e->dconst.assign(nt, nullptr);
+    e->device = dev;
+    for (int t = 0; t < nt; ++t) {
+      const std::vector<double>& v = e->g.constant[t];
+      if (v.empty()) continue;
+      MBC_HIP(hipMalloc(reinterpret_cast<void**>(&e->dconst[t]), v.size() * sizeof(double)));
+      MBC_HIP(hipMemcpyAsync(e->dconst[t], v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    MBC_HIP(hipStreamSynchronize(st));
+  }
+  if (dev != e->device) return fail(MBC_ERR_INVALID, "graph's constants live on another device");
+  std::vector<const double*> in(nt);
+  std::vector<int64_t> bs(nt);
+  for (int t = 0; t < nt; ++t) {
+    in[t] = inputs[t];
+    bs[t] = batch_stride[t];
+    if (!in[t] && e->dconst[t]) {
+      in[t] = e->dconst[t];
+      bs[t] = 0;
+    }
+    if (!is_device_ptr(in[t]) || !aligned16(in[t]))
+      return fail(MBC_ERR_INVALID, "input " + std::to_string(t) + " must be an aligned device pointer");
+    if (bs[t] < 0) return fail(MBC_ERR_INVALID, "batch strides must be >= 0");
+  }
+  return guarded([&]() {
+    MBC_HIP(mbc::egraph_launch(e->g, in.data(), bs.data(), batch, out, workspace, st));
+    return MBC_OK;
+  });
+}
+
+void mbc_egraph_free(mbc_egraph* e) {
+  if (!e) return;
+  bool any = false;
+  for (double* p : e->dconst) any = any || p;
+  if (any) {
+    (void)hipDeviceSynchronize();
+    for (double* p : e->dconst)
+      if (p) (void)hipFree(p);
+  }
+  delete e;
 }
 
 }  // extern "C"

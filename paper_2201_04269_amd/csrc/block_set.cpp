@@ -24,6 +24,7 @@
 #include <stdexcept>
 #include <unordered_map>
 
+#include "egraph.hpp"
 #include "mbc_internal.hpp"
 
 namespace mbc {
@@ -129,6 +130,7 @@ struct Pending {
 void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out) {
   *out = BlockSet();
   out->n_corr = n_corr;
+  out->descs.assign(corrs, corrs + n_corr);
   out->den.assign(n_corr, 1);
   out->corr_begin.assign(n_corr + 1, 0);
   std::vector<std::vector<Pending>> per_corr(n_corr);
@@ -459,6 +461,163 @@ bool block_multiplicities(const mbc_block_corr_desc& d, int64_t max_terms, int64
   }
   *n_distinct = distinct;
   return true;
+}
+
+}  // namespace mbc
+
+namespace mbc {
+
+// The block-level correlator `corr` as a sum of tensor expressions (Sec. 5
+// applied to the partition sum of Sec. 3).  Tensors: the set's block types
+// [sigma][c_A][s_A][c_Y][s_Y][c_C][s_C] (the A <-> C antisymmetry when the two
+// like antiquarks share a source point), then eps, C gamma5, C gamma5 P+,
+// C gamma5 P- and the unit vectors e_0..e_3.  Labels: sink spin of baryon i
+// is i; source antiquark k (written order) has colour A + 2k, spin A + 2k + 1.
+void block_expressions(const BlockSet& s, int corr, TensorProblem* out) {
+  if (corr < 0 || corr >= s.n_corr) throw std::invalid_argument("correlator index out of range");
+  const mbc_block_corr_desc& d = s.descs[corr];
+  *out = TensorProblem();
+  const int nty = int(s.types.size());
+  for (const BlockType& t : s.types) {
+    mbc_tensor_decl dc{};
+    dc.rank = 7;
+    const int ext[7] = {4, 3, 4, 3, 4, 3, 4};
+    for (int k = 0; k < 7; ++k) dc.ext[k] = ext[k];
+    if (t.src[0] == t.src[2]) {
+      const int sw[7] = {0, 5, 6, 3, 4, 1, 2};
+      dc.n_sym = 1;
+      for (int k = 0; k < 7; ++k) dc.perm[0][k] = sw[k];
+      dc.sign[0] = -1;
+    }
+    out->decls.push_back(dc);
+    out->constant.emplace_back();
+  }
+  const int t_eps = nty, t_gam = nty + 1, t_unit = nty + 4;
+  {
+    mbc_tensor_decl dc{};
+    dc.rank = 3;
+    dc.ext[0] = dc.ext[1] = dc.ext[2] = 3;
+    dc.n_sym = 2;
+    const int p0[3] = {1, 0, 2}, p1[3] = {1, 2, 0};
+    for (int k = 0; k < 3; ++k) {
+      dc.perm[0][k] = p0[k];
+      dc.perm[1][k] = p1[k];
+    }
+    dc.sign[0] = -1;
+    dc.sign[1] = 1;
+    out->decls.push_back(dc);
+    std::vector<double> v(2 * 27, 0.0);
+    const int e3[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {1, 0, 2}, {0, 2, 1}, {2, 1, 0}};
+    for (int q = 0; q < 6; ++q) v[2 * ((e3[q][0] * 3 + e3[q][1]) * 3 + e3[q][2])] = q < 3 ? 1.0 : -1.0;
+    out->constant.push_back(v);
+  }
+  for (int proj : {0, 1, -1}) {
+    int64_t re[16], im[16];
+    gamma_cg5(proj, re, im);
+    bool anti = true;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) anti = anti && re[4 * i + j] == -re[4 * j + i] && im[4 * i + j] == -im[4 * j + i];
+    mbc_tensor_decl dc{};
+    dc.rank = 2;
+    dc.ext[0] = dc.ext[1] = 4;
+    if (anti) {
+      dc.n_sym = 1;
+      dc.perm[0][0] = 1;
+      dc.perm[0][1] = 0;
+      dc.sign[0] = -1;
+    }
+    out->decls.push_back(dc);
+    std::vector<double> v(32);
+    for (int k = 0; k < 16; ++k) {
+      v[2 * k] = double(re[k]);
+      v[2 * k + 1] = double(im[k]);
+    }
+    out->constant.push_back(v);
+  }
+  for (int j = 0; j < 4; ++j) {
+    mbc_tensor_decl dc{};
+    dc.rank = 1;
+    dc.ext[0] = 4;
+    out->decls.push_back(dc);
+    std::vector<double> v(8, 0.0);
+    v[2 * j] = 1.0;
+    out->constant.push_back(v);
+  }
+  auto gam = [&](int proj) { return t_gam + (proj == 0 ? 0 : (proj > 0 ? 1 : 2)); };
+
+  int den = 1;
+  const std::vector<WrittenProduct> prods = written_baryon_products(d.op, d.sign_mode, &den);
+  const int A = prods.empty() ? 0 : prods[0].nb;
+  auto col = [&](int k) { return A + 2 * k; };
+  auto spn = [&](int k) { return A + 2 * k + 1; };
+  out->term_begin.push_back(0);
+  auto push = [&](int t, std::initializer_list<int> lab) {
+    mbc_tensor_factor f{};
+    f.tensor = t;
+    int k = 0;
+    for (int x : lab) f.label[k++] = x;
+    out->factors.push_back(f);
+  };
+  for (const WrittenProduct& snk : prods)
+    for (const WrittenProduct& src : prods) {
+      int family[3];
+      for (int i = 0; i < A; ++i) family[i] = snk.b[i].family;
+      uint8_t flav[9];
+      for (int b = 0; b < A; ++b) {
+        const bool p = src.b[b].family == MBC_FAMILY_P;
+        flav[3 * b] = flav[3 * b + 2] = p ? kFlavU : kFlavD;
+        flav[3 * b + 1] = p ? kFlavD : kFlavU;
+      }
+      for (const Partition& P : partitions(family, A, flav, 3 * A)) {
+        double coef = double(snk.sign * src.sign * P.sign) / double(den);
+        if (A == 1) {
+          push(t_unit + d.snk_spin, {0});
+        } else {
+          push(t_gam, {0, 1});
+          if (A == 3) push(t_unit + d.snk_spin, {2});
+        }
+        for (int i = 0; i < A; ++i) {
+          int a = P.grp[i][0], y = P.grp[i][1], c = P.grp[i][2];
+          int z[3] = {d.src_pt[a / 3], d.src_pt[y / 3], d.src_pt[c / 3]};
+          int ty = -1;
+          for (int k = 0; k < nty && ty < 0; ++k) {
+            const BlockType& t = s.types[k];
+            if (t.family == snk.b[i].family && t.proj == snk.b[i].proj && t.mom[0] == d.mom[i][0] &&
+                t.mom[1] == d.mom[i][1] && t.mom[2] == d.mom[i][2] && t.src[0] == z[0] && t.src[1] == z[1] &&
+                t.src[2] == z[2])
+              ty = k;
+          }
+          if (ty < 0) {
+            // the type with the like antiquarks' points exchanged: f(A,Y,C) = -f'(C,Y,A)
+            std::swap(a, c);
+            std::swap(z[0], z[2]);
+            coef = -coef;
+            for (int k = 0; k < nty && ty < 0; ++k) {
+              const BlockType& t = s.types[k];
+              if (t.family == snk.b[i].family && t.proj == snk.b[i].proj && t.mom[0] == d.mom[i][0] &&
+                  t.mom[1] == d.mom[i][1] && t.mom[2] == d.mom[i][2] && t.src[0] == z[0] && t.src[1] == z[1] &&
+                  t.src[2] == z[2])
+                ty = k;
+            }
+          }
+          if (ty < 0) throw std::logic_error("block type of a partition is not in the block set");
+          push(ty, {i, col(a), spn(a), col(y), spn(y), col(c), spn(c)});
+        }
+        for (int b = 0; b < A; ++b) {
+          push(t_eps, {col(3 * b), col(3 * b + 1), col(3 * b + 2)});
+          push(gam(src.b[b].proj), {spn(3 * b), spn(3 * b + 1)});
+        }
+        if (A == 1) {
+          push(t_unit + d.src_spin, {spn(2)});
+        } else {
+          push(t_gam, {spn(2), spn(5)});
+          if (A == 3) push(t_unit + d.src_spin, {spn(8)});
+        }
+        out->term_begin.push_back(int32_t(out->factors.size()));
+        out->coef.push_back(coef);
+        out->coef.push_back(0.0);
+      }
+    }
 }
 
 }  // namespace mbc

@@ -333,6 +333,27 @@ std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den
   return out;
 }
 
+std::vector<WrittenProduct> written_baryon_products(int op, int sign_mode, int* den) {
+  if (sign_mode != MBC_SIGNS_EXACT && sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
+  *den = 1;
+  std::vector<WrittenProduct> out;
+  if (op == MBC_OP_PROTON || op == MBC_OP_NEUTRON) {
+    WrittenProduct w;
+    w.nb = 1;
+    w.b[0] = slot_of(op == MBC_OP_PROTON ? P : N, 0);
+    out.push_back(w);
+    return out;
+  }
+  for (const Product& pr : written_products(op, den)) {
+    WrittenProduct w;
+    w.sign = (sign_mode == MBC_SIGNS_R2) ? 1 : pr.sign;
+    w.nb = pr.nb;
+    for (int i = 0; i < pr.nb; ++i) w.b[i] = slot_of(pr.b[i], 0);
+    out.push_back(w);
+  }
+  return out;
+}
+
 std::vector<FieldTerm> source_terms(int op, int spin, int sign_mode, bool canonical_form, const int32_t* pts) {
   if (sign_mode != MBC_SIGNS_EXACT && sign_mode != MBC_SIGNS_R2) throw std::invalid_argument("sign_mode");
   if (spin < 0 || spin > 3) throw std::invalid_argument("spin index out of range");

@@ -57,6 +57,15 @@ struct SinkProduct {
   BaryonSlot b[3];
 };
 std::vector<SinkProduct> sink_products(int op, int spin, int sign_mode, int* den);
+// The written products of eq. "ops" before the spin sums: relative sign (+1
+// under MBC_SIGNS_R2) and baryons (family, projector) in written order; the
+// spins are left open (X^T (C gamma5) Y [Z^j]).  A single baryon is one
+// product of one baryon.  *den: the s^2 denominator.
+struct WrittenProduct {
+  int sign = 1, nb = 0;
+  BaryonSlot b[3];
+};
+std::vector<WrittenProduct> written_baryon_products(int op, int sign_mode, int* den);
 // A source operator term: coefficient (not conjugated) and n antiquark
 // fields (flavour, index, source point).  Baryon slot i of the written
 // source sits at source point pts[i] (pts == nullptr: all at point 0).
@@ -96,8 +105,13 @@ struct BlockSet {
   // its number of children; the leaves are the correlator's terms, in order.
   std::vector<int32_t> tree_factor, tree_children;
   std::vector<int64_t> tree_vertex;    // [n_corr + 1] first vertex of each tree
+  std::vector<mbc_block_corr_desc> descs;  // the correlators the set was built from
 };
 void build_block_set(const mbc_block_corr_desc* corrs, int n_corr, BlockSet* out);
+// The block-level correlator `corr` of a set as tensor expressions over its
+// block types and the constants eps, C gamma5 (P+-) and e_j (egraph.hpp).
+struct TensorProblem;
+void block_expressions(const BlockSet& s, int corr, TensorProblem* out);
 // Sec. 3 multiplicity count of one correlator (see mbc_block_multiplicities);
 // hist[m] for every multiplicity m up to the largest.  Returns false, with
 // only *n_terms set, when the expansion has more than max_terms terms.
