@@ -29,8 +29,11 @@
  *                themselves and (2) one of them holds a factor with no open
  *                label of E (the paper's two conditions); classes are
  *                expanded first in, first out until node_limit e-nodes exist;
- *                a class left without an e-node is split into its last
- *                factor and the rest
+ *                a class left without an e-node is split at the root of a
+ *                greedy pairwise contraction order of its factors (join the
+ *                two operands that remove the most intermediate elements,
+ *                then the pair carrying the fewest label combinations, then
+ *                the first pair)
  *   extraction   MBC_EXTRACT_REUSE (the paper's objective): per class the
  *                e-node with the largest sum over its distinct children c
  *                with two or more factors of (parent classes of c - 1) x the

@@ -20,8 +20,8 @@
 // two conditions becomes an e-node sign x [E1] [E2] whose children are the
 // classes of the canonicalised parts.  An e-node already owned by another
 // class unites the two classes (union-find U).  Expansion stops adding
-// e-nodes at the node limit; a class left without an e-node is split into
-// its last factor and the rest.
+// e-nodes at the node limit; a class left without an e-node is split at the
+// root of a greedy pairwise contraction order of its factors.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -185,6 +185,53 @@ i128 prod_ext(const EClass& c, uint64_t mask) {
   for (int x = 0; x < MBC_EGRAPH_MAX_LABEL; ++x)
     if (mask >> x & 1u) p *= c.label_ext[x];
   return p;
+}
+
+// Root split (subset mask holding factor 0) of a greedy pairwise contraction
+// order: repeatedly join the two operands whose join removes the most
+// intermediate elements (size of the join - sizes of the two), then the one
+// whose two operands carry the fewest label combinations, then the first pair.
+uint32_t greedy_split(const Expr& cf, const std::vector<TensorInfo>& T) {
+  const int n = int(cf.size());
+  int ext[MBC_EGRAPH_MAX_LABEL] = {};
+  for (const Fac& f : cf)
+    for (int k = 0; k < T[f.t].rank; ++k) ext[f.lab[k]] = T[f.t].ext[k];
+  auto opens = [&](uint32_t mask) {
+    int c[MBC_EGRAPH_MAX_LABEL] = {};
+    for (int i = 0; i < n; ++i)
+      if (mask >> i & 1u)
+        for (int k = 0; k < T[cf[i].t].rank; ++k) ++c[cf[i].lab[k]];
+    uint64_t m = 0;
+    for (int x = 0; x < MBC_EGRAPH_MAX_LABEL; ++x)
+      if (c[x] == 1) m |= uint64_t(1) << x;
+    return m;
+  };
+  auto size = [&](uint64_t m) {
+    i128 p = 1;
+    for (int x = 0; x < MBC_EGRAPH_MAX_LABEL; ++x)
+      if (m >> x & 1u) p *= ext[x];
+    return p;
+  };
+  std::vector<uint32_t> ops;
+  for (int i = 0; i < n; ++i) ops.push_back(1u << i);
+  while (ops.size() > 2) {
+    int bi = -1, bj = -1;
+    i128 b0 = 0, b1 = 0;
+    for (int i = 0; i < int(ops.size()); ++i)
+      for (int j = i + 1; j < int(ops.size()); ++j) {
+        const uint64_t oi = opens(ops[i]), oj = opens(ops[j]);
+        const i128 k0 = size(opens(ops[i] | ops[j])) - size(oi) - size(oj), k1 = size(oi | oj);
+        if (bi < 0 || k0 < b0 || (k0 == b0 && k1 < b1)) {
+          bi = i;
+          bj = j;
+          b0 = k0;
+          b1 = k1;
+        }
+      }
+    ops[bi] |= ops[bj];
+    ops.erase(ops.begin() + bj);
+  }
+  return (ops[0] & 1u) ? ops[0] : ops[1];
 }
 
 struct Builder {
@@ -402,7 +449,10 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
     if (missing.empty()) break;
     for (int c : missing) {
       const Expr cf = g.cls[c].factors;
-      b.add_node(c, Expr(cf.begin(), cf.end() - 1), Expr(cf.end() - 1, cf.end()));
+      const uint32_t m = greedy_split(cf, g.tensors);
+      Expr p[2];
+      for (int i = 0; i < int(cf.size()); ++i) p[(m >> i & 1u) ? 0 : 1].push_back(cf[i]);
+      b.add_node(c, p[0], p[1]);
       if (g.cls[c].nodes.empty()) throw std::domain_error("a sub-expression vanishes identically");
     }
   }
@@ -493,6 +543,16 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
     const ENode& nd = g.cls[c].nodes[choice[c]];
     visit(nd.c1);
     visit(nd.c2);
+    // the executor addresses at most 16 open and 16 summed labels per step
+    int shared = 0, traces = 0;
+    for (uint8_t x : nd.o1) shared += std::count(nd.o2.begin(), nd.o2.end(), x) > 0;
+    for (int k : {nd.c1, nd.c2}) {
+      const EClass& ch = g.cls[g.find(k)];
+      if (ch.factors.size() == 1)
+        for (int x = 0; x < MBC_EGRAPH_MAX_LABEL; x += 2) traces += (ch.labels >> x & 1u) ? 1 : 0;
+    }
+    if (g.cls[c].n_open > 16 || shared + traces > 16)
+      throw std::domain_error("a plan step has more than 16 open or summed labels");
     Step s;
     s.cls = c;
     s.node = choice[c];
