@@ -139,6 +139,7 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
     flops_b = st["block_flops_per_site"] * T * V
     print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction by factor trees "
           f"{ms_tree:.3f} ms, by terms {ms_terms:.3f} ms", file=sys.stderr, flush=True)
+    egraph = bench_egraph(api, torch, bset, blk, steps, warmup)
     return {"correlators": len(corrs), "block_types": bset.n_types, "g_matrices": st["n_gmats"],
             "source_points": bset.n_points, "terms": bset.n_terms,
             "tree_vertices": st["tree_vertices"], "dtype": "f64",
@@ -146,7 +147,48 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
             "sites_per_s": T * V / ((ms_b + ms_tree) * 1e-3),
             "roofline": {"bound": "alu", "kernel": "block_g", "achieved": flops_b / (ms_b * 1e-3) / 1e12,
                          "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
-                         "frac": flops_b / (ms_b * 1e-3) / PEAK["f64"]}}
+                         "frac": flops_b / (ms_b * 1e-3) / PEAK["f64"]},
+            "egraph": egraph}
+
+
+def bench_egraph(api, torch, bset, blk, steps, warmup, node_limit=1000):
+    """The same correlators as tensor expressions over the blocks (Sec. 5):
+    e-graph per correlator, plan extracted with the paper's reuse objective and
+    with the smallest tree cost, evaluated on the GPU; HIP events around all
+    correlators' plans."""
+    T = blk.shape[0]
+    out = {"node_limit": node_limit}
+    for objective in ("reuse", "flops"):
+        t0 = time.perf_counter()
+        graphs = [api.TensorEGraph.for_blocks(bset, c, node_limit, objective) for c in range(bset.n_corr)]
+        t_build = time.perf_counter() - t0
+        wss = [torch.empty(max(g.workspace_bytes(T), 16), dtype=torch.uint8, device=blk.device) for g in graphs]
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            for g, ws in zip(graphs, wss):
+                g.execute_blocks(blk, workspace=ws)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            for g, ws in zip(graphs, wss):
+                g.execute_blocks(blk, workspace=ws)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / steps
+        fl = sum(g.stats["flops_plan"] for g in graphs) * T
+        out[objective] = {"ms": ms, "build_s": t_build, "steps": sum(g.stats["n_steps"] for g in graphs),
+                          "classes": sum(g.stats["n_classes"] for g in graphs),
+                          "nodes": sum(g.stats["n_nodes"] for g in graphs),
+                          "saturated": all(g.stats["saturated"] for g in graphs),
+                          "terms": sum(g.stats["n_terms"] for g in graphs),
+                          "roots": sum(g.stats["n_roots"] for g in graphs),
+                          "flops_plan": fl, "flops_direct": sum(g.stats["flops_direct"] for g in graphs) * T,
+                          "gflops": fl / (ms * 1e-3) / 1e9}
+        print(f"[bench] e-graph ({objective}): {out[objective]['steps']} steps, plan {fl:.3e} flops "
+              f"(direct {out[objective]['flops_direct']:.3e}), {ms:.3f} ms, built in {t_build:.2f} s",
+              file=sys.stderr, flush=True)
+    return out
 
 
 _W_ISET = None

@@ -146,7 +146,10 @@ mbc_status mbc_egraph_workspace_bytes(const mbc_egraph* g, int64_t batch, size_t
  * batch_stride host [n_tensors], complex elements
  * out          device [batch][out_elems] complex128
  * workspace    device, >= mbc_egraph_workspace_bytes(g, batch)
- * The sum over terms is taken in a fixed order (run-to-run reproducible). */
+ * At most 64 tensors.  The steps run level by level (one launch per
+ * dependency level, one for the sum over the terms); the device tables of a
+ * batch size are built on its first use (a synchronous upload).  Sums are
+ * taken in a fixed order (run-to-run reproducible). */
 mbc_status mbc_egraph_execute(mbc_egraph* g, const double* const* inputs, const int64_t* batch_stride, int64_t batch,
                               double* out, void* workspace, size_t ws_bytes, void* stream);
 /* Frees a graph and its device constants (NULL-safe; synchronises the device). */

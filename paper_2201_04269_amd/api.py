@@ -478,7 +478,7 @@ class TensorEGraph:
                                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
         return out
 
-    def execute_blocks(self, blk, stream=None):
+    def execute_blocks(self, blk, workspace=None, stream=None):
         """C[t] (complex128 [T]) of a for_blocks graph from blocks [T, n_types, 4, 12, 12, 12]."""
         T, nty = blk.shape[0], blk.shape[1]
         if nty != self.n_block_types:
@@ -487,14 +487,16 @@ class TensorEGraph:
         inputs = [flat[0, y] for y in range(nty)] + [None] * (self.stats["n_tensors"] - nty)
         strides = [nty * 6912] * nty + [0] * (self.stats["n_tensors"] - nty)
         # inputs[y] views the first timeslice of type y; entry t is t * n_types * 6912 further on
-        return self._execute_views(inputs, blk, T, strides, stream)
+        return self._execute_views(inputs, blk, T, strides, workspace, stream)
 
-    def _execute_views(self, inputs, base, batch, strides, stream):
+    def _execute_views(self, inputs, base, batch, strides, workspace, stream):
         nt = self.stats["n_tensors"]
         ptrs = (ctypes.c_void_p * nt)(*[t.data_ptr() if t is not None else 0 for t in inputs])
         bs = np.asarray(strides, dtype=np.int64)
         out = torch.empty((int(batch),) + self.out_shape, dtype=torch.complex128, device=base.device)
-        ws = torch.empty(max(self.workspace_bytes(batch), 16), dtype=torch.uint8, device=base.device)
+        ws = workspace
+        if ws is None:
+            ws = torch.empty(max(self.workspace_bytes(batch), 16), dtype=torch.uint8, device=base.device)
         B.check(B.lib().mbc_egraph_execute(self._h, ptrs, bs.ctypes.data_as(ctypes.c_void_p), int(batch), _ptr(out),
                                            _ptr(ws), ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
         return out

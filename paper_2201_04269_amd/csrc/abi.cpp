@@ -622,6 +622,7 @@ mbc_status mbc_block_contract(const mbc_block_plan* p, const double* blocks, int
 // ---------------------------------------------------------------------------
 struct mbc_egraph {
   mbc::EGraphHost g;
+  mbc::EGraphExec x;            // device step tables of the last batch size
   std::vector<double*> dconst;  // device copies of the library-defined constants
   int device = -1;
 };
@@ -796,13 +797,14 @@ mbc_status mbc_egraph_execute(mbc_egraph* e, const double* const* inputs, const 
     if (bs[t] < 0) return fail(MBC_ERR_INVALID, "batch strides must be >= 0");
   }
   return guarded([&]() {
-    MBC_HIP(mbc::egraph_launch(e->g, in.data(), bs.data(), batch, out, workspace, st));
+    MBC_HIP(mbc::egraph_launch(e->g, &e->x, in.data(), bs.data(), batch, out, workspace, st));
     return MBC_OK;
   });
 }
 
 void mbc_egraph_free(mbc_egraph* e) {
   if (!e) return;
+  mbc::egraph_exec_free(&e->x);
   bool any = false;
   for (double* p : e->dconst) any = any || p;
   if (any) {

@@ -98,8 +98,23 @@ struct EGraphHost {
 // std::invalid_argument for bad input, std::domain_error when unsupported).
 void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, EGraphHost* g);
 
-// Device evaluation of an extracted plan (egraph_exec.hip).
-hipError_t egraph_launch(const EGraphHost& g, const double* const* inputs, const int64_t* batch_stride,
-                         int64_t batch, double* out, void* workspace, hipStream_t st);
+// Device evaluation of an extracted plan (egraph_exec.hip).  The steps are
+// grouped by dependency level (a step's level is one more than its
+// children's); each level is one launch over a device table of its steps, and
+// the sum over the terms one more.  The tables depend on the batch size and
+// are rebuilt when it changes.
+constexpr int kEgraphMaxInputs = 64;
+struct EGraphExec {
+  int64_t batch = -1;
+  void* steps = nullptr;               // step records, sorted by level
+  void* roots = nullptr;               // root records
+  std::vector<int> level_begin;        // first step of each level, then the step count
+  std::vector<unsigned> level_blocks;  // workgroups of each level
+  int root_g = 1;
+  unsigned root_blocks = 0;
+};
+hipError_t egraph_launch(const EGraphHost& g, EGraphExec* x, const double* const* inputs,
+                         const int64_t* batch_stride, int64_t batch, double* out, void* workspace, hipStream_t st);
+void egraph_exec_free(EGraphExec* x);
 
 }  // namespace mbc

@@ -1,15 +1,20 @@
 // Device evaluation of an extracted tensor e-graph plan (Sec. 5).
 //
 // Every step is a batched pairwise contraction
-//   out[b][o] = coef x sum_s A[b][a(o, s)] B[b][b(o, s)]
+//   out[b][o] = sign x sum_s A[b][a(o, s)] B[b][b(o, s)]
 // over the step's summed labels s, with operands addressed through one
 // stride per label (a label may address several slots of an operand: a
-// trace).  Steps run in plan order on one stream; each output element is
-// written by one thread (or one workgroup), and the sum over the terms is
-// added root by root, so results do not depend on scheduling.
+// trace).  Steps are grouped by dependency level: one launch per level runs
+// all of its steps, each workgroup locating its step in a device table by
+// its block index.  G lanes share an output element (G = 1, 4, 16, 64 or 256,
+// chosen per step so that small steps still fill the chip) and add their
+// partial sums in a fixed tree order; the sum over the terms is one more
+// launch, again a fixed-order reduction.  Results do not depend on
+// scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <new>
 #include <stdexcept>
 
 #include "egraph.hpp"
@@ -18,111 +23,170 @@ namespace mbc {
 
 namespace {
 
-constexpr int kMaxL = 16;   // labels per side (open, summed) of one step
-constexpr int kCT = 256;    // threads per workgroup
+constexpr int kMaxL = 16;  // labels per side (open, summed) of one step
+constexpr int kCT = 256;   // threads per workgroup
 
-struct ContractArgs {
-  const double2* A;
-  const double2* B;  // nullptr: a single operand
-  double2* C;
-  int64_t a_bs, b_bs, c_bs;  // batch strides (complex elements)
+// One contraction step.  src >= 0: input tensor id; -1: a workspace buffer
+// (ws + batch * off, batch stride bs).
+struct DevStep {
+  int32_t a_src, b_src, n_o, n_s, G, pad;
+  int64_t a_off, a_bs, b_off, b_bs, c_off, c_bs;
   int64_t n_out, n_sum, total;
-  int n_o, n_s;
-  int ext_o[kMaxL], ext_s[kMaxL];
-  int64_t sa_o[kMaxL], sb_o[kMaxL], sa_s[kMaxL], sb_s[kMaxL];
-  double cre, cim;
-  int accumulate;
+  int64_t blk0;  // first workgroup of the step within its level
+  int32_t ext_o[kMaxL], ext_s[kMaxL];
+  int32_t sa_o[kMaxL], sb_o[kMaxL], sa_s[kMaxL], sb_s[kMaxL];
+  double sign;
 };
 
-__device__ __forceinline__ void operand_base(const ContractArgs& a, int64_t b, int64_t o, int64_t* ia, int64_t* ib) {
-  *ia = b * a.a_bs;
-  *ib = b * a.b_bs;
-  for (int k = a.n_o - 1; k >= 0; --k) {
-    const int64_t v = o % a.ext_o[k];
-    o /= a.ext_o[k];
-    *ia += v * a.sa_o[k];
-    *ib += v * a.sb_o[k];
-  }
+// One term of the final sum: coef x value of its class, open slots mapped to
+// the result's labels (so), traces summed (ext_s, sa_s).
+struct DevRoot {
+  int32_t src, n_s;
+  int64_t off, bs;
+  int32_t so[kMaxL], ext_s[kMaxL], sa_s[kMaxL];
+  double re, im;
+};
+
+struct Inputs {
+  const double2* p[kEgraphMaxInputs];
+  int64_t bs[kEgraphMaxInputs];
+};
+
+struct LevelArgs {
+  const DevStep* steps;
+  int n_steps;
+  Inputs in;
+  double2* ws;
+  int64_t batch;
+};
+
+struct RootArgs {
+  const DevRoot* roots;
+  int n_roots, G, n_o;
+  int ext_o[kMaxL];
+  Inputs in;
+  const double2* ws;
+  double2* out;
+  int64_t batch, out_elems, total;
+};
+
+__device__ __forceinline__ double2 cmad(double2 x, double2 y, double2 acc) {
+  acc.x = fma(x.x, y.x, fma(-x.y, y.y, acc.x));
+  acc.y = fma(x.x, y.y, fma(x.y, y.x, acc.y));
+  return acc;
 }
 
-__device__ __forceinline__ void mac(const ContractArgs& a, int64_t ia, int64_t ib, double2* acc) {
-  const double2 x = a.A[ia];
-  if (a.B) {
-    const double2 y = a.B[ib];
-    acc->x = fma(x.x, y.x, fma(-x.y, y.y, acc->x));
-    acc->y = fma(x.x, y.y, fma(x.y, y.x, acc->y));
-  } else {
-    acc->x += x.x;
-    acc->y += x.y;
-  }
-}
-
-__device__ __forceinline__ void store(const ContractArgs& a, int64_t b, int64_t o, double2 acc) {
-  const double vr = a.cre * acc.x - a.cim * acc.y, vi = a.cre * acc.y + a.cim * acc.x;
-  double2* c = a.C + b * a.c_bs + o;
-  if (a.accumulate) {
-    const double2 old = *c;
-    *c = make_double2(old.x + vr, old.y + vi);
-  } else {
-    *c = make_double2(vr, vi);
-  }
-}
-
-// one thread per output element; the summed labels walked as an odometer
-__global__ __launch_bounds__(kCT) void egraph_contract_kernel(ContractArgs a) {
-  const int64_t idx = int64_t(blockIdx.x) * kCT + threadIdx.x;
-  if (idx >= a.total) return;
-  const int64_t b = idx / a.n_out, o = idx - b * a.n_out;
-  double2 acc = make_double2(0, 0);
-  if (a.A) {
-    int64_t ia, ib;
-    operand_base(a, b, o, &ia, &ib);
-    int cnt[kMaxL];
-    for (int k = 0; k < a.n_s; ++k) cnt[k] = 0;
-    for (int64_t s = 0; s < a.n_sum; ++s) {
-      mac(a, ia, ib, &acc);
-      for (int k = a.n_s - 1; k >= 0; --k) {
-        ia += a.sa_s[k];
-        ib += a.sb_s[k];
-        if (++cnt[k] < a.ext_s[k]) break;
-        cnt[k] = 0;
-        ia -= a.sa_s[k] * a.ext_s[k];
-        ib -= a.sb_s[k] * a.ext_s[k];
-      }
-    }
-  }
-  store(a, b, o, acc);
-}
-
-// one workgroup per output element (few outputs, long sums): strided partial
-// sums, then a fixed-order tree in LDS
-__global__ __launch_bounds__(kCT) void egraph_contract_reduce_kernel(ContractArgs a) {
-  __shared__ double2 part[kCT];
-  const int64_t idx = blockIdx.x;
-  const int64_t b = idx / a.n_out, o = idx - b * a.n_out;
-  int64_t ia0, ib0;
-  operand_base(a, b, o, &ia0, &ib0);
-  double2 acc = make_double2(0, 0);
-  for (int64_t s = threadIdx.x; s < a.n_sum; s += kCT) {
-    int64_t ia = ia0, ib = ib0, r = s;
-    for (int k = a.n_s - 1; k >= 0; --k) {
-      const int64_t v = r % a.ext_s[k];
-      r /= a.ext_s[k];
-      ia += v * a.sa_s[k];
-      ib += v * a.sb_s[k];
-    }
-    mac(a, ia, ib, &acc);
-  }
+// fixed-order tree over the G lanes of each group (every thread takes part)
+__device__ __forceinline__ double2 group_sum(double2 acc, int G, int lane, double2* part) {
   part[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = kCT / 2; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) {
+  for (int w = G / 2; w > 0; w >>= 1) {
+    if (lane < w) {
       part[threadIdx.x].x += part[threadIdx.x + w].x;
       part[threadIdx.x].y += part[threadIdx.x + w].y;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) store(a, b, o, part[0]);
+  return part[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kCT) void egraph_level_kernel(LevelArgs a) {
+  __shared__ double2 part[kCT];
+  // the step owning this workgroup: the last with blk0 <= blockIdx.x
+  int lo = 0, hi = a.n_steps - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.steps[mid].blk0 <= int64_t(blockIdx.x))
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const DevStep& s = a.steps[lo];
+  const int G = s.G;
+  const int64_t gid = ((int64_t(blockIdx.x) - s.blk0) * kCT + threadIdx.x) / G;
+  const int lane = int(threadIdx.x) % G;
+  const bool live = gid < s.total;
+  int64_t b = 0, o = 0;
+  double2 acc = make_double2(0, 0);
+  if (live) {
+    b = gid / s.n_out;
+    o = gid - b * s.n_out;
+    const double2* A = s.a_src >= 0 ? a.in.p[s.a_src] : a.ws + a.batch * s.a_off;
+    const double2* B = s.b_src >= 0 ? a.in.p[s.b_src] : a.ws + a.batch * s.b_off;
+    int64_t ia = b * (s.a_src >= 0 ? a.in.bs[s.a_src] : s.a_bs);
+    int64_t ib = b * (s.b_src >= 0 ? a.in.bs[s.b_src] : s.b_bs);
+    int64_t r = o;
+    for (int k = s.n_o - 1; k >= 0; --k) {
+      const int64_t v = r % s.ext_o[k];
+      r /= s.ext_o[k];
+      ia += v * s.sa_o[k];
+      ib += v * s.sb_o[k];
+    }
+    const int last = s.n_s - 1;
+    const int E = last >= 0 ? s.ext_s[last] : 1;
+    const int64_t sa = last >= 0 ? s.sa_s[last] : 0, sb = last >= 0 ? s.sb_s[last] : 0;
+    const int64_t runs = s.n_sum / E;
+    for (int64_t q = lane; q < runs; q += G) {
+      int64_t ja = ia, jb = ib, rq = q;
+      for (int k = last - 1; k >= 0; --k) {
+        const int64_t v = rq % s.ext_s[k];
+        rq /= s.ext_s[k];
+        ja += v * s.sa_s[k];
+        jb += v * s.sb_s[k];
+      }
+      for (int e = 0; e < E; ++e) {
+        acc = cmad(A[ja], B[jb], acc);
+        ja += sa;
+        jb += sb;
+      }
+    }
+  }
+  if (G > 1) acc = group_sum(acc, G, lane, part);
+  if (live && lane == 0) {
+    double2* C = a.ws + a.batch * s.c_off + b * s.c_bs + o;
+    *C = make_double2(s.sign * acc.x, s.sign * acc.y);
+  }
+}
+
+__global__ __launch_bounds__(kCT) void egraph_root_kernel(RootArgs a) {
+  __shared__ double2 part[kCT];
+  const int G = a.G;
+  const int64_t gid = (int64_t(blockIdx.x) * kCT + threadIdx.x) / G;
+  const int lane = int(threadIdx.x) % G;
+  const bool live = gid < a.total;
+  int64_t b = 0, o = 0;
+  double2 acc = make_double2(0, 0);
+  if (live) {
+    b = gid / a.out_elems;
+    o = gid - b * a.out_elems;
+    for (int r = lane; r < a.n_roots; r += G) {
+      const DevRoot& q = a.roots[r];
+      const double2* A = q.src >= 0 ? a.in.p[q.src] : a.ws + a.batch * q.off;
+      int64_t ia = b * (q.src >= 0 ? a.in.bs[q.src] : q.bs);
+      int64_t rr = o;
+      for (int k = a.n_o - 1; k >= 0; --k) {
+        const int64_t v = rr % a.ext_o[k];
+        rr /= a.ext_o[k];
+        ia += v * q.so[k];
+      }
+      int64_t n_tr = 1;
+      for (int k = 0; k < q.n_s; ++k) n_tr *= q.ext_s[k];
+      double2 v = make_double2(0, 0);
+      for (int64_t t = 0; t < n_tr; ++t) {
+        int64_t ja = ia, rt = t;
+        for (int k = q.n_s - 1; k >= 0; --k) {
+          const int64_t d = rt % q.ext_s[k];
+          rt /= q.ext_s[k];
+          ja += d * q.sa_s[k];
+        }
+        v.x += A[ja].x;
+        v.y += A[ja].y;
+      }
+      acc = cmad(make_double2(q.re, q.im), v, acc);
+    }
+  }
+  if (G > 1) acc = group_sum(acc, G, lane, part);
+  if (live && lane == 0) a.out[b * a.out_elems + o] = acc;
 }
 
 // Labels of one step: the out labels (in output slot order), then the summed ones.
@@ -138,23 +202,23 @@ struct StepLabels {
 };
 
 struct Operand {
-  const double2* base = nullptr;
-  int64_t bs = 0;       // batch stride
-  int64_t elems = 0;    // elements of one batch entry
+  int src = -1;  // input tensor id, or -1: a workspace buffer
+  int64_t off = 0, bs = 0, elems = 0;
   std::vector<std::pair<int, int64_t>> slots;  // (step label, stride)
+  std::vector<int> trace_ext;                  // extents of the trace labels it introduced
 };
 
-// Operand for child class c whose open slot j carries the label map[j]
-// (labels of the consuming step); trace labels of a leaf get fresh ids from
-// *next_label and are summed.
-Operand child_operand(const EGraphHost& g, int c, const std::vector<int>& map, const double* const* inputs,
-                      const int64_t* batch_stride, int64_t batch, const double2* ws, std::vector<int>* traces,
+// Operand for child class c whose open slot j carries the label map[j] (labels
+// of the consuming step); the trace labels of a leaf get fresh ids from
+// *next_label.
+Operand child_operand(const EGraphHost& g, int c, const std::vector<int>& map, std::vector<int>* traces,
                       int* next_label) {
   Operand op;
   const EClass& k = g.cls[c];
   if (k.factors.size() >= 2) {
     const Step& s = g.steps[g.step_of[c]];
-    op.base = ws + batch * s.ws_off;
+    op.src = -1;
+    op.off = s.ws_off;
     op.bs = s.elems;
     op.elems = s.elems;
     int64_t st = 1;
@@ -166,8 +230,7 @@ Operand child_operand(const EGraphHost& g, int c, const std::vector<int>& map, c
   }
   const Fac& f = k.factors[0];
   const TensorInfo& ti = g.tensors[f.t];
-  op.base = reinterpret_cast<const double2*>(inputs[f.t]);
-  op.bs = batch_stride[f.t];
+  op.src = f.t;
   int tr[MBC_EGRAPH_MAX_LABEL];
   std::fill(tr, tr + MBC_EGRAPH_MAX_LABEL, -1);
   int64_t st = 1;
@@ -181,6 +244,7 @@ Operand child_operand(const EGraphHost& g, int c, const std::vector<int>& map, c
       if (tr[code] < 0) {
         tr[code] = (*next_label)++;
         traces->push_back(tr[code]);
+        op.trace_ext.push_back(ti.ext[s]);
       }
       lab = tr[code];
     }
@@ -191,131 +255,218 @@ Operand child_operand(const EGraphHost& g, int c, const std::vector<int>& map, c
   return op;
 }
 
-hipError_t launch_contract(const StepLabels& L, const Operand& A, const Operand* B, double2* C, int64_t c_bs,
-                           int64_t batch, double cre, double cim, bool accumulate, hipStream_t st) {
-  ContractArgs a{};
-  if (L.out_lab.size() > size_t(kMaxL) || L.sum_lab.size() > size_t(kMaxL))
-    throw std::domain_error("an e-graph step has more than 16 open or summed labels");
-  a.A = A.base;
-  a.B = B ? B->base : nullptr;
-  a.C = C;
-  a.a_bs = A.bs;
-  a.b_bs = B ? B->bs : 0;
-  a.c_bs = c_bs;
-  a.n_o = int(L.out_lab.size());
-  a.n_s = int(L.sum_lab.size());
-  a.n_out = 1;
-  a.n_sum = 1;
-  for (int k = 0; k < a.n_o; ++k) {
-    a.ext_o[k] = L.out_ext[k];
-    a.n_out *= L.out_ext[k];
+// per-label strides of an operand over the step's labels; checks that every
+// address stays inside one batch entry of the operand
+void strides_of(const StepLabels& L, const Operand& op, int32_t* so, int32_t* ss) {
+  const int n_o = int(L.out_lab.size()), n_s = int(L.sum_lab.size());
+  int64_t o64[kMaxL] = {}, s64[kMaxL] = {};
+  for (const auto& sl : op.slots) {
+    const int i = L.index(sl.first);
+    if (i < 0) throw std::logic_error("operand slot without a step label");
+    if (i < n_o)
+      o64[i] += sl.second;
+    else
+      s64[i - n_o] += sl.second;
   }
-  for (int k = 0; k < a.n_s; ++k) {
-    a.ext_s[k] = L.sum_ext[k];
-    a.n_sum *= L.sum_ext[k];
-  }
-  auto fill = [&](const Operand& op, int64_t* so, int64_t* ss) {
-    int64_t hi = 0;
-    for (const auto& sl : op.slots) {
-      const int i = L.index(sl.first);
-      if (i < 0) throw std::logic_error("operand slot without a step label");
-      if (i < a.n_o)
-        so[i] += sl.second;
-      else
-        ss[i - a.n_o] += sl.second;
-    }
-    for (int k = 0; k < a.n_o; ++k) hi += (a.ext_o[k] - 1) * so[k];
-    for (int k = 0; k < a.n_s; ++k) hi += (a.ext_s[k] - 1) * ss[k];
-    if (hi >= op.elems) throw std::logic_error("e-graph operand addressed out of bounds");
-  };
-  if (A.base) fill(A, a.sa_o, a.sa_s);
-  if (B) fill(*B, a.sb_o, a.sb_s);
-  a.cre = cre;
-  a.cim = cim;
-  a.accumulate = accumulate ? 1 : 0;
-  a.total = a.n_out * batch;
-  if (a.total == 0) return hipSuccess;
-  if (a.n_sum >= 4096 && a.total < 16384) {
-    hipLaunchKernelGGL(egraph_contract_reduce_kernel, dim3(static_cast<unsigned>(a.total)), dim3(kCT), 0, st, a);
-  } else {
-    const unsigned nb = static_cast<unsigned>((a.total + kCT - 1) / kCT);
-    hipLaunchKernelGGL(egraph_contract_kernel, dim3(nb), dim3(kCT), 0, st, a);
-  }
-  return hipGetLastError();
+  int64_t hi = 0;
+  for (int k = 0; k < n_o; ++k) hi += (L.out_ext[k] - 1) * o64[k];
+  for (int k = 0; k < n_s; ++k) hi += (L.sum_ext[k] - 1) * s64[k];
+  if (hi >= op.elems || op.elems > (int64_t(1) << 31))
+    throw std::logic_error("e-graph operand addressed out of bounds");
+  for (int k = 0; k < n_o; ++k) so[k] = int32_t(o64[k]);
+  for (int k = 0; k < n_s; ++k) ss[k] = int32_t(s64[k]);
 }
 
-}  // namespace
+// lanes per output: grow while the launch stays under 2^19 threads and every
+// lane still gets a run
+int lanes_for(int64_t total, int64_t runs) {
+  int G = 1;
+  while (G < 256 && total * G * 4 <= (int64_t(1) << 19) && int64_t(G) * 4 <= runs) G *= 4;
+  return G;
+}
 
-hipError_t egraph_launch(const EGraphHost& g, const double* const* inputs, const int64_t* batch_stride,
-                         int64_t batch, double* out, void* workspace, hipStream_t st) {
-  const double2* ws = reinterpret_cast<const double2*>(workspace);
-  for (const Step& s : g.steps) {
-    const EClass& k = g.cls[s.cls];
-    const ENode& nd = k.nodes[s.node];
-    StepLabels L;
-    for (int j = 0; j < k.n_open; ++j) {
-      L.out_lab.push_back(2 * j + 1);
-      L.out_ext.push_back(k.open_ext[j]);
+void build_tables(const EGraphHost& g, int64_t batch, EGraphExec* x) {
+  const int ns = int(g.steps.size());
+  // dependency levels (children come before parents in g.steps)
+  std::vector<int> level(ns, 0);
+  for (int i = 0; i < ns; ++i) {
+    const ENode& nd = g.cls[g.steps[i].cls].nodes[g.steps[i].node];
+    for (int c : {nd.c1, nd.c2}) {
+      const int k = g.step_of[g.rep(c)];
+      if (k >= 0) level[i] = std::max(level[i], level[k] + 1);
     }
-    for (uint8_t x : nd.o1)
-      for (uint8_t y : nd.o2)
-        if (x == y) {
-          L.sum_lab.push_back(x);
-          L.sum_ext.push_back(k.label_ext[x]);
+  }
+  std::vector<int> order(ns);
+  for (int i = 0; i < ns; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return level[p] < level[q]; });
+  std::vector<DevStep> steps(ns);
+  std::vector<int> lb(1, 0);
+  std::vector<unsigned> lblocks;
+  int64_t blocks = 0;
+  for (int j = 0; j < ns; ++j) {
+    const int i = order[j];
+    if (j > 0 && level[i] != level[order[j - 1]]) {
+      lb.push_back(j);
+      lblocks.push_back(unsigned(blocks));
+      blocks = 0;
+    }
+    const Step& st = g.steps[i];
+    const EClass& k = g.cls[st.cls];
+    const ENode& nd = k.nodes[st.node];
+    StepLabels L;
+    for (int o = 0; o < k.n_open; ++o) {
+      L.out_lab.push_back(2 * o + 1);
+      L.out_ext.push_back(k.open_ext[o]);
+    }
+    for (uint8_t p : nd.o1)
+      for (uint8_t q : nd.o2)
+        if (p == q) {
+          L.sum_lab.push_back(p);
+          L.sum_ext.push_back(k.label_ext[p]);
         }
     int next_label = MBC_EGRAPH_MAX_LABEL;
     std::vector<int> traces;
     const std::vector<int> m1(nd.o1.begin(), nd.o1.end()), m2(nd.o2.begin(), nd.o2.end());
-    Operand A = child_operand(g, g.rep(nd.c1), m1, inputs, batch_stride, batch, ws, &traces, &next_label);
-    Operand B = child_operand(g, g.rep(nd.c2), m2, inputs, batch_stride, batch, ws, &traces, &next_label);
-    for (int t : traces) {
-      L.sum_lab.push_back(t);
-      // the trace's extent: the extent of any slot it addresses
-      int e = 0;
-      for (const Operand* op : {&A, &B}) {
-        const Fac* f = nullptr;
-        const int c = g.rep(op == &A ? nd.c1 : nd.c2);
-        if (g.cls[c].factors.size() == 1) f = &g.cls[c].factors[0];
-        if (!f) continue;
-        for (size_t q = 0; q < op->slots.size(); ++q)
-          if (op->slots[q].first == t) e = g.tensors[f->t].ext[g.tensors[f->t].rank - 1 - int(q)];
-      }
-      L.sum_ext.push_back(e);
+    const Operand A = child_operand(g, g.rep(nd.c1), m1, &traces, &next_label);
+    const Operand B = child_operand(g, g.rep(nd.c2), m2, &traces, &next_label);
+    for (size_t t = 0; t < traces.size(); ++t) {
+      L.sum_lab.push_back(traces[t]);
+      L.sum_ext.push_back(t < A.trace_ext.size() ? A.trace_ext[t] : B.trace_ext[t - A.trace_ext.size()]);
     }
-    double2* C = const_cast<double2*>(ws) + batch * s.ws_off;
-    const hipError_t e = launch_contract(L, A, &B, C, s.elems, batch, double(nd.sign), 0.0, false, st);
-    if (e != hipSuccess) return e;
+    if (L.out_lab.size() > size_t(kMaxL) || L.sum_lab.size() > size_t(kMaxL))
+      throw std::domain_error("an e-graph step has more than 16 open or summed labels");
+    DevStep& d = steps[j];
+    d = DevStep{};
+    d.a_src = A.src;
+    d.b_src = B.src;
+    d.a_off = A.off;
+    d.a_bs = A.bs;
+    d.b_off = B.off;
+    d.b_bs = B.bs;
+    d.c_off = st.ws_off;
+    d.c_bs = st.elems;
+    d.n_o = int(L.out_lab.size());
+    d.n_s = int(L.sum_lab.size());
+    d.n_out = 1;
+    d.n_sum = 1;
+    for (int q = 0; q < d.n_o; ++q) {
+      d.ext_o[q] = L.out_ext[q];
+      d.n_out *= L.out_ext[q];
+    }
+    for (int q = 0; q < d.n_s; ++q) {
+      d.ext_s[q] = L.sum_ext[q];
+      d.n_sum *= L.sum_ext[q];
+    }
+    strides_of(L, A, d.sa_o, d.sa_s);
+    strides_of(L, B, d.sb_o, d.sb_s);
+    d.sign = double(nd.sign);
+    d.total = d.n_out * batch;
+    d.G = lanes_for(d.total, d.n_s > 0 ? d.n_sum / d.ext_s[d.n_s - 1] : 1);
+    d.blk0 = blocks;
+    blocks += (d.total * d.G + kCT - 1) / kCT;
+    if (blocks >= (int64_t(1) << 31)) throw std::domain_error("an e-graph level needs too many workgroups");
   }
-  // the sum over the terms, root by root
-  double2* C = reinterpret_cast<double2*>(out);
+  if (ns > 0) {
+    lb.push_back(ns);
+    lblocks.push_back(unsigned(blocks));
+  }
+  // the terms
+  std::vector<DevRoot> roots;
   StepLabels R;
   for (size_t j = 0; j < g.out_labels.size(); ++j) {
     R.out_lab.push_back(g.out_labels[j]);
     R.out_ext.push_back(g.out_ext[j]);
   }
-  if (g.roots.empty()) {
-    Operand none;
-    return launch_contract(R, none, nullptr, C, g.out_elems, batch, 0.0, 0.0, false, st);
-  }
-  for (size_t r = 0; r < g.roots.size(); ++r) {
-    const TermRoot& q = g.roots[r];
+  if (R.out_lab.size() > size_t(kMaxL)) throw std::domain_error("the result has more than 16 open labels");
+  for (const TermRoot& q : g.roots) {
     StepLabels L = R;
     int next_label = MBC_EGRAPH_MAX_LABEL;
     std::vector<int> traces;
     const std::vector<int> map(q.opens.begin(), q.opens.end());
-    Operand A = child_operand(g, q.cls, map, inputs, batch_stride, batch, ws, &traces, &next_label);
-    for (int t : traces) {
-      L.sum_lab.push_back(t);
-      const Fac& f = g.cls[q.cls].factors[0];
-      int e = 0;
-      for (size_t qq = 0; qq < A.slots.size(); ++qq)
-        if (A.slots[qq].first == t) e = g.tensors[f.t].ext[g.tensors[f.t].rank - 1 - int(qq)];
-      L.sum_ext.push_back(e);
+    const Operand A = child_operand(g, q.cls, map, &traces, &next_label);
+    for (size_t t = 0; t < traces.size(); ++t) {
+      L.sum_lab.push_back(traces[t]);
+      L.sum_ext.push_back(A.trace_ext[t]);
     }
-    const hipError_t e = launch_contract(L, A, nullptr, C, g.out_elems, batch, q.re, q.im, r > 0, st);
+    if (L.sum_lab.size() > size_t(kMaxL)) throw std::domain_error("a term has more than 16 traces");
+    DevRoot d{};
+    d.src = A.src;
+    d.off = A.off;
+    d.bs = A.bs;
+    d.n_s = int(L.sum_lab.size());
+    for (int k = 0; k < d.n_s; ++k) d.ext_s[k] = L.sum_ext[k];
+    strides_of(L, A, d.so, d.sa_s);
+    d.re = q.re;
+    d.im = q.im;
+    roots.push_back(d);
+  }
+  const int64_t total = g.out_elems * batch;
+  if (total * 256 >= (int64_t(1) << 40)) throw std::domain_error("e-graph result too large");
+  egraph_exec_free(x);
+  if (!steps.empty()) {
+    if (hipMalloc(&x->steps, steps.size() * sizeof(DevStep)) != hipSuccess) throw std::bad_alloc();
+    if (hipMemcpy(x->steps, steps.data(), steps.size() * sizeof(DevStep), hipMemcpyHostToDevice) != hipSuccess)
+      throw std::runtime_error("e-graph step table upload failed");
+  }
+  if (!roots.empty()) {
+    if (hipMalloc(&x->roots, roots.size() * sizeof(DevRoot)) != hipSuccess) throw std::bad_alloc();
+    if (hipMemcpy(x->roots, roots.data(), roots.size() * sizeof(DevRoot), hipMemcpyHostToDevice) != hipSuccess)
+      throw std::runtime_error("e-graph root table upload failed");
+  }
+  x->level_begin = lb;
+  x->level_blocks = lblocks;
+  x->root_g = lanes_for(total, int64_t(roots.size()));
+  x->root_blocks = unsigned((total * x->root_g + kCT - 1) / kCT);
+  x->batch = batch;
+}
+
+}  // namespace
+
+void egraph_exec_free(EGraphExec* x) {
+  if (x->steps || x->roots) (void)hipDeviceSynchronize();
+  if (x->steps) (void)hipFree(x->steps);
+  if (x->roots) (void)hipFree(x->roots);
+  x->steps = x->roots = nullptr;
+  x->batch = -1;
+}
+
+hipError_t egraph_launch(const EGraphHost& g, EGraphExec* x, const double* const* inputs,
+                         const int64_t* batch_stride, int64_t batch, double* out, void* workspace, hipStream_t st) {
+  const int nt = int(g.tensors.size());
+  if (nt > kEgraphMaxInputs) throw std::domain_error("the executor takes at most 64 tensors");
+  if (x->batch != batch) build_tables(g, batch, x);
+  Inputs in{};
+  for (int t = 0; t < nt; ++t) {
+    in.p[t] = reinterpret_cast<const double2*>(inputs[t]);
+    in.bs[t] = batch_stride[t];
+  }
+  double2* ws = reinterpret_cast<double2*>(workspace);
+  const DevStep* steps = reinterpret_cast<const DevStep*>(x->steps);
+  for (size_t l = 0; l + 1 < x->level_begin.size(); ++l) {
+    LevelArgs a{};
+    a.steps = steps + x->level_begin[l];
+    a.n_steps = x->level_begin[l + 1] - x->level_begin[l];
+    a.in = in;
+    a.ws = ws;
+    a.batch = batch;
+    hipLaunchKernelGGL(egraph_level_kernel, dim3(x->level_blocks[l]), dim3(kCT), 0, st, a);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  RootArgs r{};
+  r.roots = reinterpret_cast<const DevRoot*>(x->roots);
+  r.n_roots = int(g.roots.size());
+  r.G = x->root_g;
+  r.n_o = int(g.out_labels.size());
+  for (int k = 0; k < r.n_o; ++k) r.ext_o[k] = g.out_ext[k];
+  r.in = in;
+  r.ws = ws;
+  r.out = reinterpret_cast<double2*>(out);
+  r.batch = batch;
+  r.out_elems = g.out_elems;
+  r.total = g.out_elems * batch;
+  hipLaunchKernelGGL(egraph_root_kernel, dim3(x->root_blocks), dim3(kCT), 0, st, r);
+  return hipGetLastError();
 }
 
 }  // namespace mbc

@@ -279,6 +279,10 @@ def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
     C, blk = api.block_correlators(plan, su, sd, (L, L, L))
     Ct = api.block_contract(plan, blk, method="terms")
     torch.cuda.synchronize()
+    # the same correlators as tensor expressions over these blocks (Sec. 5), in
+    # the bench's launch configuration
+    Ce = [api.TensorEGraph.for_blocks(bset, c, 1000, obj).execute_blocks(blk).cpu().numpy()
+          for obj in ("reuse", "flops") for c in range(bset.n_corr)]
     C, Ct = C.cpu().numpy(), Ct.cpu().numpy()
     blk = blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
     names = {("p", 0): "p", ("n", 0): "n"}
@@ -292,7 +296,7 @@ def test_blocks_dinucleon_16x16x16x32_on_sampled_sites():
     for c, corr in enumerate(corrs):
         want = OB.block_correlator(Su, Sd, corr["op"], 0, 0, corr["sign_mode"], corr["moms"], (L, L, L),
                                    blocks=ref, compute_missing=False)
-        for got in (C[c], Ct[c]):  # factor trees, flat terms
+        for got in (C[c], Ct[c], Ce[c], Ce[bset.n_corr + c]):  # factor trees, flat terms, e-graph plans
             err = np.abs(got - want)
             assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
 
