@@ -318,6 +318,8 @@ def test_blocks_helium3_32x32x32x8_on_sampled_sites():
     su, sd = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda()
     C, blk = api.block_correlators(plan, su, sd, (L, L, L))
     Ct = api.block_contract(plan, blk, method="terms")
+    # the two checked correlators also as tensor-expression plans (Sec. 5)
+    Ce = {c: api.TensorEGraph.for_blocks(bset, c, 1000).execute_blocks(blk).cpu().numpy() for c in (0, 4)}
     torch.cuda.synchronize()
     C, Ct = C.cpu().numpy(), Ct.cpu().numpy()
     blk = blk.cpu().numpy().reshape(T, bset.n_types, 4, 1728)
@@ -332,6 +334,6 @@ def test_blocks_helium3_32x32x32x8_on_sampled_sites():
         corr = corrs[c]
         want = OB.block_correlator(Su, Sd, corr["op"], corr["snk_spin"], corr["src_spin"],
                                    corr.get("sign_mode", "exact"), corr["moms"], (L, L, L), blocks=ref, compute_missing=False)
-        for got in (C[c], Ct[c]):
+        for got in (C[c], Ct[c], Ce[c]):
             err = np.abs(got - want)
             assert np.all(err <= 1e-12 * np.abs(want).max() + 1e-300), (c, err.max(), np.abs(want).max())
