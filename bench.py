@@ -398,9 +398,16 @@ def main():
         "roofline": {"bound": "alu", "kernel": r["dominant"], "achieved": dk["alg_tflops"],
                      "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": dk["frac"],
                      "traffic": profiled_traffic(wl["name"], r["dominant"], head)},
+        "hbm": None,
         "kernels": r["kernels"],
         "fwd_only_value": r["fwd_value"],
     }
+    # HBM rate of the dominant kernel: its profiled bytes per launch over its
+    # launch time measured here (null when the profile is stale)
+    tr = out["roofline"]["traffic"]
+    if tr is not None:
+        out["hbm"] = {"kernel": r["dominant"], "bytes": tr, "GBps": tr / (dk["ms"] * 1e-3) / 1e9,
+                      "peak_GBps": 8000.0}
     for prec, rr in results.items():
         if prec != head:
             out[prec] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "fwd_only_value": rr["fwd_value"],
