@@ -25,8 +25,8 @@
  *                it with both signs vanishes identically)
  *   re-writes    E = E1 E2 over every split of a class's canonical factors
  *                (E1 holds its first factor; splits in increasing subset
- *                mask), admitted when (1) both parts contract a label inside
- *                themselves and (2) one of them holds a factor with no open
+ *                mask), admitted when (1) both parts hold a label that is
+ *                summed in E and (2) one of them holds a factor with no open
  *                label of E (the paper's two conditions); classes are
  *                expanded first in, first out until node_limit e-nodes exist;
  *                a class left without an e-node is split at the root of a
@@ -34,7 +34,11 @@
  *                two operands that remove the most intermediate elements,
  *                then the pair carrying the fewest label combinations, then
  *                the first pair)
- *   extraction   MBC_EXTRACT_REUSE (the paper's objective): per class the
+ *   roots        terms with the same class and open map are one root, their
+ *                coefficients (times the canonical signs) summed; a root
+ *                whose sum is exactly zero is dropped (those terms cancel)
+ *   extraction   from the roots, in order of first appearance.
+ *                MBC_EXTRACT_REUSE (the paper's objective): per class the
  *                e-node with the largest sum over its distinct children c
  *                with two or more factors of (parent classes of c - 1) x the
  *                direct cost of c, then the fewest flops of its own
@@ -103,7 +107,10 @@ mbc_status mbc_egraph_build(const mbc_tensor_decl* tensors, int32_t n_tensors, c
  * (the layout of mbc_blocks_compute's [4][1728] per type), with the A <-> C
  * antisymmetry when z_A = z_C; then the library-defined constants eps
  * [3][3][3], C gamma5, C gamma5 P+, C gamma5 P- [4][4] and e_0..e_3 [4].
- * The result is a scalar per timeslice. */
+ * The result is a scalar per timeslice.  MBC_ERR_INVALID if a block type
+ * the expressions need is not in the set (a correlator whose canonical
+ * expansion is empty, such as exact-sign D_II with a local source, adds no
+ * types of its own). */
 mbc_status mbc_egraph_build_blocks(const mbc_block_set* s, int32_t corr, int64_t node_limit, int32_t objective,
                                    mbc_egraph** out);
 
@@ -112,7 +119,8 @@ typedef struct {
   int32_t n_classes;     /* e-classes (union-find roots) */
   int32_t n_nodes;       /* e-nodes */
   int32_t saturated;     /* 1: no admitted re-write was cut by node_limit */
-  int32_t n_roots;       /* distinct (class, open map) pairs of the terms */
+  int32_t n_roots;       /* distinct (class, open map) pairs of the terms whose
+                            summed coefficients are not exactly zero */
   int32_t n_steps;       /* contractions of the extracted plan */
   int32_t n_open;        /* rank of the result */
   int32_t out_ext[MBC_EGRAPH_MAX_LABEL];

@@ -367,9 +367,10 @@ class TensorEGraph:
 
     tensors: list of (extents, symmetries) with symmetries a list of
     (slot permutation, sign); terms: list of (coef, [(tensor, labels)]).
-    Use ``TensorEGraph.for_blocks`` for a block-level correlator."""
+    Use ``TensorEGraph.for_blocks`` for a block-level correlator.  objective:
+    "flops" (smallest tree cost, the default) or "reuse" (the paper's)."""
 
-    def __init__(self, tensors=None, terms=None, node_limit=100000, objective="reuse", _handle=None):
+    def __init__(self, tensors=None, terms=None, node_limit=100000, objective="flops", _handle=None):
         L = B.lib()
         if _handle is None:
             decl = (B.TensorDecl * len(tensors))()
@@ -408,7 +409,7 @@ class TensorEGraph:
         self.out_shape = tuple(st.out_ext[k] for k in range(st.n_open))
 
     @classmethod
-    def for_blocks(cls, bset, corr=0, node_limit=100000, objective="reuse"):
+    def for_blocks(cls, bset, corr=0, node_limit=100000, objective="flops"):
         """The block-level correlator `corr` of a BlockSet (mbc_egraph_build_blocks)."""
         h = ctypes.c_void_p()
         B.check(B.lib().mbc_egraph_build_blocks(bset._h, int(corr), int(node_limit), B.EXTRACT[objective],

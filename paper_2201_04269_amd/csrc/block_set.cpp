@@ -600,7 +600,10 @@ void block_expressions(const BlockSet& s, int corr, TensorProblem* out) {
                 ty = k;
             }
           }
-          if (ty < 0) throw std::logic_error("block type of a partition is not in the block set");
+          if (ty < 0)
+            throw std::invalid_argument(
+                "a block type of this correlator is not in the block set (a correlator whose canonical "
+                "expansion is empty adds no types: build the set together with one that uses them)");
           push(ty, {i, col(a), spn(a), col(y), spn(y), col(c), spn(c)});
         }
         for (int b = 0; b < A; ++b) {

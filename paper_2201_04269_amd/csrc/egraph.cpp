@@ -17,7 +17,8 @@
 // hash-cons H maps codes and e-nodes to class ids) and expanded first in,
 // first out: every split E = E1 E2 of the class's canonical factors (E1
 // holds factor 0; splits by increasing subset mask) that passes the paper's
-// two conditions becomes an e-node sign x [E1] [E2] whose children are the
+// two conditions (each part holds a label summed in E; one part holds a
+// factor with no open label of E) becomes an e-node sign x [E1] [E2] whose children are the
 // classes of the canonicalised parts.  An e-node already owned by another
 // class unites the two classes (union-find U).  Expansion stops adding
 // e-nodes at the node limit; a class left without an e-node is split at the
@@ -319,15 +320,16 @@ struct Builder {
     for (uint32_t m = 1; m < all_mask; m += 2) {
       Expr p[2];
       for (int i = 0; i < n; ++i) p[(m >> i & 1u) ? 0 : 1].push_back(cf[i]);
-      bool inner = true;
-      for (int k = 0; k < 2 && inner; ++k) {
-        int c[MBC_EGRAPH_MAX_LABEL];
-        count_labels(p[k], g.tensors, c);
+      // (1) each part holds a label summed in E (condition (2) holds for
+      // every split once E has a factor with no open label)
+      bool summed = true;
+      for (int k = 0; k < 2 && summed; ++k) {
         bool any = false;
-        for (int x = 0; x < MBC_EGRAPH_MAX_LABEL; ++x) any = any || c[x] == 2;
-        inner = any;
+        for (const Fac& f : p[k])
+          for (int q = 0; q < g.tensors[f.t].rank; ++q) any = any || cnt[f.lab[q]] == 2;
+        summed = any;
       }
-      if (!inner) continue;
+      if (!summed) continue;
       if (g.n_nodes >= node_limit) {
         g.saturated = false;
         return;
@@ -533,7 +535,28 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
     pick(nodes[best].c1);
     pick(nodes[best].c2);
   };
-  for (const TermRoot& r : g.terms) pick(r.cls);
+  // roots: terms merged by (class, open map), in order of first appearance;
+  // exact zeros dropped (those terms cancel)
+  for (const TermRoot& r : g.terms) {
+    const int c = g.find(r.cls);
+    bool merged = false;
+    for (TermRoot& q : g.roots)
+      if (q.cls == c && q.opens == r.opens) {
+        q.re += r.re;
+        q.im += r.im;
+        merged = true;
+        break;
+      }
+    if (!merged) {
+      TermRoot q = r;
+      q.cls = c;
+      g.roots.push_back(q);
+    }
+  }
+  g.roots.erase(std::remove_if(g.roots.begin(), g.roots.end(),
+                               [](const TermRoot& q) { return q.re == 0.0 && q.im == 0.0; }),
+                g.roots.end());
+  for (const TermRoot& r : g.roots) pick(r.cls);
 
   // steps: post-order from the terms, each class once
   g.step_of.assign(nc, -1);
@@ -564,25 +587,7 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
     g.steps.push_back(s);
     g.flops_plan += double(node_flops(c, nd));
   };
-  for (const TermRoot& r : g.terms) visit(r.cls);
-
-  // roots: terms merged by (class, open map), in order of first appearance
-  for (const TermRoot& r : g.terms) {
-    const int c = g.find(r.cls);
-    bool merged = false;
-    for (TermRoot& q : g.roots)
-      if (q.cls == c && q.opens == r.opens) {
-        q.re += r.re;
-        q.im += r.im;
-        merged = true;
-        break;
-      }
-    if (!merged) {
-      TermRoot q = r;
-      q.cls = c;
-      g.roots.push_back(q);
-    }
-  }
+  for (const TermRoot& r : g.roots) visit(r.cls);
   g.flops_plan += 8.0 * double(g.out_elems) * double(g.roots.size());
 }
 

@@ -46,9 +46,11 @@ def test_paper_example_matches_the_oracle():
     groups = {0: E.closure(E.EPS_GENS, 3), 1: E.closure([], 3)}
     expr = [(0, (0, 1, 2)), (0, (3, 4, 5)), (1, (0, 1, 3)), (1, (5, 4, 2))]
     og = E.EGraph(groups, {0: (3, 3, 3), 1: (3, 3, 3)}).build([(1.0, expr)], 1000)
-    g = api.TensorEGraph([((3, 3, 3), E.EPS_GENS), ((3, 3, 3), [])], [(1.0, expr)], 1000)
+    g = api.TensorEGraph([((3, 3, 3), E.EPS_GENS), ((3, 3, 3), [])], [(1.0, expr)], 1000, "reuse")
     _compare(g, og, "reuse")
-    assert g.stats["n_steps"] == 2 and g.stats["flops_plan"] < g.stats["flops_direct"]
+    gf = api.TensorEGraph([((3, 3, 3), E.EPS_GENS), ((3, 3, 3), [])], [(1.0, expr)], 1000, "flops")
+    _compare(gf, og, "flops")
+    assert gf.stats["n_steps"] == 2 and gf.stats["flops_plan"] < g.stats["flops_direct"]
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -147,3 +149,64 @@ def test_block_expressions_match_the_oracle_canonically(corr):
         code, sign, _, _ = E.canonical([(ids[nm], lab) for nm, lab in factors], groups)
         assert ex["classes"][cls]["code"] == tuple(code)
         assert abs(coef - ocoef * sign) < 1e-15
+
+
+def _bset_with_types(corr):
+    # exact-sign D_II adds no block types of its own; D_I supplies them
+    return api.BlockSet([corr, dict(op="DI", moms=[(0, 0, 0)] * 2)])
+
+
+def test_exact_dii_cancels_and_r2_is_twice_di_by_canonical_forms():
+    # Appendix-C-type identities found structurally: at one source point the
+    # 36 terms of exact-sign D_II fall into 9 canonical classes whose summed
+    # coefficients are exactly zero, and under R2 every class carries exactly
+    # twice D_I's coefficient (C_DII = 2 C_DI)
+    roots = {}
+    for name, corr in (("exact", dict(op="DII", moms=[(0, 0, 0)] * 2)),
+                       ("r2", dict(op="DII", sign_mode="r2", moms=[(0, 0, 0)] * 2)),
+                       ("di", dict(op="DI", moms=[(0, 0, 0)] * 2))):
+        g = api.TensorEGraph.for_blocks(_bset_with_types(corr), 0, 100000)
+        ex = g.export()
+        acc = {}
+        for (c, o), k in zip(ex["terms"], ex["coefs"]):
+            acc[(ex["classes"][c]["code"], o)] = acc.get((ex["classes"][c]["code"], o), 0) + k
+        roots[name] = (acc, g.stats)
+    acc, st = roots["exact"]
+    assert st["n_terms"] == 36 and len(acc) == 9 and all(v == 0 for v in acc.values())
+    assert st["n_roots"] == 0 and st["n_steps"] == 0
+    r2, di = roots["r2"][0], roots["di"][0]
+    assert set(r2) == set(di) and all(r2[k] == 2 * di[k] for k in di)
+
+
+def test_the_papers_dii_subexpressions_are_shared_classes():
+    # Sec. 5 names two common sub-expressions of the D_II correlator: B1 (both
+    # blocks, two eps, two C gamma5; four open spins) and B2 (both blocks,
+    # four C gamma5; six open colours).  The saturated e-graph holds classes
+    # of both shapes, each with several parent classes.
+    bset = _bset_with_types(dict(op="DII", sign_mode="r2", moms=[(0, 0, 0)] * 2))
+    g = api.TensorEGraph.for_blocks(bset, 0, 100000)
+    assert g.stats["saturated"] == 1
+    ex = g.export()
+    n = bset.n_types
+    rank = {**{t: 7 for t in range(n)}, n: 3, n + 1: 2, n + 2: 2, n + 3: 2, **{n + 4 + j: 1 for j in range(4)}}
+    ext = lambda t, k: (4, 3, 4, 3, 4, 3, 4)[k] if t < n else (3 if t == n else 4)
+    parents = {}
+    for cid, c in enumerate(ex["classes"]):
+        for nd in c["nodes"]:
+            for k in set(nd[:2]):
+                parents.setdefault(k, set()).add(cid)
+    shapes = {"B1": [], "B2": []}
+    for cid, c in enumerate(ex["classes"]):
+        code, p, kinds, opens = c["code"], 0, [], []
+        while p < len(code):
+            t = code[p]
+            kinds.append("blk" if t < n else ("eps" if t == n else "gam" if t < n + 4 else "unit"))
+            opens += [ext(t, k) for k in range(rank[t]) if code[p + 1 + k] & 1]
+            p += 1 + rank[t]
+        kinds, opens = sorted(kinds), sorted(opens)
+        if kinds == ["blk", "blk", "eps", "eps", "gam", "gam"] and opens == [4] * 4:
+            shapes["B1"].append(len(parents.get(cid, ())))
+        if kinds == ["blk", "blk", "gam", "gam", "gam", "gam"] and opens == [3] * 6:
+            shapes["B2"].append(len(parents.get(cid, ())))
+    assert shapes["B1"] and max(shapes["B1"]) >= 2
+    assert shapes["B2"] and max(shapes["B2"]) >= 2

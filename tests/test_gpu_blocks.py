@@ -187,7 +187,7 @@ def test_block_example_from_the_readme():
     assert factors[0] == -1 and children.sum() == len(factors) - 1
     n_terms, n_distinct, hist = api.block_multiplicities(dict(op="DI", moms=[(0, 0, 0)] * 2))
     assert n_terms == 4 * 2304 * 9 and (np.arange(hist.shape[0]) * hist).sum() == n_terms
-    eg = api.TensorEGraph.for_blocks(bset, 0, node_limit=1000)
+    eg = api.TensorEGraph.for_blocks(bset, 0, node_limit=100000)
     C_eg = eg.execute_blocks(blocks)
     ref = OB.block_correlator(Su, Sd, "DI", 0, 0, "exact", [(1, 0, 0), (-1, 0, 0)], (4, 4, 4))
     assert np.abs(C.cpu().numpy()[0] - ref).max() <= 1e-12 * np.abs(ref).max()

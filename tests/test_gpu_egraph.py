@@ -90,7 +90,7 @@ def test_block_correlators_by_the_egraph_equal_the_oracle(corr, dims, P, objecti
     bset = api.BlockSet([corr])
     plan = api.BlockPlan(bset)
     blk = api.blocks(plan, torch.from_numpy(Su).to(DEV), torch.from_numpy(Sd).to(DEV), dims)
-    g = api.TensorEGraph.for_blocks(bset, 0, node_limit=1000, objective=objective)
+    g = api.TensorEGraph.for_blocks(bset, 0, node_limit=200, objective=objective)
     got = g.execute_blocks(blk).cpu().numpy()
     ref = OB.block_correlator(Su, Sd, corr["op"], corr.get("snk_spin", 0), corr.get("src_spin", 0),
                               corr.get("sign_mode", "exact"), corr["moms"], dims, src_pts=corr.get("src_pts"))

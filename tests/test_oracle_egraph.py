@@ -95,9 +95,12 @@ def test_paper_example_finds_the_common_subexpression():
     B = np.einsum("ijk,ijl->kl", _eps(), T)
     direct = E.evaluate([(1.0, expr)], {0: _eps(), 1: T}, [])
     assert abs(direct - (-np.einsum("kl,lk->", B, B))) <= 1e-13 * abs(direct)
-    assert abs(g.evaluate_plan({0: _eps(), 1: T}, []) - direct) <= 1e-13 * abs(direct)
-    steps, flops = g.plan()
-    assert len(steps) == 2 and steps[0][0] == shared[0][0]  # B once, then the root
+    for objective in ("reuse", "flops"):
+        assert abs(g.evaluate_plan({0: _eps(), 1: T}, [], objective) - direct) <= 1e-13 * abs(direct)
+    # the cheapest plan is the example's: B once, then the root from B_kl B_lk
+    steps, flops = g.plan("flops")
+    assert len(steps) == 2 and steps[0][0] == shared[0][0]
+    assert flops == 8 * 81 + 8 * 9
 
 
 @pytest.mark.parametrize("seed", range(12))
