@@ -108,6 +108,10 @@ def test_execution_is_reproducible_and_checks_its_arguments():
     g = api.TensorEGraph.for_blocks(bset, 0)
     a, b = g.execute_blocks(blk), g.execute_blocks(blk)
     assert torch.equal(a, b)
+    # another batch size rebuilds the device tables; then back again
+    c = g.execute_blocks(blk[1:].contiguous())
+    assert torch.equal(c, a[1:])
+    assert torch.equal(g.execute_blocks(blk), a)
     L = B.lib()
     import ctypes
     nt = g.stats["n_tensors"]
