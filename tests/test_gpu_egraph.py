@@ -109,8 +109,9 @@ def test_execution_is_reproducible_and_checks_its_arguments():
     a, b = g.execute_blocks(blk), g.execute_blocks(blk)
     assert torch.equal(a, b)
     # another batch size rebuilds the device tables; then back again
+    # (lanes per output depend on the batch, so the summation order may differ)
     c = g.execute_blocks(blk[1:].contiguous())
-    assert torch.equal(c, a[1:])
+    assert torch.allclose(c, a[1:], rtol=1e-13, atol=0)
     assert torch.equal(g.execute_blocks(blk), a)
     L = B.lib()
     import ctypes
