@@ -32,6 +32,9 @@
  *                 mbc_last_error() describes the last failure of the calling
  *                 thread (HIP errors carry hipGetErrorString); outputs are
  *                 unspecified after an error
+ *   logging       with the environment variable MBC_LOG set (and not "0"),
+ *                 every index set, plan, block set, block plan and e-graph
+ *                 built writes one "[mbc] ..." line with its sizes to stderr
  */
 #ifndef MBC_H
 #define MBC_H

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -29,6 +31,22 @@ mbc_status fail(mbc_status s, const std::string& m) {
   g_err = m;
   return s;
 }
+
+// MBC_LOG set (and not "0"): one stderr line per handle built, with its sizes
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("MBC_LOG");
+    return v && *v && std::string(v) != "0";
+  }();
+  return on;
+}
+#define MBC_LOGF(...)                                  \
+  do {                                                 \
+    if (log_on()) {                                    \
+      std::fprintf(stderr, "[mbc] " __VA_ARGS__);      \
+      std::fputc('\n', stderr);                       \
+    }                                                  \
+  } while (0)
 
 mbc_status hip_fail(hipError_t e, const char* where) {
   g_err = std::string(where) + ": " + hipGetErrorString(e);
@@ -159,6 +177,8 @@ mbc_status mbc_build_index_set(const mbc_op_desc* ops, int32_t n_corr, mbc_index
       delete s;
       throw;
     }
+    MBC_LOGF("index set: %d correlators, n_u %d, n_d %d, %lld entries", s->s.n_corr, s->s.n_u, s->s.n_d,
+             (long long)s->s.entries.size());
     *out = s;
     return MBC_OK;
   });
@@ -253,6 +273,10 @@ mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stre
       delete p;
       return st;
     }
+    MBC_LOGF("plan: %s, %lld entries, %d/%d/%d tiles (forward/dS/dW), %d threads, %lld LDS bytes, "
+             "%.3e algorithmic flops per site forward",
+             p->h.precision == MBC_F64 ? "f64" : "f32c", (long long)p->h.nnz, p->h.n_tiles, p->h.b_n_tiles,
+             p->h.w_n_tiles, p->h.threads, (long long)p->h.lds_bytes, p->h.alg_flops_per_site);
     *out = p;
     return MBC_OK;
   });
@@ -417,6 +441,8 @@ mbc_status mbc_block_set_build(const mbc_block_corr_desc* corrs, int32_t n_corr,
       delete s;
       throw;
     }
+    MBC_LOGF("block set: %d correlators, %d block types, %lld terms, %d source points", s->s.n_corr,
+             int(s->s.types.size()), (long long)s->s.corr.size(), s->s.n_points);
     *out = s;
     return MBC_OK;
   });
@@ -531,6 +557,8 @@ mbc_status mbc_block_plan_create(const mbc_block_set* s, void* stream, mbc_block
       release(p);
       return hip_fail(e, "hipStreamSynchronize");
     }
+    MBC_LOGF("block plan: %d types from %d G matrices, %lld terms, %.3e flops per site", p->h.n_types,
+             int(p->h.types.size()), (long long)p->h.n_terms, p->h.block_flops_per_site);
     *out = p;
     return MBC_OK;
   });
@@ -637,6 +665,11 @@ mbc_status finish_egraph(const mbc::TensorProblem& prob, int64_t node_limit, int
     delete e;
     throw;
   }
+  const mbc::EGraphHost& g = e->g;
+  MBC_LOGF("e-graph: %d terms, %d classes, %lld e-nodes (%s), %d roots, %d steps, plan %.3e flops (direct %.3e), "
+           "workspace %lld elements per batch entry",
+           g.n_input_terms, int(g.cls.size()), (long long)g.n_nodes, g.saturated ? "saturated" : "node limit reached",
+           int(g.roots.size()), int(g.steps.size()), g.flops_plan, g.flops_direct, (long long)g.ws_elems);
   *out = e;
   return MBC_OK;
 }
