@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -189,3 +190,19 @@ def test_backward_walk_matches_oracle_gradients(ods, T, V):
         r = ref[name]
         scale = np.max(np.abs(r)) + 1e-300
         assert np.max(np.abs(got - r)) <= 1e-11 * scale, name
+
+
+def test_mbc_log_writes_one_line_per_handle():
+    code = ("from paper_2201_04269_amd import api\n"
+            "api.IndexSet([dict(op='proton')])\n"
+            "b = api.BlockSet([dict(op='DI', moms=[(0, 0, 0)] * 2)])\n"
+            "api.TensorEGraph.for_blocks(b, 0, 0)\n")
+    env = dict(os.environ, MBC_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[mbc] ")]
+    assert [ln.split(":")[0] for ln in lines] == ["[mbc] index set", "[mbc] block set", "[mbc] e-graph"]
+    assert "441 entries" in lines[0]
+    env["MBC_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert "[mbc]" not in r.stderr
