@@ -108,6 +108,7 @@ struct EGraphExec {
   int64_t batch = -1;
   void* steps = nullptr;               // step records, sorted by level
   void* roots = nullptr;               // root records
+  void* blk_step = nullptr;            // per level: the step of each workgroup
   std::vector<int> level_begin;        // first step of each level, then the step count
   std::vector<unsigned> level_blocks;  // workgroups of each level
   int root_g = 1;

@@ -5,8 +5,8 @@
 // over the step's summed labels s, with operands addressed through one
 // stride per label (a label may address several slots of an operand: a
 // trace).  Steps are grouped by dependency level: one launch per level runs
-// all of its steps, each workgroup locating its step in a device table by
-// its block index.  G lanes share an output element (G = 1, 4, 16, 64 or 256,
+// all of its steps, each workgroup reading its step from a per-level map of
+// workgroups to steps.  G lanes share an output element (G = 1, 4, 16, 64 or 256,
 // chosen per step so that small steps still fill the chip) and add their
 // partial sums in a fixed tree order; the sum over the terms is one more
 // launch, again a fixed-order reduction.  Results do not depend on
@@ -54,6 +54,7 @@ struct Inputs {
 
 struct LevelArgs {
   const DevStep* steps;
+  const uint32_t* blk_step;  // step of each workgroup of the level
   int n_steps;
   Inputs in;
   double2* ws;
@@ -92,16 +93,7 @@ __device__ __forceinline__ double2 group_sum(double2 acc, int G, int lane, doubl
 
 __global__ __launch_bounds__(kCT) void egraph_level_kernel(LevelArgs a) {
   __shared__ double2 part[kCT];
-  // the step owning this workgroup: the last with blk0 <= blockIdx.x
-  int lo = 0, hi = a.n_steps - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.steps[mid].blk0 <= int64_t(blockIdx.x))
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const DevStep& s = a.steps[lo];
+  const DevStep& s = a.steps[a.blk_step[blockIdx.x]];
   const int G = s.G;
   const int64_t gid = ((int64_t(blockIdx.x) - s.blk0) * kCT + threadIdx.x) / G;
   const int lane = int(threadIdx.x) % G;
@@ -302,6 +294,7 @@ void build_tables(const EGraphHost& g, int64_t batch, EGraphExec* x) {
   std::vector<DevStep> steps(ns);
   std::vector<int> lb(1, 0);
   std::vector<unsigned> lblocks;
+  std::vector<uint32_t> blk_step;  // per level, concatenated: the step (within its level) of each workgroup
   int64_t blocks = 0;
   for (int j = 0; j < ns; ++j) {
     const int i = order[j];
@@ -363,8 +356,11 @@ void build_tables(const EGraphHost& g, int64_t batch, EGraphExec* x) {
     d.total = d.n_out * batch;
     d.G = lanes_for(d.total, d.n_s > 0 ? d.n_sum / d.ext_s[d.n_s - 1] : 1);
     d.blk0 = blocks;
-    blocks += (d.total * d.G + kCT - 1) / kCT;
+    const int64_t nb = (d.total * d.G + kCT - 1) / kCT;
+    blocks += nb;
     if (blocks >= (int64_t(1) << 31)) throw std::domain_error("an e-graph level needs too many workgroups");
+    const uint32_t local = uint32_t(j - lb.back());
+    blk_step.insert(blk_step.end(), size_t(nb), local);
   }
   if (ns > 0) {
     lb.push_back(ns);
@@ -407,6 +403,10 @@ void build_tables(const EGraphHost& g, int64_t batch, EGraphExec* x) {
     if (hipMalloc(&x->steps, steps.size() * sizeof(DevStep)) != hipSuccess) throw std::bad_alloc();
     if (hipMemcpy(x->steps, steps.data(), steps.size() * sizeof(DevStep), hipMemcpyHostToDevice) != hipSuccess)
       throw std::runtime_error("e-graph step table upload failed");
+    if (hipMalloc(&x->blk_step, blk_step.size() * sizeof(uint32_t)) != hipSuccess) throw std::bad_alloc();
+    if (hipMemcpy(x->blk_step, blk_step.data(), blk_step.size() * sizeof(uint32_t), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      throw std::runtime_error("e-graph workgroup map upload failed");
   }
   if (!roots.empty()) {
     if (hipMalloc(&x->roots, roots.size() * sizeof(DevRoot)) != hipSuccess) throw std::bad_alloc();
@@ -423,10 +423,11 @@ void build_tables(const EGraphHost& g, int64_t batch, EGraphExec* x) {
 }  // namespace
 
 void egraph_exec_free(EGraphExec* x) {
-  if (x->steps || x->roots) (void)hipDeviceSynchronize();
+  if (x->steps || x->roots || x->blk_step) (void)hipDeviceSynchronize();
   if (x->steps) (void)hipFree(x->steps);
   if (x->roots) (void)hipFree(x->roots);
-  x->steps = x->roots = nullptr;
+  if (x->blk_step) (void)hipFree(x->blk_step);
+  x->steps = x->roots = x->blk_step = nullptr;
   x->batch = -1;
 }
 
@@ -442,9 +443,12 @@ hipError_t egraph_launch(const EGraphHost& g, EGraphExec* x, const double* const
   }
   double2* ws = reinterpret_cast<double2*>(workspace);
   const DevStep* steps = reinterpret_cast<const DevStep*>(x->steps);
+  const uint32_t* blk_step = reinterpret_cast<const uint32_t*>(x->blk_step);
   for (size_t l = 0; l + 1 < x->level_begin.size(); ++l) {
     LevelArgs a{};
     a.steps = steps + x->level_begin[l];
+    a.blk_step = blk_step;
+    blk_step += x->level_blocks[l];
     a.n_steps = x->level_begin[l + 1] - x->level_begin[l];
     a.in = in;
     a.ws = ws;
