@@ -296,7 +296,7 @@ def main():
     ap.add_argument("--no-blocks", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(sites shard by timeslice; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

@@ -2,7 +2,7 @@
 multiplicities, tensor e-graphs) built with g++ under AddressSanitizer and
 UndefinedBehaviorSanitizer and run on every operator family (no GPU).
 
-Only host C++ is instrumented: the HIP kernels are not part of this build.
+Only host C++ is instrumented: the HIP kernels are not compiled here.
 """
 import os
 import shutil
