@@ -210,3 +210,44 @@ def test_the_papers_dii_subexpressions_are_shared_classes():
             shapes["B2"].append(len(parents.get(cid, ())))
     assert shapes["B1"] and max(shapes["B1"]) >= 2
     assert shapes["B2"] and max(shapes["B2"]) >= 2
+
+
+def _random_expr_with_traces(rng, n_factors, n_open):
+    """Like _random_expr, but with a factor that repeats a label (a trace)
+    whenever the shape allows one (else the last draw is returned)."""
+    for attempt in range(400):
+        fac = [int(rng.choice((0, 1, 3, 4, 5))) for _ in range(n_factors)]
+        ranks = [3 if t in (0, 3, 4) else 2 for t in fac]
+        slots = sum(ranks)
+        if (slots - n_open) % 2 or slots < n_open:
+            continue
+        labels = list(range((slots - n_open) // 2)) * 2 + list(range(40, 40 + n_open))
+        rng.shuffle(labels)
+        out, p = [], 0
+        for t, r in zip(fac, ranks):
+            out.append((t, tuple(int(x) for x in labels[p:p + r])))
+            p += r
+        if any(len(set(l)) < len(l) for _, l in out):
+            return out
+    return _random_expr(rng, max(n_factors, 2), n_open)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_sums_with_traces_match_the_oracle_exactly(seed):
+    rng = np.random.default_rng(700 + seed)
+    T = _tensors(rng)
+    groups = {t: v[1] for t, v in T.items()}
+    ext = {t: v[2] for t, v in T.items()}
+    n_open = int(rng.integers(0, 3))
+    terms = [(complex(rng.standard_normal(), rng.standard_normal()),
+              _random_expr_with_traces(rng, int(rng.integers(1, 5)), n_open)) for _ in range(2)]
+    if len({tuple(sorted(x for _, l in e for x in l if x >= 40)) for _, e in terms}) != 1:
+        pytest.skip("terms with different open labels")
+    try:
+        og = E.EGraph(groups, ext).build(terms, 500)
+    except ValueError:
+        with pytest.raises(B.MbcError):
+            api.TensorEGraph(_lib_tensors(T), terms, 500, "flops")
+        return
+    g = api.TensorEGraph(_lib_tensors(T), terms, 500, "flops")
+    _compare(g, og, "flops")

@@ -14,7 +14,7 @@ from oracle import egraph as E
 from paper_2201_04269_amd import _binding as B
 from paper_2201_04269_amd import api, synth
 
-from test_egraph_host import _lib_tensors
+from test_egraph_host import _lib_tensors, _random_expr_with_traces
 from test_oracle_egraph import _random_expr, _tensors
 
 pytestmark = pytest.mark.gpu
@@ -125,3 +125,25 @@ def test_execution_is_reproducible_and_checks_its_arguments():
                               ctypes.c_void_p(ws.data_ptr()), 16, None)
     assert st == 1
     assert b"workspace" in L.mbc_last_error() or b"input" in L.mbc_last_error()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sums_with_traces_equal_the_direct_contraction(seed):
+    # factors that repeat a label (traces), as leaves of steps and as terms
+    rng = np.random.default_rng(800 + seed)
+    T = _tensors(rng)
+    n_open = int(rng.integers(0, 3))
+    terms = [(complex(rng.standard_normal(), rng.standard_normal()),
+              _random_expr_with_traces(rng, int(rng.integers(1, 5)), n_open)) for _ in range(2)]
+    outs = {tuple(sorted(x for _, l in e for x in l if x >= 40)) for _, e in terms}
+    if len(outs) != 1:
+        pytest.skip("terms with different open labels")
+    out_labels = list(outs.pop())
+    try:
+        g = api.TensorEGraph(_lib_tensors(T), terms, 500)
+    except B.MbcError:
+        return
+    inputs = [torch.from_numpy(np.asarray(T[t][0], dtype=np.complex128)).to(DEV).contiguous() for t in sorted(T)]
+    got = g.execute(inputs)[0].cpu().numpy()
+    ref = E.evaluate(terms, {t: T[t][0] for t in T}, out_labels)
+    assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
