@@ -58,6 +58,19 @@ def test_random_sums_equal_the_direct_contraction(seed, objective):
         assert np.abs(got[b] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
 
 
+def test_generic_example_from_the_readme():
+    eps_sym = [((1, 0, 2), -1), ((1, 2, 0), 1)]
+    g = api.TensorEGraph([((3, 3, 3), eps_sym), ((3, 3, 3), [])],
+                         [(1.0, [(0, (0, 1, 2)), (0, (3, 4, 5)), (1, (0, 1, 3)), (1, (5, 4, 2))])])
+    rng = np.random.default_rng(9)
+    Tt = rng.standard_normal((3, 3, 3)) + 1j * rng.standard_normal((3, 3, 3))
+    eps_tensor = torch.from_numpy(E.constant_tensor(("eps",)).astype(np.complex128)).to(DEV)
+    E_ = g.execute([eps_tensor, torch.from_numpy(Tt).to(DEV)])
+    assert E_.shape == (1,) and len(g.export()["steps"]) == 2
+    B_ = np.einsum("ijk,ijl->kl", E.constant_tensor(("eps",)), Tt)
+    assert abs(E_[0].item() + np.einsum("kl,lk->", B_, B_)) <= 1e-13 * abs(E_[0].item())
+
+
 def test_paper_example_on_the_gpu():
     rng = np.random.default_rng(7)
     Tt = rng.standard_normal((3, 3, 3)) + 1j * rng.standard_normal((3, 3, 3))
