@@ -135,12 +135,15 @@ mbc_status mbc_egraph_get_stats(const mbc_egraph* g, mbc_egraph_stats* out);
  *   n_classes, then per class id: representative, n_factors, n_open,
  *     code length L, code[L], n_nodes, per e-node: child1, child2, sign,
  *     n1, labels of child1's open slots[n1], n2, labels[n2]
- *   n_terms, then per term: class, n_open, open labels of the class's open slots
+ *   n, then per term whose product does not vanish identically (n of them,
+ *     in input order): class, n_open, the caller's labels of the class's
+ *     open slots
  *   n_steps, then per step: class, chosen e-node index
  * Labels are the class's canonical codes.  *len receives the length; buf
  * (capacity cap) may be NULL. */
 mbc_status mbc_egraph_export(const mbc_egraph* g, int32_t* buf, int64_t cap, int64_t* len);
-/* Per term k: coef_k x the sign of its canonical form, host [n_terms][2]. */
+/* For the terms listed by mbc_egraph_export: coef_k x the sign of its
+ * canonical form, host [n][2]. */
 mbc_status mbc_egraph_term_coefs(const mbc_egraph* g, double* coef);
 
 /* Device workspace of mbc_egraph_execute for `batch` entries. */
