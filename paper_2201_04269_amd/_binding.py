@@ -1,4 +1,4 @@
-"""ctypes binding of libmbc (include/mbc.h, mbc_blocks.h, mbc_egraph.h): argument marshalling only.
+"""ctypes binding of libmbc (include/mbc.h, mbc_blocks.h, mbc_egraph.h, mbc_tree.h): argument marshalling only.
 
 Every step of the contraction runs in the library; this module only converts
 Python/torch arguments to pointers and sizes and raises on a non-zero status.
@@ -117,6 +117,11 @@ SIGNATURES = [
     ("mbc_egraph_workspace_bytes", _I32, [_P, _I64, ctypes.POINTER(_SZ)]),
     ("mbc_egraph_execute", _I32, [_P, _P, _P, _I64, _P, _P, _SZ, _P]),
     ("mbc_egraph_free", None, [_P]),
+    ("mbc_factor_tree_create", _I32, [_P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(_P)]),
+    ("mbc_factor_tree_stats", _I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double)]),
+    ("mbc_factor_tree_workspace_bytes", _I32, [_P, _I64, ctypes.POINTER(_SZ)]),
+    ("mbc_factor_tree_evaluate", _I32, [_P, _P, _I64, _P, _P, _SZ, _P]),
+    ("mbc_factor_tree_destroy", None, [_P]),
 ]
 
 

@@ -507,3 +507,52 @@ class TensorEGraph:
         if h is not None and h.value:
             self._free(h)
             self._h = None
+
+
+# ----------------------------------------------------------------------------
+# Linearised factor trees over arbitrary factor sets (mbc_tree.h)
+# ----------------------------------------------------------------------------
+class FactorTree:
+    """A linearised factor tree (Sec. 4): the paper's factors / children /
+    coefficients arrays in depth-first order (factors[0] = -1, the root),
+    factors indexing a table of n_values factor values."""
+
+    def __init__(self, factors, children, coefficients, n_values, stream=None):
+        L = B.lib()
+        f = np.ascontiguousarray(factors, dtype=np.int32)
+        ch = np.ascontiguousarray(children, dtype=np.int32)
+        c = np.asarray(coefficients, dtype=np.complex128).reshape(-1)
+        coef = np.ascontiguousarray(np.stack([c.real, c.imag], axis=-1).reshape(-1))
+        if f.shape != ch.shape:
+            raise ValueError("factors and children must have one entry per vertex")
+        h = ctypes.c_void_p()
+        B.check(L.mbc_factor_tree_create(f.ctypes.data_as(ctypes.c_void_p), ch.ctypes.data_as(ctypes.c_void_p),
+                                         f.shape[0], coef.ctypes.data_as(ctypes.c_void_p), c.shape[0],
+                                         int(n_values), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self._free = L.mbc_factor_tree_destroy
+        self.n_values = int(n_values)
+        d, fl = ctypes.c_int32(), ctypes.c_double()
+        B.check(L.mbc_factor_tree_stats(h, ctypes.byref(d), ctypes.byref(fl)))
+        self.depth, self.flops = d.value, fl.value
+
+    def evaluate(self, values, stream=None):
+        """[batch] complex128: the tree's value for each row of values
+        ([batch, n_values] CUDA complex128)."""
+        if not (values.is_cuda and values.dtype == torch.complex128 and values.is_contiguous()
+                and values.dim() == 2 and values.shape[1] == self.n_values):
+            raise ValueError(f"values must be a contiguous CUDA complex128 tensor [batch, {self.n_values}]")
+        batch = values.shape[0]
+        out = torch.empty(batch, dtype=torch.complex128, device=values.device)
+        n = ctypes.c_size_t()
+        B.check(B.lib().mbc_factor_tree_workspace_bytes(self._h, batch, ctypes.byref(n)))
+        ws = torch.empty(max(n.value, 16), dtype=torch.uint8, device=values.device)
+        B.check(B.lib().mbc_factor_tree_evaluate(self._h, _ptr(values), batch, _ptr(out), _ptr(ws),
+                                                 ctypes.c_size_t(ws.numel()), _stream_ptr(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._free(h)
+            self._h = None

@@ -12,8 +12,10 @@
 #include <string>
 
 #include "../../include/mbc_debug.h"
+#include "../../include/mbc_tree.h"
 #include "kernels.hpp"
 #include "egraph.hpp"
+#include "factor_tree.hpp"
 #include "mbc_internal.hpp"
 
 namespace mbc {
@@ -846,6 +848,108 @@ void mbc_egraph_free(mbc_egraph* e) {
       if (p) (void)hipFree(p);
   }
   delete e;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Linearised factor trees over arbitrary factor sets (mbc_tree.h)
+// ---------------------------------------------------------------------------
+struct mbc_factor_tree {
+  mbc::TreeHost h;
+  mbc::TreeDev d;
+  int device = -1;
+};
+
+namespace {
+
+void free_tree(mbc_factor_tree* t) {
+  for (void* p : {static_cast<void*>(t->d.factor), static_cast<void*>(t->d.child_begin),
+                  static_cast<void*>(t->d.child_list), static_cast<void*>(t->d.leaf),
+                  static_cast<void*>(t->d.level_vertices), static_cast<void*>(t->d.coef)})
+    if (p) (void)hipFree(p);
+  delete t;
+}
+
+}  // namespace
+
+extern "C" {
+
+mbc_status mbc_factor_tree_create(const int32_t* factors, const int32_t* children, int64_t n_vertices,
+                                  const double* coefficients, int64_t n_leaves, int32_t n_values, void* stream,
+                                  mbc_factor_tree** out) {
+  if (!factors || !children || !out || (n_leaves > 0 && !coefficients)) return fail(MBC_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  return guarded([&]() -> mbc_status {
+    auto* t = new mbc_factor_tree();
+    try {
+      mbc::build_tree_host(factors, children, n_vertices, coefficients, n_leaves, n_values, &t->h);
+    } catch (...) {
+      delete t;
+      throw;
+    }
+    if (hipGetDevice(&t->device) != hipSuccess) {
+      delete t;
+      return hip_fail(hipGetLastError(), "hipGetDevice");
+    }
+    const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    mbc_status st = MBC_OK;
+    if ((st = upload(t->h.factor, &t->d.factor, hs)) != MBC_OK ||
+        (st = upload(t->h.child_begin, &t->d.child_begin, hs)) != MBC_OK ||
+        (st = upload(t->h.child_list, &t->d.child_list, hs)) != MBC_OK ||
+        (st = upload(t->h.leaf, &t->d.leaf, hs)) != MBC_OK ||
+        (st = upload(t->h.level_vertices, &t->d.level_vertices, hs)) != MBC_OK ||
+        (st = upload(t->h.coef, &t->d.coef, hs)) != MBC_OK) {
+      free_tree(t);
+      return st;
+    }
+    const hipError_t e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) {
+      free_tree(t);
+      return hip_fail(e, "hipStreamSynchronize");
+    }
+    MBC_LOGF("factor tree: %lld vertices, depth %d, %lld leaves", (long long)t->h.n_vertices, t->h.depth,
+             (long long)(t->h.coef.size() / 2));
+    *out = t;
+    return MBC_OK;
+  });
+}
+
+mbc_status mbc_factor_tree_stats(const mbc_factor_tree* t, int32_t* depth, double* flops) {
+  if (!t) return fail(MBC_ERR_INVALID, "tree is NULL");
+  if (depth) *depth = t->h.depth;
+  if (flops) *flops = t->h.flops;
+  return MBC_OK;
+}
+
+mbc_status mbc_factor_tree_workspace_bytes(const mbc_factor_tree* t, int64_t batch, size_t* bytes) {
+  if (!t || !bytes) return fail(MBC_ERR_INVALID, "NULL argument");
+  if (batch < 1) return fail(MBC_ERR_INVALID, "batch must be >= 1");
+  *bytes = size_t(batch) * size_t(t->h.n_vertices) * 16;
+  return MBC_OK;
+}
+
+mbc_status mbc_factor_tree_evaluate(const mbc_factor_tree* t, const double* values, int64_t batch, double* out,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!t) return fail(MBC_ERR_INVALID, "tree is NULL");
+  if (batch < 1) return fail(MBC_ERR_INVALID, "batch must be >= 1");
+  if (!is_device_ptr(out) || !aligned16(out)) return fail(MBC_ERR_INVALID, "out must be an aligned device pointer");
+  if (t->h.n_values > 0 && (!is_device_ptr(values) || !aligned16(values)))
+    return fail(MBC_ERR_INVALID, "values must be an aligned device pointer");
+  if (!workspace || !is_device_ptr(workspace) || !aligned16(workspace))
+    return fail(MBC_ERR_INVALID, "workspace must be an aligned device pointer");
+  if (ws_bytes < size_t(batch) * size_t(t->h.n_vertices) * 16) return fail(MBC_ERR_INVALID, "workspace too small");
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != t->device) return fail(MBC_ERR_INVALID, "tree was created on another device");
+  MBC_HIP(mbc::launch_tree_eval(t->h, t->d, values, batch, out, workspace, reinterpret_cast<hipStream_t>(stream)));
+  return MBC_OK;
+}
+
+void mbc_factor_tree_destroy(mbc_factor_tree* t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  free_tree(t);
 }
 
 }  // extern "C"

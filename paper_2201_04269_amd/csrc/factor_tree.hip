@@ -1,0 +1,147 @@
+// Linearised factor trees over arbitrary factor sets (Sec. 4).
+//
+// Host: the factors / children / coefficients arrays are parsed in
+// depth-first order (an explicit stack of vertices with children still to
+// read), which checks that they form exactly one tree and yields each
+// vertex's children and depth.  Device: the tree is evaluated bottom up, one
+// launch per depth level from the deepest: a vertex's value is its factor's
+// value (1 for the root) times its leaf coefficient or the sum of its
+// children's values, added in depth-first order; one thread per (table,
+// vertex).  The root's value is the tree's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stdexcept>
+#include <utility>
+
+#include "factor_tree.hpp"
+
+namespace mbc {
+
+void build_tree_host(const int32_t* factors, const int32_t* children, int64_t n_vertices, const double* coef,
+                     int64_t n_leaves, int32_t n_values, TreeHost* out) {
+  if (n_vertices < 1 || n_vertices > (int64_t(1) << 30)) throw std::invalid_argument("n_vertices out of range");
+  if (n_values < 0 || n_leaves < 0) throw std::invalid_argument("n_values and n_leaves must be >= 0");
+  TreeHost& t = *out;
+  t = TreeHost();
+  t.n_vertices = n_vertices;
+  t.n_values = n_values;
+  t.factor.assign(factors, factors + n_vertices);
+  if (t.factor[0] != -1) throw std::invalid_argument("the root (vertex 0) must have factor -1");
+  for (int64_t v = 1; v < n_vertices; ++v)
+    if (t.factor[v] < 0 || t.factor[v] >= n_values) throw std::invalid_argument("factor index out of range");
+  for (int64_t v = 0; v < n_vertices; ++v)
+    if (children[v] < 0) throw std::invalid_argument("negative child count");
+  // depth-first parse
+  std::vector<int32_t> depth(n_vertices, 0);
+  std::vector<std::vector<int32_t>> kids(n_vertices);
+  std::vector<std::pair<int32_t, int32_t>> stack;  // (vertex, children still to read)
+  stack.push_back({0, children[0]});
+  int64_t pos = 1;
+  while (!stack.empty()) {
+    auto& top = stack.back();
+    if (top.second == 0) {
+      stack.pop_back();
+      continue;
+    }
+    --top.second;
+    if (pos >= n_vertices) throw std::invalid_argument("children counts need more vertices than given");
+    const int32_t c = int32_t(pos++);
+    kids[top.first].push_back(c);
+    depth[c] = depth[top.first] + 1;
+    stack.push_back({c, children[c]});
+  }
+  if (pos != n_vertices) throw std::invalid_argument("vertices left over after the root's subtree");
+  t.leaf.assign(n_vertices, -1);
+  int64_t l = 0;
+  for (int64_t v = 1; v < n_vertices; ++v)
+    if (children[v] == 0) t.leaf[v] = int32_t(l++);
+  if (l != n_leaves) throw std::invalid_argument("number of leaves differs from the number of coefficients");
+  t.coef.assign(coef, coef + 2 * n_leaves);
+  t.child_begin.assign(1, 0);
+  for (int64_t v = 0; v < n_vertices; ++v) {
+    t.child_list.insert(t.child_list.end(), kids[v].begin(), kids[v].end());
+    t.child_begin.push_back(int32_t(t.child_list.size()));
+  }
+  for (int64_t v = 0; v < n_vertices; ++v) t.depth = std::max(t.depth, depth[v]);
+  t.level_begin.assign(t.depth + 2, 0);
+  for (int64_t v = 0; v < n_vertices; ++v) ++t.level_begin[depth[v] + 1];
+  for (int d = 0; d <= t.depth; ++d) t.level_begin[d + 1] += t.level_begin[d];
+  t.level_vertices.assign(n_vertices, 0);
+  std::vector<int32_t> fill(t.level_begin.begin(), t.level_begin.end() - 1);
+  for (int64_t v = 0; v < n_vertices; ++v) t.level_vertices[fill[depth[v]]++] = int32_t(v);
+  t.flops = 8.0 * double(n_vertices - 1);
+}
+
+namespace {
+
+constexpr int kTT = 256;
+
+struct TreeArgs {
+  const int32_t* factor;
+  const int32_t* child_begin;
+  const int32_t* child_list;
+  const int32_t* leaf;
+  const double2* coef;
+  const double2* values;
+  double2* vals;  // workspace [batch][n_vertices]
+  double2* out;
+  int64_t n_vertices, batch;
+  int32_t n_values;
+};
+
+__global__ __launch_bounds__(kTT) void tree_level_kernel(TreeArgs a, const int32_t* verts, int n, int root) {
+  const int64_t idx = int64_t(blockIdx.x) * kTT + threadIdx.x;
+  if (idx >= int64_t(n) * a.batch) return;
+  const int64_t b = idx / n;
+  const int32_t v = verts[idx - b * n];
+  double2 s = make_double2(0, 0);
+  if (a.leaf[v] >= 0) {
+    s = a.coef[a.leaf[v]];
+  } else {
+    const double2* row = a.vals + b * a.n_vertices;
+    for (int32_t c = a.child_begin[v]; c < a.child_begin[v + 1]; ++c) {
+      const double2 x = row[a.child_list[c]];
+      s.x += x.x;
+      s.y += x.y;
+    }
+  }
+  double2 r = s;
+  if (a.factor[v] >= 0) {
+    const double2 f = a.values[b * a.n_values + a.factor[v]];
+    r = make_double2(f.x * s.x - f.y * s.y, f.x * s.y + f.y * s.x);
+  }
+  if (root)
+    a.out[b] = r;
+  else
+    a.vals[b * a.n_vertices + v] = r;
+}
+
+}  // namespace
+
+hipError_t launch_tree_eval(const TreeHost& h, const TreeDev& d, const double* values, int64_t batch, double* out,
+                            void* workspace, hipStream_t st) {
+  TreeArgs a{};
+  a.factor = d.factor;
+  a.child_begin = d.child_begin;
+  a.child_list = d.child_list;
+  a.leaf = d.leaf;
+  a.coef = reinterpret_cast<const double2*>(d.coef);
+  a.values = reinterpret_cast<const double2*>(values);
+  a.vals = reinterpret_cast<double2*>(workspace);
+  a.out = reinterpret_cast<double2*>(out);
+  a.n_vertices = h.n_vertices;
+  a.batch = batch;
+  a.n_values = h.n_values;
+  for (int dd = h.depth; dd >= 0; --dd) {
+    const int n = h.level_begin[dd + 1] - h.level_begin[dd];
+    const unsigned nb = unsigned((int64_t(n) * batch + kTT - 1) / kTT);
+    hipLaunchKernelGGL(tree_level_kernel, dim3(nb), dim3(kTT), 0, st, a, d.level_vertices + h.level_begin[dd], n,
+                       dd == 0 ? 1 : 0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mbc
