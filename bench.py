@@ -139,11 +139,35 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
     flops_b = st["block_flops_per_site"] * T * V
     print(f"[bench] blocks: {ms_b:.3f} ms ({flops_b / (ms_b * 1e-3) / 1e12:.2f} TF), contraction by factor trees "
           f"{ms_tree:.3f} ms, by terms {ms_terms:.3f} ms", file=sys.stderr, flush=True)
+    # the same trees through the generic evaluator (mbc_tree.h), blocks as the factor table
+    e = bset.export()
+    table = blk.reshape(T, -1)
+    trees = []
+    for c in range(bset.n_corr):
+        m = e["corr_id"] == c
+        if m.any():
+            fac, ch = bset.factor_tree(c)
+            trees.append(api.FactorTree(fac, ch, (e["num_re"][m] + 1j * e["num_im"][m]) / e["den"][c],
+                                        table.shape[1]))
+    for _ in range(warmup):
+        for tr in trees:
+            tr.evaluate(table)
+    torch.cuda.synchronize()
+    evg = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a0, a1 in evg:
+        a0.record(stream)
+        for tr in trees:
+            tr.evaluate(table)
+        a1.record(stream)
+    torch.cuda.synchronize()
+    ms_generic = sum(a0.elapsed_time(a1) for a0, a1 in evg) / steps
+    print(f"[bench] blocks: factor trees by the generic evaluator {ms_generic:.3f} ms", file=sys.stderr, flush=True)
     egraph = bench_egraph(api, torch, bset, blk, steps, warmup, node_limit=EGRAPH_NODE_LIMIT.get(name, 200))
     return {"correlators": len(corrs), "block_types": bset.n_types, "g_matrices": st["n_gmats"],
             "source_points": bset.n_points, "terms": bset.n_terms,
             "tree_vertices": st["tree_vertices"], "dtype": "f64",
             "ms_blocks": ms_b, "ms_contract_tree": ms_tree, "ms_contract_terms": ms_terms,
+            "ms_contract_tree_generic": ms_generic,
             "sites_per_s": T * V / ((ms_b + ms_tree) * 1e-3),
             "roofline": {"bound": "alu", "kernel": "block_g", "achieved": flops_b / (ms_b * 1e-3) / 1e12,
                          "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
