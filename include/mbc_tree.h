@@ -55,8 +55,9 @@ mbc_status mbc_factor_tree_workspace_bytes(const mbc_factor_tree* t, int64_t bat
  * values     device [batch][n_values] complex128 (re/im interleaved)
  * out        device [batch] complex128
  * workspace  device, >= mbc_factor_tree_workspace_bytes(t, batch)
- * One launch per depth level, deepest first; each vertex sums its children
- * in depth-first order (run-to-run reproducible). */
+ * Launches per depth level, deepest first; a vertex with many children is
+ * summed by a wavefront in a fixed order, the others by one thread in
+ * depth-first order (run-to-run reproducible). */
 mbc_status mbc_factor_tree_evaluate(const mbc_factor_tree* t, const double* values, int64_t batch, double* out,
                                     void* workspace, size_t ws_bytes, void* stream);
 /* Destroys a tree (NULL-safe); synchronises the device first. */

@@ -6,8 +6,10 @@
 // vertex's children and depth.  Device: the tree is evaluated bottom up, one
 // launch per depth level from the deepest: a vertex's value is its factor's
 // value (1 for the root) times its leaf coefficient or the sum of its
-// children's values, added in depth-first order; one thread per (table,
-// vertex).  The root's value is the tree's.
+// children's values: one thread per (table, vertex) for vertices with few
+// children, a wavefront per (table, vertex) for the others (its lanes
+// stride over the children and combine in a fixed butterfly).  The root's
+// value is the tree's.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,9 +69,15 @@ void build_tree_host(const int32_t* factors, const int32_t* children, int64_t n_
   t.level_begin.assign(t.depth + 2, 0);
   for (int64_t v = 0; v < n_vertices; ++v) ++t.level_begin[depth[v] + 1];
   for (int d = 0; d <= t.depth; ++d) t.level_begin[d + 1] += t.level_begin[d];
+  // per level: narrow vertices, then wide ones, each in depth-first order
   t.level_vertices.assign(n_vertices, 0);
+  t.level_wide.assign(t.depth + 1, 0);
   std::vector<int32_t> fill(t.level_begin.begin(), t.level_begin.end() - 1);
-  for (int64_t v = 0; v < n_vertices; ++v) t.level_vertices[fill[depth[v]]++] = int32_t(v);
+  for (int64_t v = 0; v < n_vertices; ++v)
+    if (children[v] <= kTreeNarrow) t.level_vertices[fill[depth[v]]++] = int32_t(v);
+  for (int d = 0; d <= t.depth; ++d) t.level_wide[d] = fill[d];
+  for (int64_t v = 0; v < n_vertices; ++v)
+    if (children[v] > kTreeNarrow) t.level_vertices[fill[depth[v]]++] = int32_t(v);
   t.flops = 8.0 * double(n_vertices - 1);
 }
 
@@ -90,22 +98,37 @@ struct TreeArgs {
   int32_t n_values;
 };
 
+// G lanes per (table, vertex): lane l sums children l, l + G, ..; the G
+// partial sums are combined by a fixed butterfly within the wavefront
+template <int G>
 __global__ __launch_bounds__(kTT) void tree_level_kernel(TreeArgs a, const int32_t* verts, int n, int root) {
-  const int64_t idx = int64_t(blockIdx.x) * kTT + threadIdx.x;
-  if (idx >= int64_t(n) * a.batch) return;
-  const int64_t b = idx / n;
-  const int32_t v = verts[idx - b * n];
+  const int64_t idx = (int64_t(blockIdx.x) * kTT + threadIdx.x) / G;
+  const int lane = int(threadIdx.x) % G;
+  const bool live = idx < int64_t(n) * a.batch;
+  int64_t b = 0;
+  int32_t v = 0;
   double2 s = make_double2(0, 0);
-  if (a.leaf[v] >= 0) {
-    s = a.coef[a.leaf[v]];
-  } else {
-    const double2* row = a.vals + b * a.n_vertices;
-    for (int32_t c = a.child_begin[v]; c < a.child_begin[v + 1]; ++c) {
-      const double2 x = row[a.child_list[c]];
-      s.x += x.x;
-      s.y += x.y;
+  if (live) {
+    b = idx / n;
+    v = verts[idx - b * n];
+    if (a.leaf[v] >= 0) {
+      if (lane == 0) s = a.coef[a.leaf[v]];
+    } else {
+      const double2* row = a.vals + b * a.n_vertices;
+      for (int32_t c = a.child_begin[v] + lane; c < a.child_begin[v + 1]; c += G) {
+        const double2 x = row[a.child_list[c]];
+        s.x += x.x;
+        s.y += x.y;
+      }
     }
   }
+  if constexpr (G > 1) {
+    for (int w = G / 2; w > 0; w >>= 1) {
+      s.x += __shfl_xor(s.x, w, G);
+      s.y += __shfl_xor(s.y, w, G);
+    }
+  }
+  if (!live || lane != 0) return;
   double2 r = s;
   if (a.factor[v] >= 0) {
     const double2 f = a.values[b * a.n_values + a.factor[v]];
@@ -134,12 +157,22 @@ hipError_t launch_tree_eval(const TreeHost& h, const TreeDev& d, const double* v
   a.batch = batch;
   a.n_values = h.n_values;
   for (int dd = h.depth; dd >= 0; --dd) {
-    const int n = h.level_begin[dd + 1] - h.level_begin[dd];
-    const unsigned nb = unsigned((int64_t(n) * batch + kTT - 1) / kTT);
-    hipLaunchKernelGGL(tree_level_kernel, dim3(nb), dim3(kTT), 0, st, a, d.level_vertices + h.level_begin[dd], n,
-                       dd == 0 ? 1 : 0);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int n_narrow = h.level_wide[dd] - h.level_begin[dd];
+    const int n_wide = h.level_begin[dd + 1] - h.level_wide[dd];
+    if (n_narrow > 0) {
+      const unsigned nb = unsigned((int64_t(n_narrow) * batch + kTT - 1) / kTT);
+      hipLaunchKernelGGL((tree_level_kernel<1>), dim3(nb), dim3(kTT), 0, st, a, d.level_vertices + h.level_begin[dd],
+                         n_narrow, dd == 0 ? 1 : 0);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (n_wide > 0) {
+      const unsigned nb = unsigned((int64_t(n_wide) * batch * 64 + kTT - 1) / kTT);
+      hipLaunchKernelGGL((tree_level_kernel<64>), dim3(nb), dim3(kTT), 0, st, a, d.level_vertices + h.level_wide[dd],
+                         n_wide, dd == 0 ? 1 : 0);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -11,10 +11,13 @@ namespace mbc {
 
 // The validated tree: children of every vertex as a list (depth-first
 // order), the vertices of every depth, and each leaf's coefficient index.
+// Within a level, vertices with at most kTreeNarrow children come first
+// (level_begin[d] .. level_wide[d]), then the wide ones (.. level_begin[d+1]).
+constexpr int kTreeNarrow = 16;
 struct TreeHost {
   int64_t n_vertices = 0;
   int32_t n_values = 0, depth = 0;
-  std::vector<int32_t> factor, child_begin, child_list, leaf, level_begin, level_vertices;
+  std::vector<int32_t> factor, child_begin, child_list, leaf, level_begin, level_wide, level_vertices;
   std::vector<double> coef;  // [n_leaves][2]
   double flops = 0;
 };
