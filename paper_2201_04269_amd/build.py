@@ -17,7 +17,7 @@ LIB = os.path.join(LIBDIR, "libmbc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["index_set.cpp", "block_set.cpp", "plan.cpp", "debug_eval.cpp", "abi.cpp", "kernels.hip", "kernels_bwd.hip",
-           "blocks.hip", "egraph.cpp", "egraph_exec.hip", "factor_tree.hip"]
+           "blocks.hip", "egraph.cpp", "egraph_exec.hip", "factor_tree.cpp", "factor_tree.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-command-line-argument",

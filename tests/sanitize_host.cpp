@@ -1,13 +1,16 @@
 // Host planner under AddressSanitizer and UndefinedBehaviorSanitizer (built
 // with g++, host code only, by tests/test_sanitizers.py): index sets and plan
 // tables of every operator family, block sets with their factor trees, block
-// plans and multiplicity counts, and the tensor e-graphs of block-level
-// correlators, including displaced sources and a node limit that stops
-// saturation.  Any sanitizer report aborts with a non-zero status.
+// plans and multiplicity counts, the tensor e-graphs of block-level
+// correlators (including displaced sources and a node limit that stops
+// saturation), and the parse of linearised factor trees.  Any sanitizer report aborts with a non-zero status.
 #include <cstdio>
 #include <vector>
 
+#include <stdexcept>
+
 #include "../paper_2201_04269_amd/csrc/egraph.hpp"
+#include "../paper_2201_04269_amd/csrc/factor_tree.hpp"
 #include "../paper_2201_04269_amd/csrc/mbc_internal.hpp"
 
 namespace {
@@ -65,6 +68,38 @@ int main() {
         egraph_build(prob, limit, obj, &g);
         checks += int64_t(g.steps.size());
       }
+  }
+  // linearised factor trees: Fig. 4's arrays, a wide root, and rejected inputs
+  {
+    const int32_t f4[] = {-1, 0, 2, 1, 2, 3};
+    const int32_t c4[] = {2, 1, 0, 2, 0, 0};
+    const double w4[] = {5, 0, 1, 0, -1, 0};
+    TreeHost t;
+    build_tree_host(f4, c4, 6, w4, 3, 4, &t);
+    checks += t.depth;
+    std::vector<int32_t> fw(101), cw(101, 0);
+    std::vector<double> ww(200, 1.0);
+    fw[0] = -1;
+    cw[0] = 100;
+    for (int v = 1; v <= 100; ++v) fw[v] = v % 7;
+    build_tree_host(fw.data(), cw.data(), 101, ww.data(), 100, 7, &t);
+    checks += t.level_wide[0];
+    const int32_t bad_c[] = {3, 0, 0};
+    const int32_t bad_f[] = {-1, 0, 1};
+    const double bw[] = {1, 0, 1, 0};
+    int rejected = 0;
+    try {
+      build_tree_host(bad_f, bad_c, 3, bw, 2, 2, &t);
+    } catch (const std::invalid_argument&) {
+      ++rejected;
+    }
+    const int32_t neg_c[] = {1, -1};
+    try {
+      build_tree_host(bad_f, neg_c, 2, bw, 1, 2, &t);
+    } catch (const std::invalid_argument&) {
+      ++rejected;
+    }
+    if (rejected != 2) return 1;
   }
   std::printf("sanitized host run ok (%ld)\n", checks);
   return 0;

@@ -1,5 +1,5 @@
-"""The host planner (index sets, plans, block sets, factor trees,
-multiplicities, tensor e-graphs) built with g++ under AddressSanitizer and
+"""The host planner (index sets, plans, block sets, factor trees and their
+parse, multiplicities, tensor e-graphs) built with g++ under AddressSanitizer and
 UndefinedBehaviorSanitizer and run on every operator family (no GPU).
 
 Only host C++ is instrumented: the HIP kernels are not compiled here.
@@ -12,7 +12,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2201_04269_amd", "csrc")
-SOURCES = ["index_set.cpp", "block_set.cpp", "plan.cpp", "egraph.cpp"]
+SOURCES = ["index_set.cpp", "block_set.cpp", "plan.cpp", "egraph.cpp", "factor_tree.cpp"]
 
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
