@@ -190,7 +190,7 @@ def bench_egraph(api, torch, bset, blk, steps, warmup, node_limit=1000):
     executor cannot take) is reported, not run."""
     T = blk.shape[0]
     out = {"node_limit": node_limit}
-    for objective in ("reuse", "flops"):
+    for objective in ("reuse", "flops", "shared"):
         t0 = time.perf_counter()
         try:
             graphs = [api.TensorEGraph.for_blocks(bset, c, node_limit, objective) for c in range(bset.n_corr)]

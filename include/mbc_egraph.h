@@ -44,6 +44,13 @@
  *                direct cost of c, then the fewest flops of its own
  *                contraction, then the first.  MBC_EXTRACT_FLOPS: the
  *                smallest tree cost (own contraction + children's).
+ *                MBC_EXTRACT_SHARED: the MBC_EXTRACT_FLOPS choice refined in
+ *                rounds (at most 10): with P the classes of the current plan,
+ *                each class of P (by id) takes the e-node minimising its own
+ *                flops plus the tree cost of its distinct children with two
+ *                or more factors that are not in P (a class of the plan is
+ *                computed once), if strictly cheaper; new children take
+ *                their tree-cost e-node.
  *   flops        a contraction E1 E2 -> E costs 8 x the product of the
  *                extents of the labels of E1 and E2 (one complex
  *                multiply-add per point); the direct cost of an n-factor
@@ -64,7 +71,7 @@ extern "C" {
 #endif
 
 enum { MBC_EGRAPH_MAX_RANK = 8, MBC_EGRAPH_MAX_SYM = 4, MBC_EGRAPH_MAX_LABEL = 64, MBC_EGRAPH_MAX_FACTORS = 16 };
-enum { MBC_EXTRACT_REUSE = 0, MBC_EXTRACT_FLOPS = 1 };
+enum { MBC_EXTRACT_REUSE = 0, MBC_EXTRACT_FLOPS = 1, MBC_EXTRACT_SHARED = 2 };
 
 typedef struct {
   int32_t rank;                                       /* 1..MBC_EGRAPH_MAX_RANK */

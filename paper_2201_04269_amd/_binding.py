@@ -69,7 +69,7 @@ class EGraphStats(ctypes.Structure):
                 ("flops_direct", ctypes.c_double), ("flops_plan", ctypes.c_double)]
 
 
-EXTRACT = {"reuse": 0, "flops": 1}
+EXTRACT = {"reuse": 0, "flops": 1, "shared": 2}
 FAMILIES = {0: "p", 1: "n"}
 BLOCK_METHODS = {"terms": 0, "tree": 1}
 

@@ -353,7 +353,8 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
   EGraphHost& g = *gp;
   g = EGraphHost();
   if (node_limit < 0) throw std::invalid_argument("node_limit must be >= 0");
-  if (objective != MBC_EXTRACT_REUSE && objective != MBC_EXTRACT_FLOPS) throw std::invalid_argument("objective");
+  if (objective != MBC_EXTRACT_REUSE && objective != MBC_EXTRACT_FLOPS && objective != MBC_EXTRACT_SHARED)
+    throw std::invalid_argument("objective");
   const int nt = int(prob.decls.size());
   if (nt < 1) throw std::invalid_argument("no tensors declared");
   for (const mbc_tensor_decl& d : prob.decls) {
@@ -557,6 +558,74 @@ void egraph_build(const TensorProblem& prob, int64_t node_limit, int objective, 
                                [](const TermRoot& q) { return q.re == 0.0 && q.im == 0.0; }),
                 g.roots.end());
   for (const TermRoot& r : g.roots) pick(r.cls);
+  if (objective == MBC_EXTRACT_SHARED) {
+    // Sharing-aware refinement of the tree-cost choice: in rounds (at most
+    // 10), with P the classes of the current plan, every class of P (by id)
+    // takes the e-node minimising its own flops plus the tree cost of each
+    // distinct child with two or more factors that is not in P; a change is
+    // kept only if strictly cheaper, and new children get their tree-cost
+    // choice.
+    std::function<void(int)> tree_pick = [&](int c) {
+      c = g.find(c);
+      if (choice[c] >= 0 || is_leaf(c)) return;
+      const std::vector<ENode>& nodes = g.cls[c].nodes;
+      int best = 0;
+      i128 bv = -1;
+      for (int i = 0; i < int(nodes.size()); ++i) {
+        const i128 v = node_flops(c, nodes[i]) + tree_cost(nodes[i].c1) + tree_cost(nodes[i].c2);
+        if (bv < 0 || v < bv) {
+          best = i;
+          bv = v;
+        }
+      }
+      choice[c] = best;
+      tree_pick(nodes[best].c1);
+      tree_pick(nodes[best].c2);
+    };
+    for (int round = 0; round < 10; ++round) {
+      std::vector<char> in_plan(nc, 0);
+      std::vector<int> P, stack;
+      for (const TermRoot& r : g.roots) stack.push_back(r.cls);
+      while (!stack.empty()) {
+        const int c = g.find(stack.back());
+        stack.pop_back();
+        if (in_plan[c] || is_leaf(c)) continue;
+        in_plan[c] = 1;
+        P.push_back(c);
+        const ENode& nd = g.cls[c].nodes[choice[c]];
+        stack.push_back(nd.c1);
+        stack.push_back(nd.c2);
+      }
+      std::sort(P.begin(), P.end());
+      bool changed = false;
+      for (int c : P) {
+        const std::vector<ENode>& nodes = g.cls[c].nodes;
+        auto cost = [&](const ENode& nd) {
+          i128 v = node_flops(c, nd);
+          const int k1 = g.find(nd.c1), k2 = g.find(nd.c2);
+          if (!in_plan[k1] && !is_leaf(k1)) v += tree_cost(k1);
+          if (k2 != k1 && !in_plan[k2] && !is_leaf(k2)) v += tree_cost(k2);
+          return v;
+        };
+        int best = 0;
+        i128 bv = cost(nodes[0]);
+        for (int i = 1; i < int(nodes.size()); ++i) {
+          const i128 v = cost(nodes[i]);
+          if (v < bv) {
+            best = i;
+            bv = v;
+          }
+        }
+        if (bv < cost(nodes[choice[c]])) {
+          choice[c] = best;
+          changed = true;
+          tree_pick(nodes[best].c1);
+          tree_pick(nodes[best].c2);
+        }
+      }
+      if (!changed) break;
+    }
+  }
 
   // steps: post-order from the terms, each class once
   g.step_of.assign(nc, -1);

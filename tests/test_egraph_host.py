@@ -50,11 +50,14 @@ def test_paper_example_matches_the_oracle():
     _compare(g, og, "reuse")
     gf = api.TensorEGraph([((3, 3, 3), E.EPS_GENS), ((3, 3, 3), [])], [(1.0, expr)], 1000, "flops")
     _compare(gf, og, "flops")
+    gs = api.TensorEGraph([((3, 3, 3), E.EPS_GENS), ((3, 3, 3), [])], [(1.0, expr)], 1000, "shared")
+    _compare(gs, og, "shared")
+    assert gs.export()["steps"] == gf.export()["steps"]  # B_kl B_lk is already the cheapest
     assert gf.stats["n_steps"] == 2 and gf.stats["flops_plan"] < g.stats["flops_direct"]
 
 
 @pytest.mark.parametrize("seed", range(16))
-@pytest.mark.parametrize("objective", ["reuse", "flops"])
+@pytest.mark.parametrize("objective", ["reuse", "flops", "shared"])
 def test_random_sums_match_the_oracle_exactly(seed, objective):
     rng = np.random.default_rng(300 + seed)
     T = _tensors(rng)
@@ -176,6 +179,13 @@ def test_exact_dii_cancels_and_r2_is_twice_di_by_canonical_forms():
     assert st["n_roots"] == 0 and st["n_steps"] == 0
     r2, di = roots["r2"][0], roots["di"][0]
     assert set(r2) == set(di) and all(r2[k] == 2 * di[k] for k in di)
+
+
+def test_sharing_aware_extraction_lowers_the_dinucleon_plan():
+    bset = api.BlockSet([dict(op="DI", moms=[(1, 0, 0), (-1, 0, 0)])])
+    f = api.TensorEGraph.for_blocks(bset, 0, 100000, "flops").stats["flops_plan"]
+    s = api.TensorEGraph.for_blocks(bset, 0, 100000, "shared").stats["flops_plan"]
+    assert s < 0.95 * f
 
 
 def test_the_papers_dii_subexpressions_are_shared_classes():

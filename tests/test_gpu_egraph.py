@@ -22,7 +22,7 @@ DEV = "cuda"
 
 
 @pytest.mark.parametrize("seed", range(8))
-@pytest.mark.parametrize("objective", ["reuse", "flops"])
+@pytest.mark.parametrize("objective", ["reuse", "flops", "shared"])
 def test_random_sums_equal_the_direct_contraction(seed, objective):
     rng = np.random.default_rng(500 + seed)
     T = _tensors(rng)
@@ -93,7 +93,7 @@ CORRS = [
 
 
 @pytest.mark.parametrize("corr,dims,P", CORRS)
-@pytest.mark.parametrize("objective", ["reuse", "flops"])
+@pytest.mark.parametrize("objective", ["reuse", "flops", "shared"])
 def test_block_correlators_by_the_egraph_equal_the_oracle(corr, dims, P, objective):
     T = 2
     V = dims[0] * dims[1] * dims[2]

@@ -149,7 +149,7 @@ def test_vanishing_expressions_are_detected():
 
 
 @pytest.mark.parametrize("seed", range(10))
-@pytest.mark.parametrize("objective", ["reuse", "flops"])
+@pytest.mark.parametrize("objective", ["reuse", "flops", "shared"])
 def test_extracted_plan_equals_the_direct_contraction(seed, objective):
     rng = np.random.default_rng(200 + seed)
     T = _tensors(rng)
