@@ -236,6 +236,11 @@ mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stre
       delete p;
       throw;
     }
+    std::string why;
+    if (!forward_supports(p->h, &why) || !backward_supports(p->h, &why)) {
+      delete p;
+      return fail(MBC_ERR_UNSUPPORTED, why);
+    }
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;

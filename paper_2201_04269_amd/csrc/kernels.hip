@@ -260,8 +260,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__
   }
 }
 
+// Source-key slots per thread (MAXS) and columns per thread (QMAX) the
+// forward kernel is instantiated with, per operator family; 0 if none.
+constexpr int fwd_maxs(int nu, int nd) {
+  return (nu == 2 && nd == 1) || (nu == 1 && nd == 2) ? 1 : ((nu == 3 && nd == 3) || (nu == 5 && nd == 4) ? 4 : 0);
+}
+constexpr int fwd_qmax(int nu, int nd) { return fwd_maxs(nu, nd) ? 1 : 0; }
+
 template <typename R, int NU, int ND, int MAXS, int QMAX>
 hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+  static_assert(MAXS == fwd_maxs(NU, ND) && QMAX == fwd_qmax(NU, ND), "instantiation table");
   constexpr int NT = family_threads(NU, ND);
   if ((p->h.max_src + NT - 1) / NT > MAXS || (p->h.max_ncol + NT - 1) / NT > QMAX) return hipErrorNotSupported;
   auto k = fwd_kernel<R, NU, ND, MAXS, QMAX, NT>;
@@ -284,6 +292,25 @@ hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t
 }
 
 }  // namespace
+
+bool forward_supports(const PlanHost& h, std::string* why) {
+  const int maxs = fwd_maxs(h.n_u, h.n_d), qmax = fwd_qmax(h.n_u, h.n_d);
+  const int nt = family_threads(h.n_u, h.n_d);
+  if (maxs == 0) {
+    *why = "no forward kernel for (n_u, n_d) = (" + std::to_string(h.n_u) + ", " + std::to_string(h.n_d) + ")";
+    return false;
+  }
+  if ((h.max_src + nt - 1) / nt > maxs) {
+    *why = "a correlator has " + std::to_string(h.max_src) + " source keys, more than the forward kernel's " +
+           std::to_string(maxs * nt);
+    return false;
+  }
+  if ((h.max_ncol + nt - 1) / nt > qmax) {
+    *why = "a level has " + std::to_string(h.max_ncol) + " columns, more than the kernels' " + std::to_string(qmax * nt);
+    return false;
+  }
+  return true;
+}
 
 Launch forward_launch_shape(const PlanHost& h, int T, int64_t V) {
   Launch L;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <string>
+
 #include "mbc_internal.hpp"
 
 namespace mbc {
@@ -15,6 +17,13 @@ struct Launch {
 };
 
 Launch forward_launch_shape(const PlanHost& h, int T, int64_t V);
+
+// Whether the kernels are instantiated for a compiled plan's family and
+// sizes (source keys per thread, columns per level, dW keys per tile, dS
+// bins and source-key lists); false with the reason in *why otherwise.
+// mbc_plan_create rejects such a plan with MBC_ERR_UNSUPPORTED.
+bool forward_supports(const PlanHost& h, std::string* why);
+bool backward_supports(const PlanHost& h, std::string* why);
 
 // W_plan[i] = W_user[perm[i]] in the plan's precision.
 hipError_t launch_gather_w(const mbc_plan* p, const double* W_user, void* W_plan, hipStream_t st);

@@ -803,6 +803,29 @@ hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, 
 
 }  // namespace
 
+bool backward_supports(const PlanHost& h, std::string* why) {
+  const int nu = h.n_u, nd = h.n_d;
+  const bool fam = (nu == 2 && nd == 1) || (nu == 1 && nd == 2) || (nu == 3 && nd == 3) || (nu == 5 && nd == 4);
+  if (!fam) {
+    *why = "no backward kernels for (n_u, n_d) = (" + std::to_string(nu) + ", " + std::to_string(nd) + ")";
+    return false;
+  }
+  // dW: source slots per thread, one column per thread, keys per tile
+  const int nt = family_threads(nu, nd);
+  if (h.max_src > dw_src_per_thread(nu, nd) * nt || h.max_ncol > nt ||
+      h.w_max_b > dw_keys_per_tile(nu, nd, h.precision)) {
+    *why = "the dW kernel is not instantiated for this plan's source keys, columns or keys per tile";
+    return false;
+  }
+  // dS: columns per level, source keys per top column, j-list bins
+  const int maxcol = nu + nd >= 8 ? 512 : 256, mc = nu + nd >= 8 ? 10 : (nu + nd >= 6 ? 6 : 2);
+  if (h.max_ncol > maxcol || h.max_csr > mc || !bins_fit(h)) {
+    *why = "the dS kernel is not instantiated for this plan's columns, source-key lists or j-lists";
+    return false;
+  }
+  return true;
+}
+
 Launch backward_dw_launch_shape(const PlanHost& h, int T, int64_t V) {
   Launch L;
   L.T = T;

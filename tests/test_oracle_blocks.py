@@ -173,3 +173,93 @@ def test_one_source_point_set_reproduces_the_local_source():
     f = B.block(Su, Sd, "p", (1, 0, 0), (2, 1, 1), srcs=(1, 1, 1))
     g = B.block(Su[1], Sd[1], "p", (1, 0, 0), (2, 1, 1))
     assert np.array_equal(f, g)
+
+
+# ---------------------------------------------------------------------------
+# Multiplicity histogram (Sec. 3, Fig. 2): pins of the counting rule
+# ---------------------------------------------------------------------------
+# Non-zero entries (row, column) of C gamma5 in the Dirac basis (reading of
+# Sec. 1's C gamma5: real, antisymmetric, one entry per row and column).
+_CG5_PAIRS = {(0, 1), (1, 0), (2, 3), (3, 2)}
+
+
+def test_multiplicity_histogram_of_the_proton_by_hand():
+    # p^alpha's source expands into 6 colour permutations x 4 (beta', gamma')
+    # entries of C gamma5 = 24 written terms, each with the one partition
+    # (A, Y, C) = (ubar, dbar, ubar) in written order; the bundles
+    # (4a'+beta', 4b'+gamma', 4c'+alpha') recover (a', b', c', beta', gamma'),
+    # so all 24 strings are distinct
+    for op in ("proton", "neutron"):
+        n, hist = B.multiplicity_histogram(op, 0, 0, "exact")
+        assert n == 24 and dict(hist) == {1: 24}
+
+
+def test_multiplicity_histogram_of_di_by_inverting_the_expansion():
+    """D_I's histogram counted the other way round: for every candidate string,
+    the number of (source term, partition) pairs that produce it.
+
+    A D_I term is a written source term nbar^{a'} pbar^{b'} (fields
+    dbar ubar dbar | ubar dbar ubar at positions 0..5), a sink product (the
+    n and p spins (alpha, beta), a C gamma5 entry) and a partition: the n
+    block takes two of the three dbar (in position order, A and C) and one
+    ubar (Y), the p block the other two ubar (A', C') and the last dbar (Y').
+    Given a string (A, Y, C, A', Y', C'; alpha, beta) and a partition (which
+    dbar k went to p, which ubar m went to n), the source term is fixed: it
+    exists iff each source baryon's three colours are a permutation (eps),
+    its first two spins are a C gamma5 pair, and the two source baryons'
+    open spins are a C gamma5 pair.  A string's multiplicity is the number
+    of the 9 partitions for which that holds.  The sink spins only label the
+    string, so every sink product contributes the same counts.
+    """
+    from collections import Counter
+    lab = np.indices((12,) * 6).reshape(6, -1)
+    A, Y, Cc, A2, Y2, C2 = lab
+    col, spin = lab // 4, lab % 4
+
+    def pair_ok(s1, s2):
+        ok = np.zeros(s1.shape, bool)
+        for a, b in _CG5_PAIRS:
+            ok |= (s1 == a) & (s2 == b)
+        return ok
+
+    def colours_ok(c1, c2, c3):
+        return (c1 != c2) & (c1 != c3) & (c2 != c3)
+
+    mult = np.zeros(A.shape, np.int64)
+    for k in range(3):          # the dbar that went to the p block (as Y')
+        for m in range(3):      # the ubar that went to the n block (as Y)
+            d = [None] * 3
+            d[k] = Y2
+            rest = iter((A, Cc))
+            for q in range(3):
+                if q != k:
+                    d[q] = next(rest)
+            u = [None] * 3
+            u[m] = Y
+            rest = iter((A2, C2))
+            for q in range(3):
+                if q != m:
+                    u[q] = next(rest)
+            # written source: nbar = dbar(d0) ubar(u0) dbar(d1), pbar = ubar(u1) dbar(d2) ubar(u2)
+            ok = colours_ok(d[0] // 4, u[0] // 4, d[1] // 4) & pair_ok(d[0] % 4, u[0] % 4)
+            ok &= colours_ok(u[1] // 4, d[2] // 4, u[2] // 4) & pair_ok(u[1] % 4, d[2] % 4)
+            ok &= pair_ok(d[1] % 4, u[2] % 4)
+            mult += ok
+    per_product = Counter(mult[mult > 0].tolist())
+    expect = Counter({m: len(_CG5_PAIRS) * c for m, c in per_product.items()})
+    n, hist = B.multiplicity_histogram("DI", 0, 0, "exact")
+    assert n == sum(m * c for m, c in expect.items()) == 82944
+    assert dict(hist) == dict(expect)
+    assert max(hist) == 9  # every partition of one string
+
+
+@pytest.mark.slow
+def test_multiplicity_histogram_of_dii_is_sign_free_and_symmetric():
+    # the counting key carries no sign: exact and R2 signs give one histogram;
+    # the key is sorted: product (p, n) of every term has a twin from
+    # product (n, p) with the same factors (the slots' blocks swapped), so
+    # every multiplicity is even
+    n1, h1 = B.multiplicity_histogram("DII", 0, 0, "exact")
+    n2, h2 = B.multiplicity_histogram("DII", 0, 0, "r2")
+    assert n1 == n2 and h1 == h2
+    assert all(m % 2 == 0 for m in h1)

@@ -201,3 +201,79 @@ def test_block_expressions_equal_the_block_level_correlator(op, s, sp, mode, mom
     ref = OB.block_correlator(Su, Sd, op, s, sp, mode, moms, dims, src_pts=pts)[0]
     assert abs(got - ref) <= 1e-13 * abs(ref)
     assert abs(ref) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Extraction choices pinned on hand-worked examples (Sec. 5 objective)
+# ---------------------------------------------------------------------------
+def _chain_graph(ext, labels, node_limit=1000):
+    groups = {t: E.closure([], len(e)) for t, e in ext.items()}
+    expr = [(t, lab) for t, lab in labels]
+    return E.EGraph(groups, ext).build([(1.0, expr)], node_limit), expr
+
+
+def test_tree_cost_picks_the_cheapest_order_of_a_three_factor_chain():
+    # A_ij (2 x 8) B_jk (8 x 8) C_kl (8 x 8), open i, l.  By hand, at 8 flops
+    # per complex multiply-add over the labels of the two operands:
+    #   (A B) C: 8 (2*8*8) + 8 (2*8*8)       =  2048
+    #   A (B C): 8 (8*8*8) + 8 (2*8*8)       =  5120
+    #   (A C) B: 8 (2*8*8*8) + 8 (2*8*8*8)   = 16384  (A C is an outer product)
+    # catches a cost model that counts only the result's labels, or a pick of
+    # the first admitted split instead of the cheapest tree
+    g, expr = _chain_graph({0: (2, 8), 1: (8, 8), 2: (8, 8)}, [(0, (0, 1)), (1, (1, 2)), (2, (2, 3))])
+    steps, flops = g.plan("flops")
+    assert flops == 2048 and len(steps) == 2
+    first = g.cls[steps[0][0]]
+    assert sorted(t for t, _ in first["factors"]) == [0, 1]  # A B first
+    rng = np.random.default_rng(5)
+    T = {t: rng.standard_normal(e) + 1j * rng.standard_normal(e) for t, e in ((0, (2, 8)), (1, (8, 8)), (2, (8, 8)))}
+    direct = E.evaluate([(1.0, expr)], T, [0, 3])
+    assert np.allclose(g.evaluate_plan(T, [0, 3], "flops"), direct, rtol=1e-13, atol=0)
+
+
+def test_tree_cost_of_a_vector_matrix_chain():
+    # v_i M_ij N_jk u_k (all extents 8), a scalar.  Every order that never
+    # forms M N costs 8 (64 + 64 + 8) = 1088 by hand (v M, then with N, then
+    # with u; or v M and N u, then their dot product); forming M N first
+    # costs 8 (512 + ...) and more
+    ext = {0: (8,), 1: (8, 8), 2: (8, 8), 3: (8,)}
+    g, expr = _chain_graph(ext, [(0, (0,)), (1, (0, 1)), (2, (1, 2)), (3, (2,))])
+    steps, flops = g.plan("flops")
+    assert flops == 1088 and len(steps) == 3
+
+
+def test_reuse_objective_scores_on_the_paper_example_by_hand():
+    """The reuse objective (excess parents from distinct e-classes x flops,
+    read per child class) on E = eps_ijk eps_lmn T_ijl T_nmk, by hand.
+
+    Saturated, the e-graph holds these 2-factor classes, with their parent
+    classes (classes that have an e-node using them) and direct costs:
+      eps eps (outer, 3^6 points):   parents E, eps eps T         -> 2, 8*729 = 5832
+      T T (outer, 3^6 points):       parents E, eps T T           -> 2, 5832
+      B_kl = eps_ijk T_ijl (3^4):    parents E, eps eps T, eps T T -> 3, 8*81 = 648
+      eps_ijk T_nmk (one shared, 3^5): parents E, eps eps T, eps T T -> 3, 8*243 = 1944
+    so the root's e-nodes score (eps eps)(T T): 5832 + 5832 = 11664,
+    (eps T_nmk)^2: 2*1944 = 3888, B_kl B_lk: 2*648 = 1296, and splits with a
+    3-factor child (one parent each) 0: the objective picks (eps eps)(T T),
+    not the example's B_kl B_lk, which the smallest tree cost picks.
+    """
+    gold = json.load(open(GOLD))
+    tid = {"eps": 0, "T": 1}
+    expr = [(tid[n], tuple(l)) for n, l in gold["factors"]]
+    groups = {0: E.closure(E.EPS_GENS, 3), 1: E.closure([], 3)}
+    g = E.EGraph(groups, {0: (3, 3, 3), 1: (3, 3, 3)}).build([(1.0, expr)], 1000)
+    npar = g.n_parents()
+    two = {}
+    for cid in range(len(g.cls)):
+        c = g.cls[cid]
+        if g.find(cid) == cid and len(c["factors"]) == 2:
+            key = (tuple(sorted(t for t, _ in c["factors"])), c["n_open"])
+            two[key] = (npar[cid], g.naive_flops(cid))
+    assert two == {((0, 0), 6): (2, 5832), ((1, 1), 6): (2, 5832), ((0, 1), 2): (3, 648), ((0, 1), 4): (3, 1944)}
+    root = g.roots[0][0]
+    choice = g.extract("reuse")
+    n = g.cls[root]["nodes"][choice[root]]
+    kids = sorted(tuple(sorted(t for t, _ in g.cls[g.find(k)]["factors"])) for k in n[:2])
+    assert kids == [(0, 0), (1, 1)]  # (eps eps)(T T)
+    n = g.cls[root]["nodes"][g.extract("flops")[root]]
+    assert n[0] == n[1] and g.cls[g.find(n[0])]["n_open"] == 2  # B_kl B_lk

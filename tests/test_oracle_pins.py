@@ -339,3 +339,63 @@ def test_gradient_w_equals_site_products():
                 dd = np.linalg.det(Sd[t, v][np.ix_(iset.snk_d[k], iset.src_d[k])])
                 ref[k] += gC[0, t] * np.conj(du * dd)
     assert np.allclose(gW, ref, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Gradient scales (the tolerance of every gradient parity test)
+# ---------------------------------------------------------------------------
+def _monomial_gradient_scales(Su, Sd, iset, gC):
+    """Sum of |monomial| derivatives at one site, by explicit enumeration.
+
+    Every canonical entry k expands (eq. 1 with Leibniz's formula for both
+    determinants) into the monomials W_k sgn(pu) sgn(pd) prod_i S_u[ru_i, cu_pu(i)]
+    prod_i S_d[rd_i, cd_pd(i)], one per pair of permutations (pu, pd).  With
+    every sign dropped, the scale of a gradient entry is the sum over the
+    monomials that contain that propagator entry of |g| |W_k| times the
+    magnitudes of the monomial's other factors; the scale of grad_W[k] is the
+    sum of |g| times the magnitudes of all factors of entry k's monomials.
+    No permanent and no cofactor is formed here.
+    """
+    from itertools import permutations
+    aSu, aSd = np.abs(Su), np.abs(Sd)
+    ag = np.abs(gC[iset.corr_id, 0])
+    aW = np.abs(iset.weights())
+    nu, nd = iset.nu, iset.nd
+    out_W = np.zeros(iset.nnz)
+    out_u = np.zeros(144)
+    out_d = np.zeros(144)
+    for pu in permutations(range(nu)):
+        fu = [aSu[iset.snk_u[:, i], iset.src_u[:, pu[i]]] for i in range(nu)]
+        for pd in permutations(range(nd)):
+            fd = [aSd[iset.snk_d[:, i], iset.src_d[:, pd[i]]] for i in range(nd)]
+            allf = fu + fd
+            out_W += ag * np.prod(allf, axis=0)
+            for slot in range(nu + nd):
+                rest = ag * aW * np.prod([f for q, f in enumerate(allf) if q != slot], axis=0)
+                if slot < nu:
+                    flat = iset.snk_u[:, slot] * 12 + iset.src_u[:, pu[slot]]
+                    out_u += np.bincount(flat, weights=rest, minlength=144)
+                else:
+                    i = slot - nu
+                    flat = iset.snk_d[:, i] * 12 + iset.src_d[:, pd[i]]
+                    out_d += np.bincount(flat, weights=rest, minlength=144)
+    return out_W, out_u.reshape(12, 12), out_d.reshape(12, 12)
+
+
+@pytest.mark.parametrize("op", ["proton", "neutron", "DI"])
+def test_gradient_abs_scales_equal_the_monomial_enumeration(op):
+    # catches, in gradient_abs_scales: a dropped |W| or |g|, the other
+    # flavour's permanent taken from the wrong flavour, a transposed
+    # (source, sink) flat index, or a cofactor permanent of the wrong minor
+    Su, Sd = synth.iid(1, 1, seed=91)
+    iset = iset_of(op)
+    gC = np.array([[0.7 - 1.3j]])
+    got = CO.gradient_abs_scales(Su, Sd, iset, gC)
+    ref_W, ref_u, ref_d = _monomial_gradient_scales(Su[0, 0], Sd[0, 0], iset, gC)
+    assert np.allclose(got["W"], ref_W, rtol=1e-12, atol=0)
+    assert np.allclose(got["S_u"][0, 0], ref_u, rtol=1e-12, atol=0)
+    assert np.allclose(got["S_d"][0, 0], ref_d, rtol=1e-12, atol=0)
+    # and each scale bounds its gradient entry (every term counted by magnitude)
+    g = CO.gradients(Su, Sd, iset, gC)
+    for name in ("W", "S_u", "S_d"):
+        assert np.all(np.abs(g[name]) <= got[name] * (1 + 1e-12) + 1e-300)
