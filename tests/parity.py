@@ -25,3 +25,12 @@ def tol_f64(C_ref, A, nu, nd):
 
 def tol_f32c(A, nu, nd):
     return kappa(nu, nd) * 2.0 ** -24 * A
+
+
+def f64_branch(C_ref, A, nu, nd):
+    """Which term of the FP64 bound applied, per entry: 'rel' where
+    1e-12 |C| exceeds kappa 2^-53 A, 'abs' otherwise; returns a short report."""
+    rel = 1e-12 * np.abs(C_ref)
+    ab = kappa(nu, nd) * 2.0 ** -53 * np.asarray(A)
+    n_rel = int(np.count_nonzero(rel > ab))
+    return f"FP64 bound branch: 1e-12|C| on {n_rel}, kappa 2^-53 A on {rel.size - n_rel} of {rel.size} entries"

@@ -13,7 +13,7 @@ import pytest
 from oracle import correlator as CO
 from oracle import operators as O
 from paper_2201_04269_amd import synth
-from tests.parity import kappa, tol_f32c, tol_f64
+from tests.parity import f64_branch, kappa, tol_f32c, tol_f64
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -80,6 +80,8 @@ def _check(C, ref, A, nu, nd, prec, label):
     tol = tol_f64(ref, A, nu, nd) if prec == "f64" else tol_f32c(A, nu, nd)
     mask = A > 0
     print(label, prec, "max err/A", float(np.max(err[mask] / A[mask])) if mask.any() else 0.0, flush=True)
+    if prec == "f64":
+        print(label, f64_branch(ref, A, nu, nd), flush=True)
     assert np.all(err <= tol + 1e-300)
 
 
