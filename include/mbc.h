@@ -158,6 +158,22 @@ mbc_status mbc_contract(const mbc_plan* p, const void* S_u, const void* S_d, int
                         int32_t T, int64_t sites_per_t, const double* W, double* C,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* ---- forward without allocation or workspace ----
+ * For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, result and errors as mbc_contract without
+ * the workspace: the intermediate buffers (plan-ordered weights when W is
+ * given, per-tile partial sums) live in a fixed scratch array of
+ * 32 MiB = 33554432 bytes per GPU, held by the library until the process
+ * ends.  A call whose intermediates would exceed it returns
+ * MBC_ERR_UNSUPPORTED (for example the 3He batch with a caller W: 8.35M
+ * weights); use mbc_contract with a workspace there.  The call allocates
+ * nothing.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+mbc_status mbc_contract_noalloc(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
+                                int32_t T, int64_t sites_per_t, const double* W, double* C, void* stream);
+
 /* ---- backward (adjoint of mbc_contract), PyTorch's complex convention ----
  * grad_C    device [n_corr][T] complex128: dL/dC* of a real loss L
  * grad_W    device [nnz] complex128 or NULL:

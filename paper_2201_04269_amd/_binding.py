@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libmbc.so")
 
 MBC_OK = 0
+MBC_ERR_UNSUPPORTED = 2
 OPS = {"proton": 0, "neutron": 1, "DI": 2, "DII": 3, "HE3_I": 4, "HE3_II": 5}
 SIGNS = {"exact": 0, "r2": 1}
 F64, F32C = 0, 1
@@ -90,6 +91,7 @@ SIGNATURES = [
     ("mbc_plan_workspace_bytes", _I32, [_P, _I32, _I64, _I32, ctypes.POINTER(_SZ)]),
     ("mbc_plan_destroy", None, [_P]),
     ("mbc_contract", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
+    ("mbc_contract_noalloc", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P]),
     ("mbc_contract_backward", _I32, [_P, _P, _P, _I32, _I32, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("mbc_debug_eval_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, ctypes.POINTER(PlanStats)]),
     ("mbc_debug_backward_host", _I32, [_P, _I32, _P, _P, _I32, _I64, _P, _P, _P, _P, _P]),

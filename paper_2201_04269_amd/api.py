@@ -139,6 +139,22 @@ def contract(plan, S_u, S_d, W=None, stream=None):
     return C
 
 
+def contract_noalloc(plan, S_u, S_d, C, W=None, stream=None):
+    """mbc_contract_noalloc: eq. 1 into the caller's C (complex128 [n_corr, T])
+    with the library's fixed per-GPU scratch instead of a workspace; nothing
+    is allocated by this call.  Overlapping calls on one GPU race."""
+    dt = _check_S(S_u, S_d)
+    T, V = S_u.shape[:2]
+    if W is not None and (W.dtype != torch.complex128 or not W.is_cuda or W.numel() != plan.iset.nnz
+                          or not W.is_contiguous()):
+        raise ValueError("W must be a contiguous CUDA complex128 tensor of nnz entries")
+    if C.dtype != torch.complex128 or not C.is_cuda or tuple(C.shape) != (plan.n_corr, T) or not C.is_contiguous():
+        raise ValueError("C must be a contiguous CUDA complex128 tensor [n_corr, T]")
+    B.check(B.lib().mbc_contract_noalloc(plan._h, _ptr(S_u), _ptr(S_d), dt, int(T), int(V), _ptr(W), _ptr(C),
+                                         _stream_ptr(stream)))
+    return C
+
+
 def contract_backward(plan, S_u, S_d, W, grad_C, need_W=True, need_S=True, stream=None):
     """(grad_W, grad_S_u, grad_S_d) of mbc_contract_backward (None where not requested)."""
     dt = _check_S(S_u, S_d)

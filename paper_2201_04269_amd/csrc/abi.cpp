@@ -362,6 +362,39 @@ mbc_status mbc_contract(const mbc_plan* p, const void* S_u, const void* S_d, int
   return MBC_OK;
 }
 
+mbc_status mbc_contract_noalloc(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype, int32_t T,
+                                int64_t sites_per_t, const double* W, double* C, void* stream) {
+  mbc_status st = check_common(p, S_u, S_d, s_dtype, T, sites_per_t);
+  if (st != MBC_OK) return st;
+  if (!is_device_ptr(C)) return fail(MBC_ERR_INVALID, "C must be a device pointer");
+  if (W && !is_device_ptr(W)) return fail(MBC_ERR_INVALID, "W must be a device pointer or NULL");
+  if (W && !aligned16(W)) return fail(MBC_ERR_INVALID, "W must be 16-byte aligned");
+  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+  const FwdWorkspace ws = fwd_workspace(p->h, L, W != nullptr);
+  if (ws.total > kScratchBytes)
+    return fail(MBC_ERR_UNSUPPORTED, "mbc_contract_noalloc needs " + std::to_string(ws.total) +
+                                         " bytes of scratch, more than its fixed " + std::to_string(kScratchBytes) +
+                                         " (use mbc_contract with a workspace)");
+  int dev = -1;
+  MBC_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MBC_ERR_INVALID, "plan was created on another device");
+  void* scr = nullptr;
+  MBC_HIP(scratch_device_ptr(&scr));
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  // the scratch needs no clearing: the weight gather and the forward kernel
+  // write every element they later read
+  char* wsb = static_cast<char*>(scr);
+  const void* W_plan = p->d.w_exact;
+  if (W) {
+    MBC_HIP(launch_gather_w(p, W, wsb, hs));
+    W_plan = wsb;
+  }
+  double* partial = reinterpret_cast<double*>(wsb + ws.w_plan);
+  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, hs));
+  MBC_HIP(launch_reduce(p, L, partial, C, hs));
+  return MBC_OK;
+}
+
 mbc_status mbc_contract_backward(const mbc_plan* p, const void* S_u, const void* S_d, int32_t s_dtype,
                                  int32_t T, int64_t sites_per_t, const double* W, const double* grad_C,
                                  double* grad_W, void* grad_S_u, void* grad_S_d, void* workspace,

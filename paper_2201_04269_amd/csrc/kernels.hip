@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -383,6 +384,31 @@ __global__ void zero_kernel(unsigned long long* p, size_t n) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = 0;
 }
 }  // namespace
+
+// Fixed device scratch for mbc_contract_noalloc: one copy per GPU, held
+// until the process ends.  In host code the array's name is not a device
+// address; scratch_device_ptr() looks the address up once per device with
+// hipGetSymbolAddress (with that device current) and caches it.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_device_ptr(void** out) {
+  constexpr int kMaxDevices = 64;
+  static void* ptrs[kMaxDevices] = {};
+  static std::mutex mu;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (ptrs[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = ptr;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 8;

@@ -36,6 +36,11 @@ hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, i
 hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
                          hipStream_t st);
 
+// Size of the fixed per-device scratch array behind mbc_contract_noalloc,
+// and its device address on the current device (looked up once per device).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+hipError_t scratch_device_ptr(void** out);
+
 // Zero-fills bytes (a multiple of 8) of device memory with a kernel (no
 // memset node when the caller captures the stream).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
