@@ -2,21 +2,26 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
-A step is one pass of the hot path over one batch of synthetic propagators
-resident in HBM: the forward contraction C[t] (eq. 1, per-timeslice sums)
-and, when the library provides it, the backward pass (dC/dW, dC/dS).  The
-index set and plan are built once, outside the timed region (the paper
-amortises its tree construction over configurations the same way).
+A step is one pass of the whole hot path over one batch of synthetic
+propagators resident in HBM: the forward contraction C[t] (eq. 1,
+per-timeslice sums) and the backward pass (dC/dW, then dC/dS).  The index
+set and plan are built once, outside the timed region (the paper amortises
+its tree construction over configurations the same way).
 
 Workloads (synthetic inputs, the paper's propagators are not available):
-  di_mixed   D_I and D_II (R2) mixed as W(c) = c1 W_DI + c2 W_DII, c = (1, 0.5),
-             on the union index set (270400 entries), 16^3 x 32 sites,
-             i.i.d. complex Gaussian propagators (seed 3) [default]
-  di_8       D_I, 8^3 x 16 sites, SU(3) x spin propagators (seed 1)
   he3        3He_I^j and 3He_II^j (R2), j = 0..3, 8 correlators in one launch,
-             32^3 x 64 sites, i.i.d. (seed 4)  [large: ~10 GB of propagators]
+             32^3 x 64 sites, i.i.d. (seed 4), all 64 timeslices resident in
+             HBM (9.7 GB).  A step is one timeslice (32^3 sites, the sites of
+             one C[t]); step i takes timeslice i mod 64.  Beside the steps,
+             the forward over the whole 32^3 x 64 lattice in one launch is
+             timed once per precision.  [default]
   he3_shard  the same operators on one GPU's share of that lattice when it is
              split by timeslice over 8 GPUs: 32^3 x 8 sites (i.i.d., seed 4)
+  di_mixed   D_I and D_II (R2) mixed as W(c) = c1 W_DI + c2 W_DII, c = (1, 0.5),
+             on the union index set (270400 entries), 16^3 x 32 sites,
+             i.i.d. complex Gaussian propagators (seed 3); a step is the whole
+             lattice
+  di_8       D_I, 8^3 x 16 sites, SU(3) x spin propagators (seed 1)
 
 Beside each workload the hadron-block path (Sec. 2 blocks with sink
 momentum projection, Sec. 3 block-level correlators; FP64) is timed on the
@@ -25,9 +30,9 @@ di_mixed also with displaced sources (a second propagator set), under
 "blocks"/"displaced".
 
 Prints one JSON line (rank 0).  `value` is index entries contracted per
-second, sum over correlators of |I_c| times the number of sites, divided by
-the time of one step, for the FP32-compensated path; the FP64 path is timed
-beside it and reported under "fp64".
+second, sum over correlators of |I_c| times the number of sites of a step,
+divided by the time of one step, for the FP32-compensated path; the FP64 path
+is timed beside it and reported under "f64" (forward only for he3).
 """
 import argparse
 import json
@@ -60,7 +65,9 @@ def workload(name):
         ops = [dict(op="HE3_I", snk_spin=j, src_spin=j) for j in range(4)] + \
               [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2") for j in range(4)]
         gen = lambda: synth.iid(T, L ** 3, seed=4)  # noqa: E731
-        desc = "3He_I^j + 3He_II^j (R2), j=0..3, 32^3x64, iid seed 4"
+        desc = ("3He_I^j + 3He_II^j (R2), j=0..3, 8 correlators, 32^3x64 resident (iid seed 4); "
+                "step = one timeslice (32^3 sites)")
+        return dict(name=name, L=L, T=T, ops=ops, gen=gen, desc=desc, step_T=1, fwd_full=True, bwd_precs=("f32c",))
     elif name == "he3_shard":
         L, T = 32, 8
         ops = [dict(op="HE3_I", snk_spin=j, src_spin=j) for j in range(4)] + \
@@ -69,7 +76,8 @@ def workload(name):
         desc = "3He_I^j + 3He_II^j (R2), j=0..3, 32^3x8 (one timeslice shard of 32^3x64), iid seed 4"
     else:
         raise SystemExit(f"unknown workload {name}")
-    return dict(name=name, L=L, T=T, ops=ops, gen=gen, desc=desc)
+    return dict(name=name, L=L, T=T, ops=ops, gen=gen, desc=desc, step_T=T, fwd_full=False,
+                bwd_precs=("f32c", "f64"))
 
 
 def block_corrs(name):
@@ -85,7 +93,7 @@ def block_corrs(name):
             out.append(dict(op=op, sign_mode=mode, moms=[(0, 0, 0), (0, 0, 0)]))
             out.append(dict(op=op, sign_mode=mode, moms=[(1, 0, 0), (-1, 0, 0)]))
         return out
-    if name == "he3_shard":
+    if name in ("he3_shard", "he3"):
         return [dict(op="HE3_I", snk_spin=j, src_spin=j, moms=[(0, 0, 0)] * 3) for j in range(4)] + \
                [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2", moms=[(0, 0, 0)] * 3) for j in range(4)]
     return None
@@ -168,6 +176,7 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
             "tree_vertices": st["tree_vertices"], "dtype": "f64",
             "ms_blocks": ms_b, "ms_contract_tree": ms_tree, "ms_contract_terms": ms_terms,
             "ms_contract_tree_generic": ms_generic,
+            "flops_contract_tree": st["tree_flops_per_t"] * T, "flops_contract_terms": st["contract_flops_per_t"] * T,
             "sites_per_s": T * V / ((ms_b + ms_tree) * 1e-3),
             "roofline": {"bound": "alu", "kernel": "block_g", "achieved": flops_b / (ms_b * 1e-3) / 1e12,
                          "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
@@ -178,8 +187,8 @@ def bench_blocks(api, torch, name, su, sd, L, steps, warmup, corrs=None):
 # e-graph node limits: the dinucleon graphs saturate (about 74 000 e-nodes for
 # the four di_mixed correlators); 3He's do not, and its admitted re-writes cost
 # canonicalisation time without lowering the plan's flops
-EGRAPH_NODE_LIMIT = {"di_mixed": 100000, "he3_shard": 200}
-EGRAPH_MAX_WS = 8 << 30
+EGRAPH_NODE_LIMIT = {"di_mixed": 100000, "he3_shard": 200, "he3": 200}
+EGRAPH_MAX_WS = 48 << 30
 
 
 def bench_egraph(api, torch, bset, blk, steps, warmup, node_limit=1000):
@@ -257,16 +266,37 @@ def _oracle_sites(args):
     return Su.shape[0]
 
 
+def host_cores():
+    """Cores this process may run on (the box's share of the host) and the
+    CPU model name from lscpu."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except Exception:  # pragma: no cover
+        pass
+    return n, model
+
+
 def cpu_baseline(wl, Su, Sd, nnz, budget_s=15.0):
     """Time the FP64 oracle (as it stands) on a bounded sample of sites.
 
     The sample is the first n sites of the workload, n sized so that the run
     takes about budget_s seconds; per site the oracle's forward (determinants
     of every needed submatrix, then the sum over the index set) and its
-    gradients (dW, dS_u, dS_d by cofactors) run, one process per host core.
+    gradients (dW, dS_u, dS_d by cofactors) run, one process per core of the
+    host share this process may use (at most 16, the share of one GPU).
     """
     ops = wl["ops"][:1] if wl["name"] == "di_mixed" else wl["ops"]
-    nproc = min(os.cpu_count() or 1, 16)
+    avail, model = host_cores()
+    nproc = max(1, min(avail, 16))
     flat_u = Su.reshape(-1, 12, 12)
     flat_d = Sd.reshape(-1, 12, 12)
     _oracle_init(ops)
@@ -283,6 +313,7 @@ def cpu_baseline(wl, Su, Sd, nnz, budget_s=15.0):
         done = sum(pool.map(_oracle_sites, chunks, chunksize=1))
         dt = time.perf_counter() - t0
     return {"value": nnz * done / dt, "unit": "index entries/s (fwd+bwd)", "cores": nproc, "kind": "oracle",
+            "host_cores_available": avail, "cpu_model": model,
             "sample": f"oracle forward + gradients over the first {done} sites of this workload ({dt:.1f} s)"}
 
 
@@ -313,11 +344,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="di_mixed")
+    ap.add_argument("--workload", default="he3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precisions", default="f32c,f64")
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--no-blocks", action="store_true")
+    ap.add_argument("--no-full", action="store_true", help="skip the whole-lattice forward launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -350,21 +382,29 @@ def main():
         n1 = nnz
         assert np.array_equal(e["snk_u"][:n1], e["snk_u"][n1:]) and np.array_equal(e["src_d"][:n1], e["src_d"][n1:])
         W = torch.from_numpy(1.0 * w[:n1] + 0.5 * w[n1:]).to(dev)
-    n_sites = T * V
-    entries = float(nnz) * n_sites
+    step_T = wl["step_T"]
+    n_batches = T // step_T
+    sites_step = step_T * V
+    entries = float(nnz) * sites_step
     stream = torch.cuda.current_stream()
     rng = np.random.default_rng(11)
     n_corr = len(iset_ops)
-    gC = torch.from_numpy(rng.standard_normal((n_corr, T)) + 1j * rng.standard_normal((n_corr, T))).to(dev)
-    do_bwd = not args.fwd_only
+    gC = torch.from_numpy(rng.standard_normal((n_corr, step_T)) + 1j * rng.standard_normal((n_corr, step_T))).to(dev)
+
+    def batch(i):
+        t = (i % n_batches) * step_T
+        return su[t:t + step_T], sd[t:t + step_T]
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
     results = {}
+    plans = {}
     for prec in args.precisions.split(","):
+        do_bwd = (not args.fwd_only) and prec in wl["bwd_precs"]
         t0 = time.perf_counter()
         plan = api.Plan(iset, prec)
+        plans[prec] = plan
         st = plan.stats
         print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']}/{st['w_n_tiles']} lds={st['lds_bytes']}/"
               f"{st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} alg fwd={st['alg_flops_per_site']:.3e} "
@@ -374,22 +414,23 @@ def main():
         # one step: forward, then the backward as its two launches (dW, then
         # dS: the work of one contract_backward with both gradients), with
         # HIP events on the launch stream between them
-        def step(marks=None):
+        def step(i, marks=None):
+            bu, bd = batch(i)
             if marks:
                 marks[0].record(stream)
-            api.contract(plan, su, sd, W)
+            api.contract(plan, bu, bd, W)
             if marks:
                 marks[1].record(stream)
             if do_bwd:
-                api.contract_backward(plan, su, sd, W, gC, need_W=True, need_S=False)
+                api.contract_backward(plan, bu, bd, W, gC, need_W=True, need_S=False)
                 if marks:
                     marks[2].record(stream)
-                api.contract_backward(plan, su, sd, W, gC, need_W=False, need_S=True)
+                api.contract_backward(plan, bu, bd, W, gC, need_W=False, need_S=True)
                 if marks:
                     marks[3].record(stream)
 
         for i in range(args.warmup):
-            step()
+            step(i)
             torch.cuda.synchronize()
             print(f"[bench] {prec}: warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
         marks = [[ev() for _ in range(4)] for _ in range(args.steps)]
@@ -398,8 +439,8 @@ def main():
         t_wall = time.perf_counter()
         first.record(stream)
         for i in range(args.steps):
-            step(marks[i])
-            if args.steps > 1 and n_sites * nnz > 1e13:  # long steps: report progress
+            step(i, marks[i])
+            if args.steps > 1 and sites_step * nnz > 1e11:  # long steps: report progress
                 torch.cuda.synchronize()
                 print(f"[bench] {prec}: step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
         last.record(stream)
@@ -412,15 +453,37 @@ def main():
             kern["dS"] = (sum(m[2].elapsed_time(m[3]) for m in marks) / args.steps, st["ds_alg_flops_per_site"])
         dom = max(kern, key=lambda k: kern[k][0])
         r = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall, value=entries / (ms * 1e-3), dominant=dom,
-                 kernels={k: {"ms": v[0], "alg_tflops": v[1] * n_sites / (v[0] * 1e-3) / 1e12,
-                              "frac": v[1] * n_sites / (v[0] * 1e-3) / PEAK[prec]} for k, v in kern.items()},
+                 pass_="fwd+bwd" if do_bwd else "fwd",
+                 kernels={k: {"ms": v[0], "alg_tflops": v[1] * sites_step / (v[0] * 1e-3) / 1e12,
+                              "frac": v[1] * sites_step / (v[0] * 1e-3) / PEAK[prec]} for k, v in kern.items()},
                  fwd_value=entries / (kern["fwd"][0] * 1e-3),
-                 exec_tflops_fwd=st["exec_flops_per_site"] * n_sites / (kern["fwd"][0] * 1e-3) / 1e12)
+                 exec_tflops_fwd=st["exec_flops_per_site"] * sites_step / (kern["fwd"][0] * 1e-3) / 1e12)
         results[prec] = r
         print(f"[bench] {prec}: step {ms:.3f} ms ({entries / (ms * 1e-3):.3e} entries/s) " +
               " ".join(f"{k} {v['ms']:.2f} ms {v['alg_tflops']:.2f} TF" for k, v in r["kernels"].items()),
               file=sys.stderr, flush=True)
-        del plan
+
+    # the forward over the whole lattice in one launch (one timed launch per
+    # precision; the kernel was already run on the steps' batches above)
+    full = None
+    if wl["fwd_full"] and not args.no_full:
+        full = {"steps": 1, "sites": T * V, "T": T}
+        for prec, plan in plans.items():
+            a0, a1 = ev(), ev()
+            torch.cuda.synchronize()
+            print(f"[bench] {prec}: forward over the whole {T}x{V} lattice in one launch ...", file=sys.stderr,
+                  flush=True)
+            a0.record(stream)
+            api.contract(plan, su, sd, W)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            fms = a0.elapsed_time(a1)
+            fl = plan.stats["alg_flops_per_site"] * T * V
+            full[prec] = {"ms": fms, "value": float(nnz) * T * V / (fms * 1e-3), "alg_tflops": fl / (fms * 1e-3) / 1e12,
+                          "frac": fl / (fms * 1e-3) / PEAK[prec]}
+            print(f"[bench] {prec}: whole-lattice forward {fms / 1e3:.2f} s ({full[prec]['value']:.3e} entries/s, "
+                  f"{full[prec]['alg_tflops']:.2f} TF)", file=sys.stderr, flush=True)
+    plans.clear()
 
     head = "f32c" if "f32c" in results else list(results)[0]
     r = results[head]
@@ -438,8 +501,8 @@ def main():
         "vs_baseline": None,
         "dtype": head,
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "pass": "fwd+bwd" if do_bwd else "fwd", "sites": n_sites,
-                   "nnz": nnz, "index_entries_per_step": entries},
+        "config": {"workload": wl["desc"], "pass": r["pass_"], "sites_per_step": sites_step,
+                   "lattice_sites": T * V, "correlators": n_corr, "nnz": nnz, "index_entries_per_step": entries},
         "roofline": {"bound": "alu", "kernel": r["dominant"], "achieved": dk["alg_tflops"],
                      "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": dk["frac"],
                      "traffic": profiled_traffic(wl["name"], r["dominant"], head)},
@@ -455,8 +518,10 @@ def main():
                       "peak_GBps": 8000.0}
     for prec, rr in results.items():
         if prec != head:
-            out[prec] = {"value": rr["value"], "ms_per_step": rr["ms_per_step"], "fwd_only_value": rr["fwd_value"],
-                         "kernels": rr["kernels"]}
+            out[prec] = {"pass": rr["pass_"], "value": rr["value"], "ms_per_step": rr["ms_per_step"],
+                         "fwd_only_value": rr["fwd_value"], "kernels": rr["kernels"]}
+    if full is not None:
+        out["whole_lattice_forward"] = full
     if not args.no_blocks:
         blk = bench_blocks(api, torch, wl["name"], su, sd, wl["L"], args.steps, args.warmup)
         if blk is not None:

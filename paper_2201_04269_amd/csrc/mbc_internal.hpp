@@ -198,9 +198,11 @@ constexpr int ds_threads(int n_u, int n_d, int precision) {
 // Sink keys per tile of the dW schedule, and source keys per thread the dW
 // kernel is built for, per operator family (n_u, n_d) and precision (the
 // kernel keeps keys x source slots compensated accumulators in registers;
-// on the D_I bench workload 2 keys (FP32) and 1 (FP64) measured fastest).
+// on the D_I bench workload 2 keys (FP32) and 1 (FP64) measured fastest; on
+// the 3He batch 4 keys in FP32 (1.20 s per 32^3 timeslice, against 1.75 s
+// with 2 and 1.47 s with 8), 2 in FP64, where 4 spills registers).
 constexpr int dw_keys_per_tile(int n_u, int n_d, int precision) {
-  return n_u + n_d >= 8 ? 2 : (n_u + n_d >= 6 ? (precision == MBC_F64 ? 1 : 2) : 4);
+  return n_u + n_d >= 8 ? (precision == MBC_F64 ? 2 : 4) : (n_u + n_d >= 6 ? (precision == MBC_F64 ? 1 : 2) : 4);
 }
 constexpr int dw_src_per_thread(int n_u, int n_d) { return n_u + n_d >= 8 ? 3 : (n_u + n_d >= 6 ? 3 : 1); }
 
