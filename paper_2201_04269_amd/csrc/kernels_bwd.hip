@@ -226,34 +226,54 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const double* __restrict
 // S-bar partials of a level-K row: bin j collects the columns C that contain
 // j.  Levels K <= 2 have short bins (at most 11 entries): one lane per bin,
 // thread t takes bin t % 12 of row group t / 12 (21 rows side by side).
-// Levels K >= 3: a DPP row of 16 lanes per bin, thread t takes bin t / 16
-// (t < 192) of one row, lane t % 16 holds entries l, l + 16, ...
-__host__ __device__ constexpr int bin_regs(int k) { return k == 1 ? 1 : (k == 2 ? 11 : (k == 3 ? 4 : (k == 4 ? 11 : 14))); }
-__host__ __device__ constexpr int bin_lanes(int k) { return k <= 2 ? 1 : 16; }
+// Levels K >= 3: L = 16 lanes per bin (workgroups of fewer than 384 threads)
+// or 32 (384 threads or more), thread t takes bin t / L (t < 12 L) of one
+// row, lane t % L holds entries l, l + L, ...; 32 lanes halve the entries
+// per lane, so the 3He rows' bins (up to 224 entries) take 7 registers.
+// Level 2 with 384 threads or more: 4 lanes per bin (3 entries each).
+__host__ __device__ constexpr int bin_lanes(int k, int nt) {
+  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 4 : 1) : (nt >= 384 ? 32 : 16));
+}
+__host__ __device__ constexpr int bin_regs(int k, int nt) {
+  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 3 : 11) : (nt >= 384 ? (k == 3 ? 2 : (k == 4 ? 6 : 7)) : (k == 3 ? 4 : (k == 4 ? 11 : 14))));
+}
+
+// Sum over the 4 lanes of each quad (every lane receives the quad's sum).
+__device__ __forceinline__ float quad4_sum(float x) {
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xf, 0xf, false));
+  x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xf, 0xf, false));
+  return x;
+}
+__device__ __forceinline__ double quad4_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  return x;
+}
 
 template <int K, int NT>
 struct BinTab {
-  int e[bin_regs(K)];
+  static constexpr int kRegs = bin_regs(K, NT), kLanes = bin_lanes(K, NT);
+  int e[kRegs];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab, int t) {
     // unused slots read column ncol of the row: its zero element
     const int pad = cr[8 + 2 * (6 * f + K - 1)];
 #pragma unroll
-    for (int m = 0; m < bin_regs(K); ++m) e[m] = pad;
+    for (int m = 0; m < kRegs; ++m) e[m] = pad;
     const int32_t* jl = btab + cr[40 + 6 * f + K - 1];
     int j, l;
-    if constexpr (K <= 2) {
+    if constexpr (kLanes == 1) {
       if (t >= 12 * (NT / 12)) return;
       j = t % 12;
       l = 0;
     } else {
-      if (t >= 192 * (NT / 192)) return;
-      j = (t % 192) >> 4;
-      l = t & 15;
+      if (t >= 12 * kLanes * (NT / (12 * kLanes))) return;
+      j = (t % (12 * kLanes)) / kLanes;
+      l = t % kLanes;
     }
     const int q0 = jl[j], q1 = jl[j + 1];
 #pragma unroll
-    for (int m = 0; m < bin_regs(K); ++m) {
-      const int q = q0 + l + bin_lanes(K) * m;
+    for (int m = 0; m < kRegs; ++m) {
+      const int q = q0 + l + kLanes * m;
       if (q < q1) e[m] = jl[q];
     }
   }
@@ -443,7 +463,7 @@ template <int K, int NT, typename C>
 __device__ __forceinline__ C bin_sum(const BinTab<K, NT>& bt, int4 ov, const C* Sf, const C* sR, const C* sA) {
   C sum = cmake<C>(0, 0);
 #pragma unroll
-  for (int m = 0; m < bin_regs(K); ++m) {
+  for (int m = 0; m < BinTab<K, NT>::kRegs; ++m) {
     const int e = bt.e[m];
     const C av = sA[ov.z + (e & 4095)];
     if constexpr (K == 1) {
@@ -460,31 +480,46 @@ __device__ __forceinline__ C bin_sum(const BinTab<K, NT>& bt, int4 ov, const C* 
 
 // (ii) S-bar partials of the level-K rows [o0, o0 + cnt) of one flavour:
 // part[o][j] = sum over columns C containing j of (-1)^pos A(C) M_{K-1}(C \ j).
-// Levels K <= 2: NT / 12 rows side by side, one lane per bin.  K >= 3:
-// NT / 192 groups of 12 bins x 16 lanes, each taking two rows per trip.
+// One lane per bin (L = 1): NT / 12 rows side by side.  Otherwise NT / (12 L)
+// groups of 12 bins x L lanes, each taking two rows per trip.
 template <int K, int NT, typename C>
 __device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o0, int cnt, const int4* sOpv,
                                          const C* Sf, const C* sR, const C* sA, C* sPart) {
-  if constexpr (K <= 2) {
+  if constexpr (BinTab<K, NT>::kLanes == 1) {
     constexpr int RB = NT / 12;
     if (tid >= 12 * RB) return;
     const int j = tid % 12;
     for (int o = o0 + tid / 12; o < o0 + cnt; o += RB) sPart[12 * o + j] = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
   } else {
-    constexpr int NG = NT / 192;
-    if (tid >= 192 * NG) return;
-    const int lt = tid % 192;
-    for (int o = o0 + 2 * (tid / 192); o < o0 + cnt; o += 2 * NG) {
+    constexpr int L = BinTab<K, NT>::kLanes;
+    constexpr int GW = 12 * L;
+    constexpr int NG = NT / GW;
+    if (tid >= GW * NG) return;
+    const int lt = tid % GW;
+    for (int o = o0 + 2 * (tid / GW); o < o0 + cnt; o += 2 * NG) {
       const bool two = o + 1 < o0 + cnt;
       C s0 = bin_sum<K>(bt, sOpv[o], Sf, sR, sA);
       C s1 = two ? bin_sum<K>(bt, sOpv[o + 1], Sf, sR, sA) : cmake<C>(0, 0);
-      s0.x = row16_sum(s0.x);
-      s0.y = row16_sum(s0.y);
-      s1.x = row16_sum(s1.x);
-      s1.y = row16_sum(s1.y);
-      if ((lt & 15) == 0) {
-        sPart[12 * o + (lt >> 4)] = s0;
-        if (two) sPart[12 * (o + 1) + (lt >> 4)] = s1;
+      if constexpr (L == 4) {
+        s0.x = quad4_sum(s0.x);
+        s0.y = quad4_sum(s0.y);
+        s1.x = quad4_sum(s1.x);
+        s1.y = quad4_sum(s1.y);
+      } else {
+        s0.x = row16_sum(s0.x);
+        s0.y = row16_sum(s0.y);
+        s1.x = row16_sum(s1.x);
+        s1.y = row16_sum(s1.y);
+      }
+      if constexpr (L == 32) {  // the two 16-lane rows of a bin (aligned halves of the wave)
+        s0.x += __shfl_xor(s0.x, 16);
+        s0.y += __shfl_xor(s0.y, 16);
+        s1.x += __shfl_xor(s1.x, 16);
+        s1.y += __shfl_xor(s1.y, 16);
+      }
+      if (lt % L == 0) {
+        sPart[12 * o + lt / L] = s0;
+        if (two) sPart[12 * (o + 1) + lt / L] = s1;
       }
     }
   }
@@ -775,9 +810,9 @@ hipError_t launch_dw_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, 
   return hipErrorNotSupported;
 }
 
-bool bins_fit(const PlanHost& h) {
+bool bins_fit(const PlanHost& h, int nt) {
   for (int k = 1; k <= 5; ++k)
-    if (h.max_bin[k] > bin_lanes(k) * bin_regs(k)) return false;
+    if (h.max_bin[k] > bin_lanes(k, nt) * bin_regs(k, nt)) return false;
   return h.max_bin[6] == 0;
 }
 
@@ -792,7 +827,7 @@ hipError_t launch_ds_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, 
 template <typename R>
 hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
   const int nu = p->h.n_u, nd = p->h.n_d;
-  if (!bins_fit(p->h)) return hipErrorNotSupported;
+  if (!bins_fit(p->h, ds_threads(nu, nd, p->h.precision))) return hipErrorNotSupported;
   // instantiated for at most MAXCOL columns per level and MC source keys per top column
   if (nu == 2 && nd == 1) return launch_ds_f<R, 2, 1, 256, 2>(p, a, nb, lds, st);
   if (nu == 1 && nd == 2) return launch_ds_f<R, 1, 2, 256, 2>(p, a, nb, lds, st);
@@ -819,7 +854,7 @@ bool backward_supports(const PlanHost& h, std::string* why) {
   }
   // dS: columns per level, source keys per top column, j-list bins
   const int maxcol = nu + nd >= 8 ? 512 : 256, mc = nu + nd >= 8 ? 10 : (nu + nd >= 6 ? 6 : 2);
-  if (h.max_ncol > maxcol || h.max_csr > mc || !bins_fit(h)) {
+  if (h.max_ncol > maxcol || h.max_csr > mc || !bins_fit(h, ds_threads(nu, nd, h.precision))) {
     *why = "the dS kernel is not instantiated for this plan's columns, source-key lists or j-lists";
     return false;
   }

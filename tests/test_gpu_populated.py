@@ -181,10 +181,13 @@ def test_helium3_batch_gradients_32x32x32x8_every_site(prec):
     Su, Sd = synth.iid(T, L ** 3, seed=g["seed"])
     plan = api.Plan(api.IndexSet(HE3), prec)
     gC = _c(g["gC"])
-    print(f"3He batch backward {prec} on 32^3x8: launching", flush=True)
-    gW, gSu, gSd = api.contract_backward(plan, torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda(), None,
-                                         torch.from_numpy(gC).cuda())
-    gW, gSu, gSd = gW.cpu().numpy(), gSu.cpu().numpy(), gSd.cpu().numpy()
+    su, sd, gc = torch.from_numpy(Su).cuda(), torch.from_numpy(Sd).cuda(), torch.from_numpy(gC).cuda()
+    print(f"3He batch backward {prec} on 32^3x8: grad_W", flush=True)
+    gW, _, _ = api.contract_backward(plan, su, sd, None, gc, need_W=True, need_S=False)
+    gW = gW.cpu().numpy()
+    print(f"3He batch backward {prec} on 32^3x8: grad_S", flush=True)
+    _, gSu, gSd = api.contract_backward(plan, su, sd, None, gc, need_W=False, need_S=True)
+    gSu, gSd = gSu.cpu().numpy(), gSd.cpu().numpy()
     ent = np.asarray(g["entries"])
     ref, scl = _c(g["gW"]), np.asarray(g["sW"])
     err = np.abs(gW[ent] - ref)
