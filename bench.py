@@ -406,7 +406,8 @@ def main():
         plan = api.Plan(iset, prec)
         plans[prec] = plan
         st = plan.stats
-        print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']}/{st['w_n_tiles']} lds={st['lds_bytes']}/"
+        print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']}/{st['w_n_tiles']} "
+              f"factored dS tiles={st['f_n_tiles'] if st['rank1'] else None} lds={st['lds_bytes']}/"
               f"{st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} alg fwd={st['alg_flops_per_site']:.3e} "
               f"dS={st['ds_alg_flops_per_site']:.3e} dW={st['dw_alg_flops_per_site']:.3e} "
               f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)

@@ -136,6 +136,12 @@ typedef struct {
   double ds_alg_flops_per_site; /* dS: minors + reverse sweep (16k per level-k minor) + 16 per entry */
   double dw_alg_flops_per_site; /* dW: minors + 8 per entry */
   int32_t w_n_tiles;            /* tiles of the dW schedule */
+  int32_t rank1;                /* 1: every correlator's exact weights are a sink vector times a
+                                   source vector; for every family but the (3,3) one in
+                                   FP32-comp, mbc_contract_backward with W = NULL then runs the
+                                   dS schedule that stages those factors instead of the weights */
+  int32_t f_n_tiles;            /* tiles of that factored dS schedule */
+  int64_t f_lds_bytes_ds;       /* dynamic LDS per workgroup of the factored dS kernel */
 } mbc_plan_stats;
 mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out);
 

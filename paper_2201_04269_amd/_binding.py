@@ -37,7 +37,8 @@ class PlanStats(ctypes.Structure):
                 ("in_bytes_per_site", ctypes.c_double), ("b_n_tiles", ctypes.c_int32),
                 ("b_lds_bytes_ds", ctypes.c_int64), ("b_lds_bytes_dw", ctypes.c_int64),
                 ("ds_alg_flops_per_site", ctypes.c_double), ("dw_alg_flops_per_site", ctypes.c_double),
-                ("w_n_tiles", ctypes.c_int32)]
+                ("w_n_tiles", ctypes.c_int32), ("rank1", ctypes.c_int32), ("f_n_tiles", ctypes.c_int32),
+                ("f_lds_bytes_ds", ctypes.c_int64)]
 
 
 class BlockCorrDesc(ctypes.Structure):

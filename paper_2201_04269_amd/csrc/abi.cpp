@@ -103,7 +103,8 @@ mbc_status upload(const std::vector<T>& v, T** out, hipStream_t st) {
 
 void free_device(PlanDevice& d) {
   void* ptrs[] = {d.corr,    d.tiles,   d.ops,   d.meta,    d.src_cu, d.src_cd,  d.tabs,   d.perm,
-                  d.w_exact, d.b_tiles, d.b_ops, d.b_meta, d.b_extra, d.btab, d.w_tiles, d.w_ops, d.w_meta};
+                  d.w_exact, d.b_tiles, d.b_ops, d.b_meta, d.b_extra, d.btab, d.w_tiles, d.w_ops, d.w_meta,
+                  d.f_tiles, d.f_ops, d.f_meta, d.f_extra, d.wu, d.wv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   d = PlanDevice();
@@ -258,20 +259,31 @@ mbc_status mbc_plan_create(const mbc_index_set* s, int32_t precision, void* stre
         (st = upload(h.b_ops, &p->d.b_ops, hs)) != MBC_OK || (st = upload(h.b_meta, &p->d.b_meta, hs)) != MBC_OK ||
         (st = upload(h.b_extra, &p->d.b_extra, hs)) != MBC_OK || (st = upload(h.btab, &p->d.btab, hs)) != MBC_OK ||
         (st = upload(h.w_tiles, &p->d.w_tiles, hs)) != MBC_OK || (st = upload(h.w_ops, &p->d.w_ops, hs)) != MBC_OK ||
-        (st = upload(h.w_meta, &p->d.w_meta, hs)) != MBC_OK) {
+        (st = upload(h.w_meta, &p->d.w_meta, hs)) != MBC_OK ||
+        (st = upload(h.f_tiles, &p->d.f_tiles, hs)) != MBC_OK || (st = upload(h.f_ops, &p->d.f_ops, hs)) != MBC_OK ||
+        (st = upload(h.f_meta, &p->d.f_meta, hs)) != MBC_OK || (st = upload(h.f_extra, &p->d.f_extra, hs)) != MBC_OK) {
       free_device(p->d);
       delete p;
       return st;
     }
+    // exact weights and their sink and source factors, in the plan's precision
+    std::vector<float> wuf, wvf;
     if (h.precision == MBC_F64) {
-      double* w = nullptr;
-      st = upload(h.w_exact, &w, hs);
+      double *w = nullptr, *u = nullptr, *v = nullptr;
+      if ((st = upload(h.w_exact, &w, hs)) == MBC_OK && (st = upload(h.wu, &u, hs)) == MBC_OK)
+        st = upload(h.wv, &v, hs);
       p->d.w_exact = w;
+      p->d.wu = u;
+      p->d.wv = v;
     } else {
       wf.assign(h.w_exact.begin(), h.w_exact.end());
-      float* w = nullptr;
-      st = upload(wf, &w, hs);
+      wuf.assign(h.wu.begin(), h.wu.end());
+      wvf.assign(h.wv.begin(), h.wv.end());
+      float *w = nullptr, *u = nullptr, *v = nullptr;
+      if ((st = upload(wf, &w, hs)) == MBC_OK && (st = upload(wuf, &u, hs)) == MBC_OK) st = upload(wvf, &v, hs);
       p->d.w_exact = w;
+      p->d.wu = u;
+      p->d.wv = v;
     }
     hipError_t e = hipStreamSynchronize(hs);
     if (st == MBC_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
@@ -308,6 +320,9 @@ mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out) {
   out->ds_alg_flops_per_site = p->h.ds_alg_flops_per_site;
   out->dw_alg_flops_per_site = p->h.dw_alg_flops_per_site;
   out->w_n_tiles = p->h.w_n_tiles;
+  out->rank1 = p->h.rank1 ? 1 : 0;
+  out->f_n_tiles = p->h.f_n_tiles;
+  out->f_lds_bytes_ds = p->h.f_lds_ds;
   return MBC_OK;
 }
 
@@ -440,7 +455,10 @@ mbc_status mbc_contract_backward(const mbc_plan* p, const void* S_u, const void*
       if (grad_S_u) MBC_HIP(launch_zero(grad_S_u, bytes, hs));
       if (grad_S_d) MBC_HIP(launch_zero(grad_S_d, bytes, hs));
     } else {
-      MBC_HIP(launch_backward_ds(p, S_u, S_d, s_c64, T, sites_per_t, W_plan, grad_C, grad_S_u, grad_S_d, hs));
+      // the plan's exact weights as a product of factors: the factored tiling
+      const bool factored = (W == nullptr) && p->h.rank1 && ds_factored(p->h.n_u, p->h.n_d, p->h.precision);
+      MBC_HIP(launch_backward_ds(p, S_u, S_d, s_c64, T, sites_per_t, W_plan, grad_C, grad_S_u, grad_S_d, factored,
+                                 hs));
     }
   }
   return MBC_OK;

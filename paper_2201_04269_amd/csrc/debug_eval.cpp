@@ -93,6 +93,9 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
     stats->w_n_tiles = h.w_n_tiles;
     stats->ds_alg_flops_per_site = h.ds_alg_flops_per_site;
     stats->dw_alg_flops_per_site = h.dw_alg_flops_per_site;
+    stats->rank1 = h.rank1 ? 1 : 0;
+    stats->f_n_tiles = h.f_n_tiles;
+    stats->f_lds_bytes_ds = h.f_lds_ds;
   }
   return MBC_OK;
 }
@@ -111,20 +114,33 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
   std::vector<cd> gW(size_t(h.nnz), cd(0, 0));
   const int nS = 2 * 144;
   std::vector<cd> S(nS), R, A, part, adj1, Sbar(size_t(T) * V * nS, cd(0, 0));
-  for (int tile = 0; tile < h.b_n_tiles; ++tile) {
-    const int32_t* tr = &h.b_tiles[size_t(tile) * kTileInts];
+  // the exact weights go through the factored dS tiling, as mbc_contract_backward does
+  const bool fact = (W == nullptr) && h.rank1 && ds_factored(h.n_u, h.n_d, h.precision);
+  const std::vector<int32_t>& btiles = fact ? h.f_tiles : h.b_tiles;
+  const std::vector<int32_t>& bops = fact ? h.f_ops : h.b_ops;
+  const std::vector<int32_t>& bmeta = fact ? h.f_meta : h.b_meta;
+  const std::vector<int32_t>& bextra = fact ? h.f_extra : h.b_extra;
+  const int bn_tiles = fact ? h.f_n_tiles : h.b_n_tiles;
+  for (int tile = 0; tile < bn_tiles; ++tile) {
+    const int32_t* tr = &btiles[size_t(tile) * kTileInts];
     const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], meta0 = tr[5], units = tr[6];
     const int nreal = tr[17], nvirt = tr[18];
     const int32_t* cr = &h.corr[size_t(corr) * kCorrInts];
     const int n_src = cr[0], src_off = cr[1];
     const int nf[2] = {h.n_u, h.n_d};
-    const int32_t* ex = &h.b_extra[size_t(tr[19])];
+    const int32_t* ex = &bextra[size_t(tr[19])];
     const int n_runs = ex[0], n_dg = ex[1];
     const int32_t* runs = ex + 3;
     const int32_t* dgs = runs + 3 * n_runs;
     const int32_t* child = dgs + 2 * n_dg;
-    auto op = [&](int o) { return &h.b_ops[size_t(op0 + o) * kOpInts]; };
-    auto metab = [&](int b) { return &h.b_meta[size_t(meta0 + b) * kMetaInts]; };
+    auto op = [&](int o) { return &bops[size_t(op0 + o) * kOpInts]; };
+    auto metab = [&](int b) { return &bmeta[size_t(meta0 + b) * kMetaInts]; };
+    // W[b, s] of the tile's key b: the weight, or the product of its factors
+    auto weight = [&](int b, int sidx) {
+      if (!fact) return Wp[size_t(w_off) + size_t(b) * n_src + sidx];
+      const size_t iu = size_t(cr[32] + tr[16] + b), iv = size_t(src_off + sidx);
+      return cd(h.wu[2 * iu], h.wu[2 * iu + 1]) * cd(h.wv[2 * iv], h.wv[2 * iv + 1]);
+    };
     R.assign(size_t(units), cd(0, 0));
     A.assign(size_t(units), cd(0, 0));
     for (int t = 0; t < T; ++t) {
@@ -167,7 +183,7 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
             for (int q = csru[c]; q < csru[c + 1]; ++q) {
               const int sidx = csru[q];
               for (int b = b0; b < b1; ++b)
-                sum += Wp[size_t(w_off) + size_t(b) * n_src + sidx] * R[metab(b)[1] + h.src_cd[src_off + sidx]];
+                sum += weight(b, sidx) * R[metab(b)[1] + h.src_cd[src_off + sidx]];
             }
             A[us + c] = gbar * sum;
           }
@@ -180,7 +196,7 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
               const int sidx = csrd[q];
               for (int b = 0; b < B; ++b)
                 if (mask & (1 << b))
-                  sum += Wp[size_t(w_off) + size_t(b) * n_src + sidx] * R[metab(b)[0] + h.src_cu[src_off + sidx]];
+                  sum += weight(b, sidx) * R[metab(b)[0] + h.src_cu[src_off + sidx]];
             }
             A[ds + c] = gbar * sum;
           }

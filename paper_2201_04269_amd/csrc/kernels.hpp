@@ -51,9 +51,11 @@ Launch backward_dw_launch_shape(const PlanHost& h, int T, int64_t V);
 hipError_t launch_backward_dw(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64, const Launch& L,
                               const void* W_plan, const double* grad_C, double* partial, double* grad_W,
                               hipStream_t st);
+// factored: the plan's exact weights through their sink and source factors
+// (requires h.rank1), on the factored dS tiling; otherwise W_plan.
 hipError_t launch_backward_ds(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64, int T, int64_t V,
                               const void* W_plan, const double* grad_C, void* grad_S_u, void* grad_S_d,
-                              hipStream_t st);
+                              bool factored, hipStream_t st);
 
 // Hadron blocks: per timeslice and block type, chunks of nch sites; the
 // partial G matrices of the chunks live in the workspace.

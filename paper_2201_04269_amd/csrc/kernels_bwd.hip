@@ -54,6 +54,8 @@ struct BwdArgs {
   int chunk, nc;
   double* partial;  // dW partials [T * nc][nnz][2] (plan order)
   int64_t nnz;
+  const void* wu;   // factored dS: sink and source factors of the exact weights
+  const void* wv;
 };
 
 // Rows of one site for one tile (no propagator prefetch): one barrier per level.
@@ -378,10 +380,32 @@ struct CsrTab {
 // first NM entries (s, oc) of the column's source-key list of
 // W[b, s] * (other flavour's top minor at b's row slot, column oc).  The u
 // leaves take the run [lo, hi) and the d slots of its keys; the d leaves take
-// the sink keys in the bit mask lo and their u slots.
-template <int NM, int MC, bool MASK, typename C>
+// the sink keys in the bit mask lo and their u slots.  FACT: W[b, s] =
+// u[b] v[s] with v = sW[0, n_src) and u = sW[n_src, n_src + B) (the tile's
+// keys), summed as sum_s v[s] (sum_b u[b] minor_b).
+template <int NM, int MC, bool MASK, bool FACT, typename C>
 __device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, const C* sW, int n_src, const C* sR,
                                         const int2* sMeta) {
+  if constexpr (FACT) {
+    const C* sU = sW + n_src;
+    C sum = cmake<C>(0, 0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int sidx = e[m] & 2047, oc = e[m] >> 11;
+      C t = cmake<C>(0, 0);
+      auto key = [&](int b) {
+        const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
+        t = cmac(sU[b], orow[oc], t);
+      };
+      if constexpr (MASK) {
+        for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
+      } else {
+        for (int b = lo; b < hi; ++b) key(b);
+      }
+      sum = cmac(sW[sidx], t, sum);
+    }
+    return sum;
+  }
   C sum = cmake<C>(0, 0);
   int sidx[NM], oc[NM];
 #pragma unroll
@@ -405,14 +429,14 @@ __device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, cons
 
 // Dispatch on the wave's longest list (nw, uniform), in steps of two entries;
 // the padded entries of shorter lists contribute zero.
-template <int N, int MC, bool MASK, typename C>
+template <int N, int MC, bool MASK, bool FACT, typename C>
 __device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
                                       const C* sR, const int2* sMeta) {
   if constexpr (N >= MC) {
-    return leaf_terms<MC, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
+    return leaf_terms<MC, MC, MASK, FACT>(e, lo, hi, sW, n_src, sR, sMeta);
   } else {
-    if (nw <= N) return leaf_terms<N, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
-    return leaf_sum<N + 2, MC, MASK>(nw, e, lo, hi, sW, n_src, sR, sMeta);
+    if (nw <= N) return leaf_terms<N, MC, MASK, FACT>(e, lo, hi, sW, n_src, sR, sMeta);
+    return leaf_sum<N + 2, MC, MASK, FACT>(nw, e, lo, hi, sW, n_src, sR, sMeta);
   }
 }
 
@@ -596,7 +620,7 @@ __device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX, NT>& ru, cons
   }
 }
 
-template <typename R, int NU, int ND, int QMAX, int MC, int NT>
+template <typename R, int NU, int ND, int QMAX, int MC, int NT, bool FACT>
 __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
@@ -645,8 +669,8 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
     C gbar;
     gbar.x = R(a.grad_C[2 * (int64_t(corr) * a.T + t)]);
     gbar.y = R(-a.grad_C[2 * (int64_t(corr) * a.T + t) + 1]);
-    C* sW = sS + 288;
-    C* sR = sW + B * n_src;
+    C* sW = sS + 288;  // W (B x n_src), or FACT: the factors v (n_src) and u (B)
+    C* sR = sW + (FACT ? n_src + B : B * n_src);
     C* sA = sR + units;
     C* sAdj1 = sA + units;
     C* sPart = sAdj1 + 12 * nvirt;
@@ -656,7 +680,12 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
     int32_t* sEx = reinterpret_cast<int32_t*>(sOpv + nops);
     int2* sMeta = reinterpret_cast<int2*>(sEx + ((ex_len + 1) & ~1));  // (u slot, d slot) of each sink key
     __syncthreads();  // the previous tile's LDS is no longer read
-    stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+    if constexpr (FACT) {
+      stage_lds<NT>(sW, reinterpret_cast<const C*>(a.wv) + cr[1], n_src);
+      if (tid < B) sW[n_src + tid] = reinterpret_cast<const C*>(a.wu)[cr[32] + tr[16] + tid];
+    } else {
+      stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+    }
     if (tid < B) {
       const int4 mb = meta_all[meta0 + tid];
       sMeta[tid] = make_int2(mb.x, mb.y);
@@ -690,7 +719,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_u + NT * q;
           if (c < cu_tab.ncol) {
-            const C sum = leaf_sum<2, MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<2, MC, false, FACT>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
           }
         }
@@ -701,7 +730,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_d + NT * q;
           if (c < cd_tab.ncol) {
-            const C sum = leaf_sum<2, MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<2, MC, true, FACT>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
           }
         }
@@ -778,6 +807,8 @@ BwdArgs make_args(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64
   a.grad_S_u = nullptr;
   a.grad_S_d = nullptr;
   a.partial = nullptr;
+  a.wu = p->d.wu;
+  a.wv = p->d.wv;
   return a;
 }
 
@@ -817,22 +848,23 @@ bool bins_fit(const PlanHost& h, int nt) {
 }
 
 template <typename R, int NU, int ND, int MAXCOL, int MC>
-hipError_t launch_ds_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
+hipError_t launch_ds_f(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, bool factored, hipStream_t st) {
   constexpr int NT = ds_threads(NU, ND, std::is_same<R, double>::value ? MBC_F64 : MBC_F32C);
   constexpr int QMAX = (MAXCOL + NT - 1) / NT;
   if (p->h.max_ncol > MAXCOL || p->h.max_csr > MC) return hipErrorNotSupported;
-  return launch_k(ds_kernel<R, NU, ND, QMAX, MC, NT>, NT, nb, lds, st, a);
+  if (factored) return launch_k(ds_kernel<R, NU, ND, QMAX, MC, NT, true>, NT, nb, lds, st, a);
+  return launch_k(ds_kernel<R, NU, ND, QMAX, MC, NT, false>, NT, nb, lds, st, a);
 }
 
 template <typename R>
-hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, hipStream_t st) {
+hipError_t launch_ds_r(const mbc_plan* p, const BwdArgs& a, int nb, size_t lds, bool factored, hipStream_t st) {
   const int nu = p->h.n_u, nd = p->h.n_d;
   if (!bins_fit(p->h, ds_threads(nu, nd, p->h.precision))) return hipErrorNotSupported;
   // instantiated for at most MAXCOL columns per level and MC source keys per top column
-  if (nu == 2 && nd == 1) return launch_ds_f<R, 2, 1, 256, 2>(p, a, nb, lds, st);
-  if (nu == 1 && nd == 2) return launch_ds_f<R, 1, 2, 256, 2>(p, a, nb, lds, st);
-  if (nu == 3 && nd == 3) return launch_ds_f<R, 3, 3, 256, 6>(p, a, nb, lds, st);
-  if (nu == 5 && nd == 4) return launch_ds_f<R, 5, 4, 512, 10>(p, a, nb, lds, st);
+  if (nu == 2 && nd == 1) return launch_ds_f<R, 2, 1, 256, 2>(p, a, nb, lds, factored, st);
+  if (nu == 1 && nd == 2) return launch_ds_f<R, 1, 2, 256, 2>(p, a, nb, lds, factored, st);
+  if (nu == 3 && nd == 3) return launch_ds_f<R, 3, 3, 256, 6>(p, a, nb, lds, factored, st);
+  if (nu == 5 && nd == 4) return launch_ds_f<R, 5, 4, 512, 10>(p, a, nb, lds, factored, st);
   return hipErrorNotSupported;
 }
 
@@ -901,7 +933,7 @@ hipError_t launch_backward_dw(const mbc_plan* p, const void* S_u, const void* S_
 
 hipError_t launch_backward_ds(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64, int T, int64_t V,
                               const void* W_plan, const double* grad_C, void* grad_S_u, void* grad_S_d,
-                              hipStream_t st) {
+                              bool factored, hipStream_t st) {
   Launch L;
   L.T = T;
   L.V = V;
@@ -909,11 +941,20 @@ hipError_t launch_backward_ds(const mbc_plan* p, const void* S_u, const void* S_
   a.grad_C = grad_C;
   a.grad_S_u = grad_S_u;
   a.grad_S_d = grad_S_d;
+  factored = factored && p->h.rank1;
+  size_t lds = size_t(p->h.b_lds_ds);
+  if (factored) {
+    a.tiles = p->d.f_tiles;
+    a.ops = p->d.f_ops;
+    a.meta = p->d.f_meta;
+    a.extra = p->d.f_extra;
+    a.n_tiles = p->h.f_n_tiles;
+    lds = size_t(p->h.f_lds_ds);
+  }
   const int64_t nb = int64_t(T) * V;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t lds = size_t(p->h.b_lds_ds);
-  if (p->h.precision == MBC_F64) return launch_ds_r<double>(p, a, int(nb), lds, st);
-  return launch_ds_r<float>(p, a, int(nb), lds, st);
+  if (p->h.precision == MBC_F64) return launch_ds_r<double>(p, a, int(nb), lds, factored, st);
+  return launch_ds_r<float>(p, a, int(nb), lds, factored, st);
 }
 
 }  // namespace mbc

@@ -148,6 +148,10 @@ bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64
 //                     0xffff if C' + {j} is not a needed column
 //   [80 + f]          longest source-key list of a top column of flavour f
 //   [82 + 6*f + k-1]  longest j-list of level k
+//   [32] snk_vec_off  offset of the correlator's sink keys (plan order) in
+//                     the sink factor wu; the source factor wv is indexed by
+//                     src_off + s like src_cu / src_cd
+//   [33] ftile_begin [34] ftile_end   tiles of the factored dS tiling
 // Column table of level k >= 2: ncol*k uint16 entries (sub << 4) | col, the k
 //   terms of the expansion along the first row; col = C_j, sub = index of
 //   C \ C_j in level k-1 (for k = 2: the remaining column number itself).
@@ -174,10 +178,15 @@ bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64
 //   (virtual = a level-1 parent standing for S row r0: out = 12 * its index
 //   in the tile's level-1 adjoint rows).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
-// Three tilings of the sink keys per plan: the forward's (tiles/ops/meta),
+// Four tilings of the sink keys per plan: the forward's (tiles/ops/meta),
 // the dS kernel's (b_*: backward records, every row slot followed by one
-// zero element that padded table entries point at) and the dW kernel's
-// (w_*: forward-style records, at most dw_keys_per_tile keys per tile).
+// zero element that padded table entries point at), the dW kernel's
+// (w_*: forward-style records, at most dw_keys_per_tile keys per tile), and,
+// when every correlator's exact weights are a product W[b, s] = wu[b] wv[s]
+// (a sink vector times a source vector, as a single operator's
+// sigma s^2 w_r conj(w_c) is), the factored dS tiling (f_*: backward
+// records whose tiles stage the n_src + B factors instead of the B x n_src
+// weights, so that more sink keys share a tile's rows).
 // ---------------------------------------------------------------------------
 constexpr int kCorrInts = 96;
 constexpr int kTileInts = 48;
@@ -193,6 +202,16 @@ constexpr int family_threads(int n_u, int n_d) { return n_u + n_d >= 8 ? 512 : 2
 // spill to scratch memory).
 constexpr int ds_threads(int n_u, int n_d, int precision) {
   return (n_u + n_d >= 8 && precision == MBC_F64) ? 256 : family_threads(n_u, n_d);
+}
+
+// Whether the dS kernel of a family and precision takes the factored
+// schedule for the exact weights (when they factor): measured faster for the
+// 3He batch (FP32-comp 4.92 -> 4.24 s per 32^3 timeslice) and the FP64
+// dinucleon (594 -> 524 ms on 16^3 x 32), slower for the FP32-comp dinucleon
+// (312 -> 331 ms), whose factored leaf sums read the factors once per key
+// and source slot instead of one weight.
+constexpr bool ds_factored(int n_u, int n_d, int precision) {
+  return !(n_u + n_d == 6 && precision == MBC_F32C);
 }
 
 // Sink keys per tile of the dW schedule, and source keys per thread the dW
@@ -227,6 +246,12 @@ struct PlanHost {
   std::vector<int32_t> w_tiles, w_ops, w_meta;
   int max_csr = 0;       // longest source-key list of a top column
   int max_bin[7] = {0, 0, 0, 0, 0, 0, 0};  // longest j-list per level
+  // factored dS tiling (used for the exact weights when rank1)
+  bool rank1 = false;
+  int f_n_tiles = 0, f_max_ops = 0, f_max_b = 0;
+  int64_t f_lds_ds = 0;
+  std::vector<int32_t> f_tiles, f_ops, f_meta, f_extra;
+  std::vector<double> wu, wv;     // (re, im): sink factor [sum n_snk], source factor [sum n_src]
   std::vector<uint16_t> tabs;
   std::vector<int64_t> perm;      // plan-ordered W slot -> index-set entry
   std::vector<double> w_exact;    // plan-ordered exact W (re, im)
@@ -255,6 +280,12 @@ struct PlanDevice {
   int32_t* w_tiles = nullptr;
   int32_t* w_ops = nullptr;
   int32_t* w_meta = nullptr;
+  int32_t* f_tiles = nullptr;
+  int32_t* f_ops = nullptr;
+  int32_t* f_meta = nullptr;
+  int32_t* f_extra = nullptr;
+  void* wu = nullptr;  // plan precision complex
+  void* wv = nullptr;
 };
 
 // Block plan: per block type the non-zero entries of its Gamma and its

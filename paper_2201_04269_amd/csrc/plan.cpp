@@ -144,15 +144,18 @@ struct TileSetOut {
 struct LdsModel {
   bool backward;  // dS kernel (rows carry a zero element, adjoint rows)
   int csz;
-  bool with_w = true;  // forward: the tile's weights are staged (not for dW)
+  bool with_w = true;     // forward: the tile's weights are staged (not for dW)
+  bool factored = false;  // dS: the n_src + B weight factors instead of B x n_src weights
+  int64_t weights(int B, int n_src) const { return factored ? int64_t(n_src) + B : int64_t(B) * n_src; }
   int64_t operator()(int B, int n_src, int64_t row_units, int n_ops, int n_virt, int64_t n_child) const {
     if (!backward) {
       int64_t bytes = (576 + (with_w ? int64_t(B) * n_src : 0) + row_units) * csz;
       return ((bytes + 15) & ~int64_t(15)) + int64_t(n_ops) * 16 + int64_t(B) * 16;
     }
-    // dS kernel: S, W, rows, adjoint rows, level-1 adjoints, per-op j-partials,
-    // S-bar accumulators (16 B each), staged op records and child lists
-    const int64_t ds = (288 + int64_t(B) * n_src + 2 * row_units + 12 * int64_t(n_virt) + 12 * int64_t(n_ops)) * csz +
+    // dS kernel: S, W (or its factors), rows, adjoint rows, level-1 adjoints,
+    // per-op j-partials, S-bar accumulators (16 B each), staged op records
+    // and child lists
+    const int64_t ds = (288 + weights(B, n_src) + 2 * row_units + 12 * int64_t(n_virt) + 12 * int64_t(n_ops)) * csz +
                        288 * 16 + int64_t(n_ops + n_virt) * 32 + n_child * 4 + 64 * 4;
     return ds;
   }
@@ -354,7 +357,7 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
       // S-bar partials (complex, rounded up to 16 B), then int4 op records
       // (real ops; all ops twice), the extra ints (rounded up to 8 B) and the
       // (u slot, d slot) pairs of the sink keys
-      int64_t cunits = 288 + int64_t(B) * X.n_src + 2 * int64_t(units) + 12 * int64_t(nv) + 12 * int64_t(n_ops);
+      int64_t cunits = 288 + m.weights(B, X.n_src) + 2 * int64_t(units) + 12 * int64_t(nv) + 12 * int64_t(n_ops);
       int64_t bytes = cunits * m.csz;
       bytes = (bytes + 15) & ~int64_t(15);
       lds = bytes + int64_t(n_ops + 2 * (n_ops + nv)) * 16 + ((ex_len + 1) & ~int64_t(1)) * 4 + int64_t(B) * 8;
@@ -508,6 +511,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   const int64_t bbudget = big ? 150 * 1024 : (precision == MBC_F64 ? 76 : 78) * 1024;
   const int kMaxB = 16;
   const LdsModel fwd_model{false, csz}, bwd_model{true, csz}, dw_model{false, csz, false};
+  const LdsModel bwdf_model{true, csz, true, true};
+  P.rank1 = true;
   const int dw_keys = dw_keys_per_tile(s.n_u, s.n_d, precision);
   P.corr.assign(size_t(s.n_corr) * kCorrInts, 0);
   P.w_exact.assign(size_t(2 * P.nnz), 0.0);
@@ -517,6 +522,7 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   TileSetOut fo{&P.tiles, &P.ops, &P.meta, nullptr, &P.n_tiles, &P.max_ops, &P.max_b, &exec};
   TileSetOut bo{&P.b_tiles, &P.b_ops, &P.b_meta, &P.b_extra, &P.b_n_tiles, &P.b_max_ops, &P.b_max_b, nullptr};
   TileSetOut wo{&P.w_tiles, &P.w_ops, &P.w_meta, nullptr, &P.w_n_tiles, &P.w_max_ops, &P.w_max_b, nullptr};
+  TileSetOut fo2{&P.f_tiles, &P.f_ops, &P.f_meta, &P.f_extra, &P.f_n_tiles, &P.f_max_ops, &P.f_max_b, nullptr};
 
   for (int c = 0; c < s.n_corr; ++c) {
     int32_t* cr = &P.corr[size_t(c) * kCorrInts];
@@ -526,6 +532,8 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     cr[5] = int32_t(e0);
     cr[66] = int32_t(w_pos);
     cr[1] = int32_t(P.src_cu.size());
+    cr[32] = int32_t(P.wu.size() / 2);
+    cr[33] = cr[34] = P.f_n_tiles;
     if (e0 == e1) continue;  // empty correlator: C = 0, no tiles
     CorrCtx X;
     X.c = c;
@@ -568,6 +576,57 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
         P.w_exact[size_t(2 * w_pos + 1)] = double(s.entries[e].w_im) / den;
         ++w_pos;
       }
+    // Exact weights as a product of a sink and a source vector: with the
+    // pivot (0, j0) (j0 the largest weight of sink key 0), W is a product iff
+    // W[i, j] W[0, j0] = W[i, j0] W[0, j] for every entry (checked in exact
+    // Gaussian-integer arithmetic on the numerators); then
+    // wu[i] = W[i, j0] and wv[j] = W[0, j] / W[0, j0].
+    {
+      auto num = [&](int i, int j) {
+        const Entry& en = s.entries[ent[size_t(i) * X.n_src + j]];
+        return std::make_pair(en.w_re, en.w_im);
+      };
+      int j0 = 0;
+      __int128 best = -1;
+      for (int j = 0; j < X.n_src; ++j) {
+        const auto w = num(0, j);
+        const __int128 n2 = __int128(w.first) * w.first + __int128(w.second) * w.second;
+        if (n2 > best) {
+          best = n2;
+          j0 = j;
+        }
+      }
+      const auto p = num(0, j0);
+      bool prod = best > 0;
+      for (int i = 0; i < X.n_snk && prod; ++i) {
+        const auto a = num(i, j0);
+        for (int j = 0; j < X.n_src; ++j) {
+          const auto w = num(i, j), b = num(0, j);
+          const __int128 lre = __int128(w.first) * p.first - __int128(w.second) * p.second;
+          const __int128 lim = __int128(w.first) * p.second + __int128(w.second) * p.first;
+          const __int128 rre = __int128(a.first) * b.first - __int128(a.second) * b.second;
+          const __int128 rim = __int128(a.first) * b.second + __int128(a.second) * b.first;
+          if (lre != rre || lim != rim) {
+            prod = false;
+            break;
+          }
+        }
+      }
+      P.rank1 = P.rank1 && prod;
+      const double den = double(s.w_den[c]);
+      const double pr = double(p.first), pi = double(p.second), pn = pr * pr + pi * pi;
+      for (int i = 0; i < X.n_snk; ++i) {
+        const auto a = num(i, j0);
+        P.wu.push_back(double(a.first) / den);
+        P.wu.push_back(double(a.second) / den);
+      }
+      for (int j = 0; j < X.n_src; ++j) {
+        const auto b = num(0, j);
+        const double br = double(b.first), bi = double(b.second);
+        P.wv.push_back(prod ? (br * pr + bi * pi) / pn : 0.0);  // b / p
+        P.wv.push_back(prod ? (bi * pr - br * pi) / pn : 0.0);
+      }
+    }
     // column levels per flavour: all k-subsets of the source tuples
     std::vector<Key> top_cols[2];
     for (auto& k : X.src) {
@@ -636,6 +695,11 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     cr[7] = P.b_n_tiles;
     auto wt = make_tiles(X, budget, dw_keys, dw_model);
     P.b_lds_dw = std::max(P.b_lds_dw, emit_tiles(X, wt, dw_model, wo));
+    if (ds_factored(s.n_u, s.n_d, precision)) {
+      auto ftl = make_tiles(X, bbudget, kMaxB, bwdf_model);
+      P.f_lds_ds = std::max(P.f_lds_ds, emit_tiles(X, ftl, bwdf_model, fo2));
+    }
+    cr[34] = P.f_n_tiles;
   }
   if (w_pos != P.nnz) throw std::logic_error("plan does not cover the index set");
   for (int c = 0; c < s.n_corr; ++c) {
