@@ -377,47 +377,21 @@ struct CsrTab {
 };
 
 // Leaf adjoint of one top column: sum over the group's sink keys b and the
-// first NM entries (s, oc) of the column's source-key list of
+// first nw entries (s, oc) of the column's source-key list (nw: the wave's
+// longest list, uniform; padded entries read the zero element) of
 // W[b, s] * (other flavour's top minor at b's row slot, column oc).  The u
 // leaves take the run [lo, hi) and the d slots of its keys; the d leaves take
-// the sink keys in the bit mask lo and their u slots.  FACT: W[b, s] =
-// u[b] v[s] with v = sW[0, n_src) and u = sW[n_src, n_src + B) (the tile's
-// keys), summed as sum_s v[s] (sum_b u[b] minor_b).
-template <int NM, int MC, bool MASK, bool FACT, typename C>
-__device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, const C* sW, int n_src, const C* sR,
-                                        const int2* sMeta) {
-  if constexpr (FACT) {
-    const C* sU = sW + n_src;
-    C sum = cmake<C>(0, 0);
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      const int sidx = e[m] & 2047, oc = e[m] >> 11;
-      C t = cmake<C>(0, 0);
-      auto key = [&](int b) {
-        const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
-        t = cmac(sU[b], orow[oc], t);
-      };
-      if constexpr (MASK) {
-        for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
-      } else {
-        for (int b = lo; b < hi; ++b) key(b);
-      }
-      sum = cmac(sW[sidx], t, sum);
-    }
-    return sum;
-  }
+// the sink keys in the bit mask lo and their u slots.
+template <int MC, bool MASK, typename C>
+__device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
+                                      const C* sR, const int2* sMeta) {
   C sum = cmake<C>(0, 0);
-  int sidx[NM], oc[NM];
-#pragma unroll
-  for (int m = 0; m < NM; ++m) {
-    sidx[m] = e[m] & 2047;
-    oc[m] = e[m] >> 11;
-  }
   auto key = [&](int b) {
     const C* wrow = sW + b * n_src;
     const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
 #pragma unroll
-    for (int m = 0; m < NM; ++m) sum = cmac(wrow[sidx[m]], orow[oc[m]], sum);
+    for (int m = 0; m < MC; ++m)
+      if (m < nw) sum = cmac(wrow[e[m] & 2047], orow[e[m] >> 11], sum);
   };
   if constexpr (MASK) {
     for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
@@ -427,17 +401,53 @@ __device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, cons
   return sum;
 }
 
-// Dispatch on the wave's longest list (nw, uniform), in steps of two entries;
-// the padded entries of shorter lists contribute zero.
-template <int N, int MC, bool MASK, bool FACT, typename C>
-__device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
-                                      const C* sR, const int2* sMeta) {
-  if constexpr (N >= MC) {
-    return leaf_terms<MC, MC, MASK, FACT>(e, lo, hi, sW, n_src, sR, sMeta);
-  } else {
-    if (nw <= N) return leaf_terms<N, MC, MASK, FACT>(e, lo, hi, sW, n_src, sR, sMeta);
-    return leaf_sum<N + 2, MC, MASK, FACT>(nw, e, lo, hi, sW, n_src, sR, sMeta);
+// Factored weights W[b, s] = u[b] v[s] (v = sW[0, n_src), u = sW[n_src, n_src + B)).
+// Slot field of a staged key record; bit 30 of the d slot marks the first key
+// of the tile with its d-tuple.
+constexpr int kSlotMask = (1 << 30) - 1;
+
+// u top column of a run [b0, b1): sum over the first nw (the wave's longest
+// list, uniform) entries of the column's source-key list of
+// v[s] sum_b u[b] Dd_b[c_d(s)], in groups of G entries with the keys inside,
+// so that a key's gathers of a group are in flight together; padded entries
+// read the zero element.
+template <int MC, typename C>
+__device__ __forceinline__ C leaf_u_fact(int nw, const int (&e)[MC], int b0, int b1, const C* sW, int n_src,
+                                         const C* sR, const int2* sMeta) {
+  constexpr int G = 2;
+  const C* sU = sW + n_src;
+  C sum = cmake<C>(0, 0);
+#pragma unroll
+  for (int m0 = 0; m0 < MC; m0 += G) {
+    if (m0 < nw) {
+      C t[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) t[j] = cmake<C>(0, 0);
+      for (int b = b0; b < b1; ++b) {
+        const C u = sU[b];
+        const C* orow = sR + (sMeta[b].y & kSlotMask);
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if (m0 + j < MC) t[j] = cmac(u, orow[e[m0 + j] >> 11], t[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (m0 + j < MC) sum = cmac(sW[e[m0 + j] & 2047], t[j], sum);
+    }
   }
+  return sum;
+}
+
+// d top column, one run: H = sum over the first nw entries of the column's
+// source-key list of v[s] Du[c_u(s)] (du: the run's u top row).  The run's
+// keys b then add u[b] H to the adjoint of their d top row.
+template <int MC, typename C>
+__device__ __forceinline__ C leaf_h_fact(int nw, const int (&e)[MC], const C* sW, const C* du) {
+  C sum = cmake<C>(0, 0);
+#pragma unroll
+  for (int m = 0; m < MC; ++m)
+    if (m < nw) sum = cmac(sW[e[m] & 2047], du[e[m] >> 11], sum);
+  return sum;
 }
 
 template <int NF, int QMAX, int NT>
@@ -688,7 +698,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
     }
     if (tid < B) {
       const int4 mb = meta_all[meta0 + tid];
-      sMeta[tid] = make_int2(mb.x, mb.y);
+      sMeta[tid] = make_int2(mb.x, FACT ? (mb.y | ((mb.z & 2) << 29)) : mb.y);
     }
     for (int i = tid; i < nops; i += NT) {
       const int4* op = reinterpret_cast<const int4*>(a.ops + int64_t(op0 + i) * kOpInts);
@@ -709,7 +719,43 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
     tile_levels<KMIN, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR);
 
     // adjoints of the top rows from the factor-tree leaves
-    {
+    if constexpr (FACT) {
+      // per run: u top row adjoint (u columns), and u[b] H added to the d top
+      // row adjoint of each key b of the run (d columns; the first key of a
+      // d-tuple writes, later ones add, in key order)
+      const int n_runs = sEx[0];
+      const int32_t* runs = sEx + 3;
+      const C* sU = sW + n_src;
+      for (int r = 0; r < n_runs; ++r) {
+        const int us = runs[3 * r], b0 = runs[3 * r + 1], b1 = runs[3 * r + 2];
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          const int c = vt_u + NT * q;
+          if (c < cu_tab.ncol) {
+            const C sum = leaf_u_fact<MC>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
+            sA[us + c] = cmul(gbar, sum);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+          const int c = vt_d + NT * q;
+          if (c < cd_tab.ncol) {
+            const C h = cmul(gbar, leaf_h_fact<MC>(cd_tab.nw[q], cd_tab.e[q], sW, sR + us));
+            for (int b = b0; b < b1; ++b) {
+              const int dy = sMeta[b].y;
+              C* dst = sA + (dy & kSlotMask) + c;
+              C v = cmul(sU[b], h);
+              if (!(dy >> 30)) {
+                const C o = *dst;
+                v.x += o.x;
+                v.y += o.y;
+              }
+              *dst = v;
+            }
+          }
+        }
+      }
+    } else {
       const int n_runs = sEx[0], n_dg = sEx[1];
       const int32_t* runs = sEx + 3;
       const int32_t* dgs = runs + 3 * n_runs;
@@ -719,7 +765,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_u + NT * q;
           if (c < cu_tab.ncol) {
-            const C sum = leaf_sum<2, MC, false, FACT>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
           }
         }
@@ -730,7 +776,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_d + NT * q;
           if (c < cd_tab.ncol) {
-            const C sum = leaf_sum<2, MC, true, FACT>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
           }
         }

@@ -178,6 +178,8 @@ bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64
 //   (virtual = a level-1 parent standing for S row r0: out = 12 * its index
 //   in the tile's level-1 adjoint rows).
 // Meta per sink key of a tile (kMetaInts ints): u_slot, d_slot, run_end, snk
+//   (factored dS tiling: run_end | 2 if no earlier key of the tile has the
+//   key's d-tuple)
 // Four tilings of the sink keys per plan: the forward's (tiles/ops/meta),
 // the dS kernel's (b_*: backward records, every row slot followed by one
 // zero element that padded table entries point at), the dW kernel's

@@ -311,7 +311,10 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
       const bool run_end = (b + 1 == B) || !(X.snk[sk[b + 1]].first == X.snk[i].first);
       const int u_slot = slot.at({0, X.nf[0], X.snk[i].first});
       const int d_slot = slot.at({1, X.nf[1], X.snk[i].second});
-      const int32_t mm[kMetaInts] = {u_slot, d_slot, run_end ? 1 : 0, i};
+      bool first_d = true;  // no earlier key of the tile shares the d-tuple
+      for (int q = 0; q < b && first_d; ++q) first_d = !(X.snk[sk[q]].second == X.snk[i].second);
+      const int32_t flags = (run_end ? 1 : 0) | ((m.factored && first_d) ? 2 : 0);
+      const int32_t mm[kMetaInts] = {u_slot, d_slot, flags, i};
       o.meta->insert(o.meta->end(), mm, mm + kMetaInts);
       if (o.exec) *o.exec += 8.0 * X.n_src + (run_end ? 8.0 * X.n_src : 0.0);
     }
