@@ -283,23 +283,32 @@ struct BinTab {
 
 // Parent adjoints: the (parent, column) items of a level are spread like the
 // forward row items: with ncol <= NT, G = NT / ncol parents side by side
-// (thread t: column t % ncol of parent group t / ncol); else columns t, t + NT.
-// Entries: index of C' + {j} one level up | parity of the position of j << 11
-// | j << 12, compacted and padded to 12 - K entries (the most a K-column can
-// have) with the child row's zero element (index ncol one level up), two per
-// int32.
+// (thread t: item t % ncol of parent group t / ncol); else items t, t + NT.
+// Item i takes column col = order[i] of the level's columns ordered by their
+// count of supersets, so a wave's columns have similar counts; nw is the
+// wave's largest count (uniform).  Entries: index of C' + {j} one level up |
+// parity of the position of j << 11 | j << 12, compacted and padded to
+// 12 - K entries (the most a K-column can have) with the child row's zero
+// element (index ncol one level up), two per int32.
 __host__ __device__ constexpr int up_len(int k) { return 12 - k; }
+
+// Parent-table entries per uniform bound check: the loads of a step issue
+// together.
+constexpr int kUpStep = 4;
 
 template <int K, int QMAX, int NT>
 struct UpTab {
   int ncol = 0, G = 1, g = 0, i0 = 0;
   unsigned up[QMAX][6];
+  int col[QMAX];     // the item's column, ncol if none
+  int nw[QMAX];      // entries the wave runs
   int colnum[QMAX];
   __device__ __forceinline__ void load(const int32_t* cr, int f, const int32_t* __restrict__ btab,
                                        const uint16_t* __restrict__ tabs, int t) {
     ncol = cr[8 + 2 * (6 * f + K - 1)];
     const unsigned pad = unsigned(cr[8 + 2 * (6 * f + K)]) & 2047u;  // ncol one level up
     const int32_t* ut = btab + cr[67 + 6 * f + K - 1];
+    const int32_t* order = ut + 6 * ncol;
     const int toff = cr[8 + 2 * (6 * f + K - 1) + 1];
     if (ncol > 0 && ncol <= NT) {
       G = NT / ncol;
@@ -312,8 +321,10 @@ struct UpTab {
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = i0 + NT * q;
-      const bool ok = c < ncol && g < G;
+      const int i = i0 + NT * q;
+      const bool ok = i < ncol && g < G;
+      const int c = ok ? order[i] : 0;
+      col[q] = ok ? c : ncol;
       int cnt = 0;
 #pragma unroll
       for (int w = 0; w < 6; ++w) up[q][w] = 0;
@@ -333,6 +344,8 @@ struct UpTab {
       for (int m = 0; m < up_len(K); ++m)
         if (m >= cnt) up[q][m >> 1] |= pad << (16 * (m & 1));
       colnum[q] = (K == 1 && ok) ? int(tabs[toff + c]) : 0;
+      for (int off = 32; off > 0; off >>= 1) cnt = max(cnt, __shfl_xor(cnt, off));
+      nw[q] = __builtin_amdgcn_readfirstlane(cnt);
     }
   }
 };
@@ -390,8 +403,11 @@ __device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi
     const C* wrow = sW + b * n_src;
     const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
 #pragma unroll
-    for (int m = 0; m < MC; ++m)
-      if (m < nw) sum = cmac(wrow[e[m] & 2047], orow[e[m] >> 11], sum);
+    for (int m0 = 0; m0 < MC; m0 += 2)
+      if (m0 < nw) {
+#pragma unroll
+        for (int m = m0; m < m0 + 2 && m < MC; ++m) sum = cmac(wrow[e[m] & 2047], orow[e[m] >> 11], sum);
+      }
   };
   if constexpr (MASK) {
     for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
@@ -445,8 +461,11 @@ template <int MC, typename C>
 __device__ __forceinline__ C leaf_h_fact(int nw, const int (&e)[MC], const C* sW, const C* du) {
   C sum = cmake<C>(0, 0);
 #pragma unroll
-  for (int m = 0; m < MC; ++m)
-    if (m < nw) sum = cmac(sW[e[m] & 2047], du[e[m] >> 11], sum);
+  for (int m0 = 0; m0 < MC; m0 += 2)
+    if (m0 < nw) {
+#pragma unroll
+      for (int m = m0; m < m0 + 2 && m < MC; ++m) sum = cmac(sW[e[m] & 2047], du[e[m] >> 11], sum);
+    }
   return sum;
 }
 
@@ -560,7 +579,7 @@ __device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o
 }
 
 template <int KP, typename C>
-__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int4 ox, const int4* sOpv,
+__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int nw, int4 ox, const int4* sOpv,
                                         const int32_t* children, const C* Sf, const C* sA) {
   C sum = cmake<C>(0, 0);
   const int nch = ox.w & 0xffff;
@@ -568,10 +587,15 @@ __device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int4 ox, const 
     const int4 chv = sOpv[children[ox.z + ci]];
     const C* srow = Sf + 12 * chv.x;
 #pragma unroll
-    for (int m = 0; m < up_len(KP); ++m) {
-      const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
-      const C av = sA[chv.z + int(ent & 2047u)];
-      sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
+    for (int m0 = 0; m0 < up_len(KP); m0 += kUpStep) {
+      if (m0 < nw) {  // entries past a lane's count read the zero element
+#pragma unroll
+        for (int m = m0; m < m0 + kUpStep && m < up_len(KP); ++m) {
+          const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+          const C av = sA[chv.z + int(ent & 2047u)];
+          sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
+        }
+      }
     }
   }
   return sum;
@@ -590,9 +614,9 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, in
     const int4 ov = sOpv[p];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
-      const int c = ut.i0 + NT * q;
+      const int c = ut.col[q];
       if (c < ut.ncol) {
-        const C sum = parent_sum<K - 1>(ut.up[q], ox, sOpv, children, Sf, sA);
+        const C sum = parent_sum<K - 1>(ut.up[q], ut.nw[q], ox, sOpv, children, Sf, sA);
         if (K == 2)
           sAdj1[ov.z + ut.colnum[q]] = sum;
         else

@@ -146,6 +146,9 @@ bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64
 //                     per column C', 12 uint16 (packed two per int32): the
 //                     index of C' + {j} in level k+1 | (position of j) << 12,
 //                     0xffff if C' + {j} is not a needed column
+//                     (12 uint16 per column C'), followed by the ncol[f][k]
+//                     column numbers ordered by their count of such
+//                     supersets, most first
 //   [80 + f]          longest source-key list of a top column of flavour f
 //   [82 + 6*f + k-1]  longest j-list of level k
 //   [32] snk_vec_off  offset of the correlator's sink keys (plan order) in

@@ -437,7 +437,9 @@ void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) 
     for (int k = 1; k < X.nf[f]; ++k) {
       cr[67 + 6 * f + k - 1] = int32_t(btab.size());
       const auto& cols = X.lev[f].cols[k];
-      for (const Key& Cp : cols) {
+      std::vector<int> n_up(cols.size(), 0);
+      for (size_t ci = 0; ci < cols.size(); ++ci) {
+        const Key& Cp = cols[ci];
         uint32_t pk[6] = {0, 0, 0, 0, 0, 0};
         for (int j = 0; j < 12; ++j) {
           int idx = 0xffff;
@@ -459,12 +461,19 @@ void backward_tables(const CorrCtx& X, int32_t* cr, std::vector<int32_t>& btab) 
               for (int q = 0; q < Cp.n; ++q) pos += Cp.v[q] < j;
               if (it->second >= 4096) throw std::runtime_error("column list too long");
               idx = it->second | (pos << 12);
+              ++n_up[ci];
             }
           }
           pk[j / 2] |= (uint32_t(idx) & 0xffffu) << (16 * (j % 2));
         }
         for (uint32_t w : pk) btab.push_back(int32_t(w));
       }
+      // then the columns ordered by their number of supersets (most first),
+      // so that the columns a wave takes have similar counts
+      std::vector<int32_t> perm(cols.size());
+      for (size_t ci = 0; ci < cols.size(); ++ci) perm[ci] = int32_t(ci);
+      std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return n_up[x] > n_up[y]; });
+      btab.insert(btab.end(), perm.begin(), perm.end());
     }
   // source keys grouped by their top u column and by their top d column
   for (int f = 0; f < 2; ++f) {
