@@ -406,10 +406,17 @@ def main():
         plan = api.Plan(iset, prec)
         plans[prec] = plan
         st = plan.stats
+        # algorithmic flops per site of what runs: the exact weights (W None)
+        # go through their factors where the plan says so
+        fwd_fact = W is None and bool(st["fwd_factored"])
+        ds_fact = W is None and bool(st["ds_factored"])
+        fl_fwd = st["fact_alg_flops_per_site"] if fwd_fact else st["alg_flops_per_site"]
+        fl_ds = st["fact_ds_alg_flops_per_site"] if ds_fact else st["ds_alg_flops_per_site"]
         print(f"[bench] plan {prec}: tiles={st['n_tiles']}/{st['b_n_tiles']}/{st['w_n_tiles']} "
-              f"factored dS tiles={st['f_n_tiles'] if st['rank1'] else None} lds={st['lds_bytes']}/"
-              f"{st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} alg fwd={st['alg_flops_per_site']:.3e} "
-              f"dS={st['ds_alg_flops_per_site']:.3e} dW={st['dw_alg_flops_per_site']:.3e} "
+              f"factored tiles={st['f_n_tiles'] if st['rank1'] else None} (fwd {fwd_fact}, dS {ds_fact}) "
+              f"lds={st['f_lds_bytes_fwd'] if fwd_fact else st['lds_bytes']}/"
+              f"{st['f_lds_bytes_ds'] if ds_fact else st['b_lds_bytes_ds']}/{st['b_lds_bytes_dw']} "
+              f"alg fwd={fl_fwd:.3e} dS={fl_ds:.3e} dW={st['dw_alg_flops_per_site']:.3e} "
               f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
 
         # one step: forward, then the backward as its two launches (dW, then
@@ -448,17 +455,18 @@ def main():
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t_wall) / args.steps
         ms = first.elapsed_time(last) / args.steps
-        kern = {"fwd": (sum(m[0].elapsed_time(m[1]) for m in marks) / args.steps, st["alg_flops_per_site"])}
+        kern = {"fwd": (sum(m[0].elapsed_time(m[1]) for m in marks) / args.steps, fl_fwd)}
         if do_bwd:
             kern["dW"] = (sum(m[1].elapsed_time(m[2]) for m in marks) / args.steps, st["dw_alg_flops_per_site"])
-            kern["dS"] = (sum(m[2].elapsed_time(m[3]) for m in marks) / args.steps, st["ds_alg_flops_per_site"])
+            kern["dS"] = (sum(m[2].elapsed_time(m[3]) for m in marks) / args.steps, fl_ds)
         dom = max(kern, key=lambda k: kern[k][0])
         r = dict(ms_per_step=ms, wall_ms_per_step=1e3 * wall, value=entries / (ms * 1e-3), dominant=dom,
                  pass_="fwd+bwd" if do_bwd else "fwd",
                  kernels={k: {"ms": v[0], "alg_tflops": v[1] * sites_step / (v[0] * 1e-3) / 1e12,
                               "frac": v[1] * sites_step / (v[0] * 1e-3) / PEAK[prec]} for k, v in kern.items()},
                  fwd_value=entries / (kern["fwd"][0] * 1e-3),
-                 exec_tflops_fwd=st["exec_flops_per_site"] * sites_step / (kern["fwd"][0] * 1e-3) / 1e12)
+                 exec_tflops_fwd=(None if fwd_fact else
+                                  st["exec_flops_per_site"] * sites_step / (kern["fwd"][0] * 1e-3) / 1e12))
         results[prec] = r
         print(f"[bench] {prec}: step {ms:.3f} ms ({entries / (ms * 1e-3):.3e} entries/s) " +
               " ".join(f"{k} {v['ms']:.2f} ms {v['alg_tflops']:.2f} TF" for k, v in r["kernels"].items()),
@@ -479,7 +487,8 @@ def main():
             a1.record(stream)
             torch.cuda.synchronize()
             fms = a0.elapsed_time(a1)
-            fl = plan.stats["alg_flops_per_site"] * T * V
+            pst = plan.stats
+            fl = (pst["fact_alg_flops_per_site"] if (W is None and pst["fwd_factored"]) else pst["alg_flops_per_site"]) * T * V
             full[prec] = {"ms": fms, "value": float(nnz) * T * V / (fms * 1e-3), "alg_tflops": fl / (fms * 1e-3) / 1e12,
                           "frac": fl / (fms * 1e-3) / PEAK[prec]}
             print(f"[bench] {prec}: whole-lattice forward {fms / 1e3:.2f} s ({full[prec]['value']:.3e} entries/s, "

@@ -137,11 +137,17 @@ typedef struct {
   double dw_alg_flops_per_site; /* dW: minors + 8 per entry */
   int32_t w_n_tiles;            /* tiles of the dW schedule */
   int32_t rank1;                /* 1: every correlator's exact weights are a sink vector times a
-                                   source vector; for every family but the (3,3) one in
-                                   FP32-comp, mbc_contract_backward with W = NULL then runs the
-                                   dS schedule that stages those factors instead of the weights */
-  int32_t f_n_tiles;            /* tiles of that factored dS schedule */
+                                   source vector (the factored schedules below apply) */
+  int32_t f_n_tiles;            /* tiles of the factored schedule */
   int64_t f_lds_bytes_ds;       /* dynamic LDS per workgroup of the factored dS kernel */
+  int32_t fwd_factored;         /* 1: mbc_contract with W = NULL evaluates the exact weights through
+                                   their factors on the factored schedule (per run of equal
+                                   u-tuples: sum over d columns of (sum_b u[b] Dd)(sum_s v[s] Du)) */
+  int32_t ds_factored;          /* 1: mbc_contract_backward with W = NULL runs the factored dS
+                                   schedule (rank1, and not the (3,3) family in FP32-comp) */
+  int64_t f_lds_bytes_fwd;      /* dynamic LDS per workgroup of that factored forward */
+  double fact_alg_flops_per_site;    /* forward flops of the factored evaluation (global minor DAG) */
+  double fact_ds_alg_flops_per_site; /* dS flops with the factored leaf adjoints */
 } mbc_plan_stats;
 mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out);
 

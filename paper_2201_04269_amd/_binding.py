@@ -38,7 +38,9 @@ class PlanStats(ctypes.Structure):
                 ("b_lds_bytes_ds", ctypes.c_int64), ("b_lds_bytes_dw", ctypes.c_int64),
                 ("ds_alg_flops_per_site", ctypes.c_double), ("dw_alg_flops_per_site", ctypes.c_double),
                 ("w_n_tiles", ctypes.c_int32), ("rank1", ctypes.c_int32), ("f_n_tiles", ctypes.c_int32),
-                ("f_lds_bytes_ds", ctypes.c_int64)]
+                ("f_lds_bytes_ds", ctypes.c_int64), ("fwd_factored", ctypes.c_int32), ("ds_factored", ctypes.c_int32),
+                ("f_lds_bytes_fwd", ctypes.c_int64), ("fact_alg_flops_per_site", ctypes.c_double),
+                ("fact_ds_alg_flops_per_site", ctypes.c_double)]
 
 
 class BlockCorrDesc(ctypes.Structure):

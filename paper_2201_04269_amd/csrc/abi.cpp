@@ -116,11 +116,15 @@ struct FwdWorkspace {
   size_t w_plan = 0, partial = 0, total = 0;
 };
 
+// The forward of the exact weights runs factored when the plan allows it.
+bool fwd_factored(const PlanHost& h, bool user_w) { return !user_w && h.fwd_fact; }
+
 FwdWorkspace fwd_workspace(const PlanHost& h, const Launch& L, bool user_w) {
   FwdWorkspace w;
   const size_t csz = h.precision == MBC_F64 ? 16 : 8;
   w.w_plan = user_w ? align256(size_t(h.nnz) * csz) : 0;
-  w.partial = align256(size_t(h.n_tiles) * size_t(L.T) * size_t(L.nc) * 16);
+  const int n_tiles = fwd_factored(h, user_w) ? h.f_n_tiles : h.n_tiles;
+  w.partial = align256(size_t(n_tiles) * size_t(L.T) * size_t(L.nc) * 16);
   w.total = w.w_plan + w.partial;
   return w;
 }
@@ -323,6 +327,11 @@ mbc_status mbc_plan_get_stats(const mbc_plan* p, mbc_plan_stats* out) {
   out->rank1 = p->h.rank1 ? 1 : 0;
   out->f_n_tiles = p->h.f_n_tiles;
   out->f_lds_bytes_ds = p->h.f_lds_ds;
+  out->fwd_factored = p->h.fwd_fact ? 1 : 0;
+  out->ds_factored = (p->h.rank1 && ds_factored(p->h.n_u, p->h.n_d, p->h.precision)) ? 1 : 0;
+  out->f_lds_bytes_fwd = p->h.f_lds_fwd;
+  out->fact_alg_flops_per_site = p->h.fact_alg_flops_per_site;
+  out->fact_ds_alg_flops_per_site = p->h.fact_ds_alg_flops_per_site;
   return MBC_OK;
 }
 
@@ -334,8 +343,10 @@ mbc_status mbc_plan_workspace_bytes(const mbc_plan* p, int32_t T, int64_t sites_
     const Launch L = backward_dw_launch_shape(p->h, T, sites_per_t);
     *bytes = bwd_workspace(p->h, L, true).total;
   } else {
-    const Launch L = forward_launch_shape(p->h, T, sites_per_t);
-    *bytes = fwd_workspace(p->h, L, true).total;
+    // enough for either weights: user W, or the plan's exact ones (factored or not)
+    const Launch L = forward_launch_shape(p->h, T, sites_per_t, false);
+    const Launch Lf = forward_launch_shape(p->h, T, sites_per_t, fwd_factored(p->h, false));
+    *bytes = std::max(fwd_workspace(p->h, L, true).total, fwd_workspace(p->h, Lf, false).total);
   }
   return MBC_OK;
 }
@@ -355,7 +366,8 @@ mbc_status mbc_contract(const mbc_plan* p, const void* S_u, const void* S_d, int
   if (!is_device_ptr(C)) return fail(MBC_ERR_INVALID, "C must be a device pointer");
   if (W && !is_device_ptr(W)) return fail(MBC_ERR_INVALID, "W must be a device pointer or NULL");
   if (W && !aligned16(W)) return fail(MBC_ERR_INVALID, "W must be 16-byte aligned");
-  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+  const bool fact = fwd_factored(p->h, W != nullptr);
+  const Launch L = forward_launch_shape(p->h, T, sites_per_t, fact);
   const FwdWorkspace ws = fwd_workspace(p->h, L, W != nullptr);
   if (ws.total > 0 && (!workspace || !is_device_ptr(workspace)))
     return fail(MBC_ERR_INVALID, "workspace must be a device pointer");
@@ -372,8 +384,8 @@ mbc_status mbc_contract(const mbc_plan* p, const void* S_u, const void* S_d, int
     W_plan = wsb;
   }
   double* partial = reinterpret_cast<double*>(wsb + ws.w_plan);
-  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, hs));
-  MBC_HIP(launch_reduce(p, L, partial, C, hs));
+  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, fact, hs));
+  MBC_HIP(launch_reduce(p, L, partial, C, fact, hs));
   return MBC_OK;
 }
 
@@ -384,7 +396,8 @@ mbc_status mbc_contract_noalloc(const mbc_plan* p, const void* S_u, const void* 
   if (!is_device_ptr(C)) return fail(MBC_ERR_INVALID, "C must be a device pointer");
   if (W && !is_device_ptr(W)) return fail(MBC_ERR_INVALID, "W must be a device pointer or NULL");
   if (W && !aligned16(W)) return fail(MBC_ERR_INVALID, "W must be 16-byte aligned");
-  const Launch L = forward_launch_shape(p->h, T, sites_per_t);
+  const bool fact = fwd_factored(p->h, W != nullptr);
+  const Launch L = forward_launch_shape(p->h, T, sites_per_t, fact);
   const FwdWorkspace ws = fwd_workspace(p->h, L, W != nullptr);
   if (ws.total > kScratchBytes)
     return fail(MBC_ERR_UNSUPPORTED, "mbc_contract_noalloc needs " + std::to_string(ws.total) +
@@ -405,8 +418,8 @@ mbc_status mbc_contract_noalloc(const mbc_plan* p, const void* S_u, const void* 
     W_plan = wsb;
   }
   double* partial = reinterpret_cast<double*>(wsb + ws.w_plan);
-  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, hs));
-  MBC_HIP(launch_reduce(p, L, partial, C, hs));
+  MBC_HIP(launch_forward(p, S_u, S_d, s_dtype == MBC_C64, L, W_plan, partial, fact, hs));
+  MBC_HIP(launch_reduce(p, L, partial, C, fact, hs));
   return MBC_OK;
 }
 

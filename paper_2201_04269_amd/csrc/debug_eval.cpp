@@ -22,7 +22,67 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
   }
   std::vector<cd> out(size_t(h.n_corr) * T, cd(0, 0));
   std::vector<cd> S(288), R;
-  for (int tile = 0; tile < h.n_tiles; ++tile) {
+  // the exact weights go through the factored forward, as mbc_contract does:
+  // per run of the factored tiles, sum over top d columns c of
+  // (sum_b u[b] Dd_b[c]) (sum over the source keys of column c of v[s] Du[c_u(s)])
+  const bool fact = (W == nullptr) && h.fwd_fact;
+  for (int tile = 0; fact && tile < h.f_n_tiles; ++tile) {
+    const int32_t* tr = &h.f_tiles[size_t(tile) * kTileInts];
+    const int corr = tr[0], B = tr[1], op0 = tr[3], meta0 = tr[5], units = tr[6], nreal = tr[17];
+    const int32_t* cr = &h.corr[size_t(corr) * kCorrInts];
+    const int src_off = cr[1];
+    const int ncd = cr[8 + 2 * (6 + h.n_d - 1)];
+    const int32_t* csrd = &h.btab[size_t(cr[65])];
+    auto cx = [](const std::vector<double>& v, size_t i) { return cd(v[2 * i], v[2 * i + 1]); };
+    R.assign(size_t(units), cd(0, 0));
+    for (int t = 0; t < T; ++t)
+      for (int64_t v = 0; v < V; ++v) {
+        const int64_t site = int64_t(t) * V + v;
+        for (int i = 0; i < 144; ++i) {
+          S[i] = cd(S_u[2 * (site * 144 + i)], S_u[2 * (site * 144 + i) + 1]);
+          S[144 + i] = cd(S_d[2 * (site * 144 + i)], S_d[2 * (site * 144 + i) + 1]);
+        }
+        for (int o = 0; o < nreal; ++o) {  // rows (backward op records, level order)
+          const int32_t* p = &h.f_ops[size_t(op0 + o) * kOpInts];
+          const int f = p[0], k = p[1], r0 = p[2], in = p[3], outs = p[4];
+          const int nc = cr[8 + 2 * (6 * f + k - 1)], toff = cr[8 + 2 * (6 * f + k - 1) + 1];
+          const cd* Sf = &S[144 * f];
+          for (int i = 0; i < nc; ++i) {
+            cd val(0, 0);
+            if (k == 1) {
+              val = Sf[12 * r0 + h.tabs[toff + i]];
+            } else {
+              for (int j = 0; j < k; ++j) {
+                const int e = h.tabs[toff + i * k + j];
+                const cd x = Sf[12 * r0 + (e & 15)];
+                const cd y = (k == 2) ? Sf[12 * in + (e >> 4)] : R[in + (e >> 4)];
+                val += (j & 1) ? -x * y : x * y;
+              }
+            }
+            R[outs + i] = val;
+          }
+        }
+        cd acc(0, 0);
+        for (int c = 0; c < ncd; ++c) {
+          cd L(0, 0);
+          for (int b = 0; b < B; ++b) {
+            const int32_t* mb = &h.f_meta[size_t(meta0 + b) * kMetaInts];
+            L += cx(h.wu, size_t(cr[32] + tr[16] + b)) * R[mb[1] + c];
+            if (mb[2] & 1) {
+              cd H(0, 0);
+              for (int q = csrd[c]; q < csrd[c + 1]; ++q) {
+                const int sidx = csrd[q];
+                H += cx(h.wv, size_t(src_off + sidx)) * R[mb[0] + h.src_cu[src_off + sidx]];
+              }
+              acc += L * H;
+              L = cd(0, 0);
+            }
+          }
+        }
+        out[size_t(corr) * T + t] += acc;
+      }
+  }
+  for (int tile = 0; !fact && tile < h.n_tiles; ++tile) {
     const int32_t* tr = &h.tiles[size_t(tile) * kTileInts];
     const int corr = tr[0], B = tr[1], w_off = tr[2], op0 = tr[3], meta0 = tr[5], units = tr[6], nph = tr[7];
     const int32_t* cr = &h.corr[size_t(corr) * kCorrInts];
@@ -96,6 +156,11 @@ mbc_status debug_eval(const mbc_index_set* s, int precision, const double* S_u, 
     stats->rank1 = h.rank1 ? 1 : 0;
     stats->f_n_tiles = h.f_n_tiles;
     stats->f_lds_bytes_ds = h.f_lds_ds;
+    stats->fwd_factored = h.fwd_fact ? 1 : 0;
+    stats->ds_factored = (h.rank1 && ds_factored(h.n_u, h.n_d, h.precision)) ? 1 : 0;
+    stats->f_lds_bytes_fwd = h.f_lds_fwd;
+    stats->fact_alg_flops_per_site = h.fact_alg_flops_per_site;
+    stats->fact_ds_alg_flops_per_site = h.fact_ds_alg_flops_per_site;
   }
   return MBC_OK;
 }

@@ -40,6 +40,9 @@ struct FwdArgs {
   const int32_t* src_cd;
   const uint16_t* tabs;
   const void* W;     // plan-ordered weights, plan precision
+  const void* wu;    // factored: sink and source factors of the exact weights
+  const void* wv;
+  const int32_t* btab;
   const void* S_u;
   const void* S_d;
   int s_c64;
@@ -115,7 +118,24 @@ __device__ __forceinline__ void leaf_dispatch(int nlive, int B, const int4* meta
   }
 }
 
-template <typename R, int NU, int ND, int MAXS, int QMAX, int NT>
+// Factored leaves (W[b, s] = u[b] v[s]): thread t owns top d column t and
+// the source keys s of that column (list entries s | c_u(s) << 11, padded with
+// the zero weight at slot n_src).  Per key b of a run it accumulates
+// L += u[b] Dd_b[t]; at the run's end it adds L * H to its compensated
+// accumulator, H = sum over its source keys of v[s] Du[c_u(s)].
+template <int MC, typename C>
+__device__ __forceinline__ C fact_group(int nw, const int (&e)[MC], const C* sV, const C* du) {
+  C h = cmake<C>(0, 0);
+#pragma unroll
+  for (int m0 = 0; m0 < MC; m0 += 2)
+    if (m0 < nw) {
+#pragma unroll
+      for (int m = m0; m < m0 + 2 && m < MC; ++m) h = cmac(sV[e[m] & 2047], du[e[m] >> 11], h);
+    }
+  return h;
+}
+
+template <typename R, int NU, int ND, int MAXS, int QMAX, int NT, bool FACT, int MC>
 __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
@@ -136,16 +156,22 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
   const int n_src = cr[0], src_off = cr[1];
 
   C* sS0 = reinterpret_cast<C*>(smem);
-  C* sW = sS0 + 576;
-  C* sR = sW + B * n_src;
+  C* sW = sS0 + 576;  // W (B x n_src), or FACT: v (n_src), a zero, u (B)
+  C* sR = sW + (FACT ? n_src + 1 + B : B * n_src);
   int4* sOps = lds_align16<int4>(smem, sR + row_units);
-  int4* meta = sOps + nops;  // (u slot, d slot, run end, key) of each sink key
+  int4* meta = sOps + nops;  // (u slot, d slot, run end (bit 0), key) of each sink key
 
   for (int i = tid; i < nops; i += NT) {
     const int32_t* op = a.ops + int64_t(op0 + i) * kOpInts;
     sOps[i] = make_int4(op[2], op[3], op[4], 0);
   }
-  stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+  if constexpr (FACT) {
+    stage_lds<NT>(sW, reinterpret_cast<const C*>(a.wv) + src_off, n_src);
+    if (tid == 0) sW[n_src] = cmake<C>(0, 0);
+    if (tid < B) sW[n_src + 1 + tid] = reinterpret_cast<const C*>(a.wu)[cr[32] + tr[16] + tid];
+  } else {
+    stage_lds<NT>(sW, reinterpret_cast<const C*>(a.W) + w_off, B * n_src);
+  }
   if (tid < B) meta[tid] = reinterpret_cast<const int4*>(a.meta)[meta0 + tid];
 
   FlavTabs<NU, QMAX, NT> tu;
@@ -155,17 +181,48 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
 
   // source keys s = vt + NT m (vt: rotated lane); lanes past the last key read key n_src - 1
   // and drop their products; the wave runs the slots its first lane has
-  int cu[MAXS], cd[MAXS], sl[MAXS];
-  bool live[MAXS];
+  constexpr int NS = FACT ? 1 : MAXS;
+  int cu[NS], cd[NS], sl[NS];
+  bool live[NS];
+  int nlive = 0;
+  // FACT: the thread's top d column and its source-key list
+  constexpr int NE = FACT ? MC : 1;
+  int le[NE];
+  int lnw = 0, dcol = 0;
+  bool dlive = false;
+  if constexpr (FACT) {
+    const int ncd = cr[8 + 2 * (6 + ND - 1)];
+    dlive = vt < ncd;
+    dcol = dlive ? vt : 0;
+    const int32_t* lists = a.btab + cr[65];
+    int n = 0, q0 = 0;
+    if (dlive) {
+      q0 = lists[vt];
+      n = lists[vt + 1] - q0;
+    }
 #pragma unroll
-  for (int m = 0; m < MAXS; ++m) {
-    const int s = vt + NT * m;
-    live[m] = s < n_src;
-    sl[m] = live[m] ? s : n_src - 1;
-    cu[m] = a.src_cu[src_off + sl[m]];
-    cd[m] = a.src_cd[src_off + sl[m]];
+    for (int m = 0; m < NE; ++m) {
+      int v = n_src;  // the zero weight
+      if (m < n) {
+        const int s = lists[q0 + m];
+        v = s | (a.src_cu[src_off + s] << 11);
+      }
+      le[m] = v;
+    }
+    for (int off = 32; off > 0; off >>= 1) n = max(n, __shfl_xor(n, off));
+    lnw = __builtin_amdgcn_readfirstlane(n);
+    nlive = (vt & ~63) < ncd ? 1 : 0;  // wave has a live column
+  } else {
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int s = vt + NT * m;
+      live[m] = s < n_src;
+      sl[m] = live[m] ? s : n_src - 1;
+      cu[m] = a.src_cu[src_off + sl[m]];
+      cd[m] = a.src_cd[src_off + sl[m]];
+    }
+    nlive = (n_src - (vt & ~63) + NT - 1) / NT;  // > 0 unless the wave has no key
   }
-  const int nlive = (n_src - (vt & ~63) + NT - 1) / NT;  // > 0 unless the wave has no key
 
   const int t = tc / a.nc, ch = tc % a.nc;
   const int64_t v0 = int64_t(ch) * a.chunk;
@@ -185,7 +242,24 @@ __global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
     const bool have_next = v + 1 < v1;
     if (have_next) fetch_site<NT>(a.S_u, a.S_d, a.s_c64, int64_t(t) * a.V + v + 1, pre);
     site_levels<KMIN, KMAX, NU, ND, QMAX, NT, C>(tu, td, tr, sOps, sS, sR, sSn, pre, have_next);
-    leaf_dispatch<1, MAXS>(nlive, B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
+    if constexpr (FACT) {
+      if (nlive) {
+        const C* sU = sW + n_src + 1;
+        C L = cmake<C>(0, 0);
+        for (int b = 0; b < B; ++b) {
+          const int4 mb = meta[b];
+          L = cmac(sU[b], sR[mb.y + dcol], L);
+          if (mb.z & 1) {
+            C p = cmul(L, fact_group<NE>(lnw, le, sW, sR + mb.x));
+            if (!dlive) p = cmake<C>(0, 0);
+            acc.add(p.x, p.y);
+            L = cmake<C>(0, 0);
+          }
+        }
+      }
+    } else {
+      leaf_dispatch<1, MAXS>(nlive, B, meta, sW, sR, n_src, sl, live, cu, cd, acc);
+    }
     if constexpr (!kOverlapLeaves) __syncthreads();
   }
 
@@ -231,12 +305,14 @@ __global__ void gather_w_kernel(const double2* __restrict__ Wu, const int64_t* _
 
 // One workgroup per (correlator, timeslice): strided per-thread compensated
 // sums in a fixed order, then a fixed-order tree.
-__global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__ corr, int T, int nc,
+// range: index of the correlator record's (first tile, end tile) pair of the
+// tiling the forward ran on.
+__global__ __launch_bounds__(256) void reduce_kernel(const int32_t* __restrict__ corr, int T, int nc, int range,
                                                      const double* __restrict__ partial,
                                                      double* __restrict__ C) {
   const int c = blockIdx.x / T, t = blockIdx.x % T;
   const int32_t* cr = corr + c * kCorrInts;
-  const int tb = cr[3], te = cr[4];
+  const int tb = cr[range], te = cr[range + 1];
   const int64_t n = int64_t(te - tb) * nc;
   CompAcc<double> acc;
   for (int64_t j = threadIdx.x; j < n; j += 256) {
@@ -269,11 +345,13 @@ constexpr int fwd_maxs(int nu, int nd) {
 constexpr int fwd_qmax(int nu, int nd) { return fwd_maxs(nu, nd) ? 1 : 0; }
 
 template <typename R, int NU, int ND, int MAXS, int QMAX>
-hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, bool fact, hipStream_t st) {
   static_assert(MAXS == fwd_maxs(NU, ND) && QMAX == fwd_qmax(NU, ND), "instantiation table");
   constexpr int NT = family_threads(NU, ND);
-  if ((p->h.max_src + NT - 1) / NT > MAXS || (p->h.max_ncol + NT - 1) / NT > QMAX) return hipErrorNotSupported;
-  auto k = fwd_kernel<R, NU, ND, MAXS, QMAX, NT>;
+  constexpr int MC = top_list_max(NU, ND);
+  if ((p->h.max_ncol + NT - 1) / NT > QMAX) return hipErrorNotSupported;
+  if (fact ? !p->h.fwd_fact : (p->h.max_src + NT - 1) / NT > MAXS) return hipErrorNotSupported;
+  auto k = fact ? fwd_kernel<R, NU, ND, MAXS, QMAX, NT, true, MC> : fwd_kernel<R, NU, ND, MAXS, QMAX, NT, false, MC>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
@@ -283,12 +361,12 @@ hipError_t launch_fwd_t(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t
 
 // Instantiated shapes: proton (2,1), neutron (1,2), dinucleon (3,3), 3He (5,4).
 template <typename R>
-hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, hipStream_t st) {
+hipError_t launch_fwd_r(const mbc_plan* p, const FwdArgs& a, int nblocks, size_t lds, bool fact, hipStream_t st) {
   const int nu = p->h.n_u, nd = p->h.n_d;
-  if (nu == 2 && nd == 1) return launch_fwd_t<R, 2, 1, 1, 1>(p, a, nblocks, lds, st);
-  if (nu == 1 && nd == 2) return launch_fwd_t<R, 1, 2, 1, 1>(p, a, nblocks, lds, st);
-  if (nu == 3 && nd == 3) return launch_fwd_t<R, 3, 3, 4, 1>(p, a, nblocks, lds, st);
-  if (nu == 5 && nd == 4) return launch_fwd_t<R, 5, 4, 4, 1>(p, a, nblocks, lds, st);
+  if (nu == 2 && nd == 1) return launch_fwd_t<R, 2, 1, 1, 1>(p, a, nblocks, lds, fact, st);
+  if (nu == 1 && nd == 2) return launch_fwd_t<R, 1, 2, 1, 1>(p, a, nblocks, lds, fact, st);
+  if (nu == 3 && nd == 3) return launch_fwd_t<R, 3, 3, 4, 1>(p, a, nblocks, lds, fact, st);
+  if (nu == 5 && nd == 4) return launch_fwd_t<R, 5, 4, 4, 1>(p, a, nblocks, lds, fact, st);
   return hipErrorNotSupported;
 }
 
@@ -313,13 +391,13 @@ bool forward_supports(const PlanHost& h, std::string* why) {
   return true;
 }
 
-Launch forward_launch_shape(const PlanHost& h, int T, int64_t V) {
+Launch forward_launch_shape(const PlanHost& h, int T, int64_t V, bool fact) {
   Launch L;
   L.T = T;
   L.V = V;
   // about 16k workgroups in flight over the grid, at least 1 site each
   const double target = 16384.0;
-  const double total = double(T) * double(V) * std::max(1, h.n_tiles);
+  const double total = double(T) * double(V) * std::max(1, fact ? h.f_n_tiles : h.n_tiles);
   int64_t chunk = int64_t(total / target);
   if (chunk < 1) chunk = 1;
   if (chunk > V) chunk = V;
@@ -344,13 +422,17 @@ hipError_t launch_gather_w(const mbc_plan* p, const double* W_user, void* W_plan
 }
 
 hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64,
-                          const Launch& L, const void* W_plan, double* partial, hipStream_t st) {
-  if (p->h.n_tiles == 0) return hipSuccess;
+                          const Launch& L, const void* W_plan, double* partial, bool fact, hipStream_t st) {
+  const int n_tiles = fact ? p->h.f_n_tiles : p->h.n_tiles;
+  if (n_tiles == 0) return hipSuccess;
   FwdArgs a;
   a.corr = p->d.corr;
-  a.tiles = p->d.tiles;
-  a.ops = p->d.ops;
-  a.meta = p->d.meta;
+  a.tiles = fact ? p->d.f_tiles : p->d.tiles;
+  a.ops = fact ? p->d.f_ops : p->d.ops;
+  a.meta = fact ? p->d.f_meta : p->d.meta;
+  a.wu = p->d.wu;
+  a.wv = p->d.wv;
+  a.btab = p->d.btab;
   a.src_cu = p->d.src_cu;
   a.src_cd = p->d.src_cd;
   a.tabs = p->d.tabs;
@@ -358,24 +440,24 @@ hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, i
   a.S_u = S_u;
   a.S_d = S_d;
   a.s_c64 = s_c64;
-  a.n_tiles = p->h.n_tiles;
+  a.n_tiles = n_tiles;
   a.T = L.T;
   a.V = L.V;
   a.chunk = L.chunk;
   a.nc = L.nc;
   a.partial = partial;
-  const int64_t nb = int64_t(p->h.n_tiles) * L.T * L.nc;
+  const int64_t nb = int64_t(n_tiles) * L.T * L.nc;
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t lds = size_t(p->h.lds_bytes);
-  if (p->h.precision == MBC_F64) return launch_fwd_r<double>(p, a, int(nb), lds, st);
-  return launch_fwd_r<float>(p, a, int(nb), lds, st);
+  const size_t lds = size_t(fact ? p->h.f_lds_fwd : p->h.lds_bytes);
+  if (p->h.precision == MBC_F64) return launch_fwd_r<double>(p, a, int(nb), lds, fact, st);
+  return launch_fwd_r<float>(p, a, int(nb), lds, fact, st);
 }
 
-hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
+hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C, bool fact,
                          hipStream_t st) {
   const int nb = p->h.n_corr * L.T;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, st, p->d.corr, L.T, L.nc, partial, C);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(256), 0, st, p->d.corr, L.T, L.nc, fact ? 33 : 3, partial, C);
   return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ struct Launch {
   int nc = 1;        // chunks per timeslice
 };
 
-Launch forward_launch_shape(const PlanHost& h, int T, int64_t V);
+// fact: the factored forward on the f_* tiles (the exact weights, h.fwd_fact).
+Launch forward_launch_shape(const PlanHost& h, int T, int64_t V, bool fact);
 
 // Whether the kernels are instantiated for a compiled plan's family and
 // sizes (source keys per thread, columns per level, dW keys per tile, dS
@@ -28,12 +29,16 @@ bool backward_supports(const PlanHost& h, std::string* why);
 // W_plan[i] = W_user[perm[i]] in the plan's precision.
 hipError_t launch_gather_w(const mbc_plan* p, const double* W_user, void* W_plan, hipStream_t st);
 
-// Per-tile, per-chunk partial sums of the correlator: partial[tile][T][nc] complex128.
+// Per-tile, per-chunk partial sums of the correlator: partial[tile][T][nc]
+// complex128.  fact: the exact weights through their sink and source factors
+// on the f_* tiles (requires h.fwd_fact; W_plan unused); otherwise W_plan on
+// the forward tiles.
 hipError_t launch_forward(const mbc_plan* p, const void* S_u, const void* S_d, int s_c64,
-                          const Launch& L, const void* W_plan, double* partial, hipStream_t st);
+                          const Launch& L, const void* W_plan, double* partial, bool fact, hipStream_t st);
 
-// C[corr][t] = fixed-order FP64 sum of the partials of the correlator's tiles.
-hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C,
+// C[corr][t] = fixed-order FP64 sum of the partials of the correlator's tiles
+// (of the tiling launch_forward ran on).
+hipError_t launch_reduce(const mbc_plan* p, const Launch& L, const double* partial, double* C, bool fact,
                          hipStream_t st);
 
 // Size of the fixed per-device scratch array behind mbc_contract_noalloc,

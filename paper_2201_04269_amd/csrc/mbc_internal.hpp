@@ -230,6 +230,10 @@ constexpr int dw_keys_per_tile(int n_u, int n_d, int precision) {
 }
 constexpr int dw_src_per_thread(int n_u, int n_d) { return n_u + n_d >= 8 ? 3 : (n_u + n_d >= 6 ? 3 : 1); }
 
+// Longest source-key list of a top column (source keys sharing their u or d
+// tuple) the factored forward and the dS kernels are built for, per family.
+constexpr int top_list_max(int n_u, int n_d) { return n_u + n_d >= 8 ? 10 : (n_u + n_d >= 6 ? 6 : 2); }
+
 struct PlanHost {
   int n_u = 0, n_d = 0, n_corr = 0, precision = MBC_F64;
   int64_t nnz = 0;
@@ -251,10 +255,14 @@ struct PlanHost {
   std::vector<int32_t> w_tiles, w_ops, w_meta;
   int max_csr = 0;       // longest source-key list of a top column
   int max_bin[7] = {0, 0, 0, 0, 0, 0, 0};  // longest j-list per level
-  // factored dS tiling (used for the exact weights when rank1)
+  // factored tiling (the exact weights when rank1): dS of the families
+  // ds_factored admits, and the factored forward (fwd_fact)
   bool rank1 = false;
   int f_n_tiles = 0, f_max_ops = 0, f_max_b = 0;
   int64_t f_lds_ds = 0;
+  bool fwd_fact = false;     // the forward of the exact weights runs factored on the f_* tiles
+  int64_t f_lds_fwd = 0;     // its dynamic LDS
+  double fact_alg_flops_per_site = 0, fact_ds_alg_flops_per_site = 0;
   std::vector<int32_t> f_tiles, f_ops, f_meta, f_extra;
   std::vector<double> wu, wv;     // (re, im): sink factor [sum n_snk], source factor [sum n_src]
   std::vector<uint16_t> tabs;

@@ -530,7 +530,7 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
   P.w_exact.assign(size_t(2 * P.nnz), 0.0);
   P.perm.assign(size_t(P.nnz), 0);
   int64_t w_pos = 0;
-  double alg = 0, exec = 0, ds_alg = 0, dw_alg = 0;
+  double alg = 0, exec = 0, ds_alg = 0, dw_alg = 0, fact_alg = 0, fact_ds_alg = 0;
   TileSetOut fo{&P.tiles, &P.ops, &P.meta, nullptr, &P.n_tiles, &P.max_ops, &P.max_b, &exec};
   TileSetOut bo{&P.b_tiles, &P.b_ops, &P.b_meta, &P.b_extra, &P.b_n_tiles, &P.b_max_ops, &P.b_max_b, nullptr};
   TileSetOut wo{&P.w_tiles, &P.w_ops, &P.w_meta, nullptr, &P.w_n_tiles, &P.w_max_ops, &P.w_max_b, nullptr};
@@ -697,6 +697,13 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
       for (auto& kk : X.snk) ru.insert(kk.first);
       for (auto& kk : X.src) cu.insert(kk.first);
       alg += 8.0 * double(X.n_snk) * X.n_src + 8.0 * double(ru.size()) * cu.size();
+      // factored weights, per run (distinct u-tuple): L[c_d] = sum_b u[b] Dd,
+      // H[c_d] = sum_s v[s] Du, and sum_c_d L H (forward); the u-leaf adjoints
+      // take one product per entry and one per (run, source key), the d-leaf
+      // adjoints H per run and u[b] H per (key, d column) (dS)
+      const double nru = double(ru.size()), ncd = double(X.ncol(1, X.nf[1]));
+      fact_alg += minors + 8.0 * (double(X.n_snk) * ncd + nru * X.n_src + nru * ncd);
+      fact_ds_alg += minors + rev + 8.0 * (double(X.n_snk) * X.n_src + 2.0 * nru * X.n_src + double(X.n_snk) * ncd);
     }
 
     auto ft = make_tiles(X, budget, kMaxB, fwd_model);
@@ -707,7 +714,7 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     cr[7] = P.b_n_tiles;
     auto wt = make_tiles(X, budget, dw_keys, dw_model);
     P.b_lds_dw = std::max(P.b_lds_dw, emit_tiles(X, wt, dw_model, wo));
-    if (ds_factored(s.n_u, s.n_d, precision)) {
+    {
       auto ftl = make_tiles(X, bbudget, kMaxB, bwdf_model);
       P.f_lds_ds = std::max(P.f_lds_ds, emit_tiles(X, ftl, bwdf_model, fo2));
     }
@@ -720,6 +727,25 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     for (int f = 0; f < 2; ++f)
       for (int k = 1; k <= 6; ++k) P.max_bin[k] = std::max(P.max_bin[k], int(cr[82 + 6 * f + k - 1]));
   }
+  // the factored forward on the f_* tiles: S, the source factors (and a zero
+  // behind them), the tile's sink factors, rows, op records and key records;
+  // one top d column per thread, lists within the kernels' limit
+  int max_ncd = 0;
+  for (int c = 0; c < s.n_corr; ++c) {
+    const int32_t* cr = &P.corr[size_t(c) * kCorrInts];
+    max_ncd = std::max(max_ncd, int(cr[8 + 2 * (6 + s.n_d - 1)]));
+    for (int t = cr[33]; t < cr[34]; ++t) {
+      const int32_t* tr = &P.f_tiles[size_t(t) * kTileInts];
+      const int64_t bytes = (576 + int64_t(cr[0]) + 1 + tr[1] + tr[6]) * csz;
+      P.f_lds_fwd = std::max(P.f_lds_fwd, ((bytes + 15) & ~int64_t(15)) + int64_t(tr[4]) * 16 + int64_t(tr[1]) * 16);
+    }
+  }
+  int max_dlist = 0;
+  for (int c = 0; c < s.n_corr; ++c) max_dlist = std::max(max_dlist, int(P.corr[size_t(c) * kCorrInts + 81]));
+  P.fwd_fact = P.rank1 && P.f_n_tiles > 0 && max_ncd <= P.threads && max_dlist <= top_list_max(s.n_u, s.n_d) &&
+               P.max_src < 2048 && P.f_lds_fwd <= 160 * 1024;
+  P.fact_alg_flops_per_site = fact_alg;
+  P.fact_ds_alg_flops_per_site = fact_ds_alg;
   P.alg_flops_per_site = alg;
   P.exec_flops_per_site = exec;
   P.ds_alg_flops_per_site = ds_alg;
