@@ -307,11 +307,12 @@ mbc_status debug_backward(const mbc_index_set* s, int precision, const double* S
             for (int c = 0; c < ncp; ++c) {
               cd sum(0, 0);
               for (int ci = 0; ci < p[6]; ++ci) {
-                const int32_t* ch = op(child[p[5] + ci]);
+                const int ce = child[p[5] + ci];  // child row: slot << 4 | r0
+                const int ch_slot = ce >> 4, ch_r0 = ce & 15;
                 for (int j = 0; j < 12; ++j) {
                   const int ent = (ut[6 * c + j / 2] >> (16 * (j % 2))) & 0xffff;
                   if (ent == 0xffff) continue;
-                  const cd term = A[ch[4] + (ent & 4095)] * Sf[12 * ch[2] + j];
+                  const cd term = A[ch_slot + (ent & 4095)] * Sf[12 * ch_r0 + j];
                   sum += ((ent >> 12) & 1) ? -term : term;
                 }
               }

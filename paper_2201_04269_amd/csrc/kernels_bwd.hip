@@ -578,23 +578,22 @@ __device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o
   }
 }
 
+// One child row's terms of a parent column: sum over the first nw up entries
+// (superset C' + j: its index in the child row, the parity of j's position,
+// j) of (-1)^pos S[r0, j] A_K(child, C' + j); ce = child slot << 4 | r0.
 template <int KP, typename C>
-__device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int nw, int4 ox, const int4* sOpv,
-                                        const int32_t* children, const C* Sf, const C* sA) {
+__device__ __forceinline__ C child_terms(const unsigned (&up)[6], int nw, int ce, const C* Sf, const C* sA) {
+  const C* srow = Sf + 12 * (ce & 15);
+  const C* arow = sA + (ce >> 4);
   C sum = cmake<C>(0, 0);
-  const int nch = ox.w & 0xffff;
-  for (int ci = 0; ci < nch; ++ci) {
-    const int4 chv = sOpv[children[ox.z + ci]];
-    const C* srow = Sf + 12 * chv.x;
 #pragma unroll
-    for (int m0 = 0; m0 < up_len(KP); m0 += kUpStep) {
-      if (m0 < nw) {  // entries past a lane's count read the zero element
+  for (int m0 = 0; m0 < up_len(KP); m0 += kUpStep) {
+    if (m0 < nw) {  // entries past a lane's count read the zero element
 #pragma unroll
-        for (int m = m0; m < m0 + kUpStep && m < up_len(KP); ++m) {
-          const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
-          const C av = sA[chv.z + int(ent & 2047u)];
-          sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
-        }
+      for (int m = m0; m < m0 + kUpStep && m < up_len(KP); ++m) {
+        const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+        const C av = arow[int(ent & 2047u)];
+        sum = cmac(cneg_if(av, int((ent >> 11) & 1u)), srow[ent >> 12], sum);
       }
     }
   }
@@ -603,6 +602,7 @@ __device__ __forceinline__ C parent_sum(const unsigned (&up)[6], int nw, int4 ox
 
 // (i) adjoints of the parents of level K-1 (real rows; S rows for K = 2):
 // A_{K-1}(C') = sum over children, over j not in C', of (-1)^pos S[r0, j] A_K(C' + j).
+// The first child (most parents have one) is summed straight-line.
 template <int K, int QMAX, int NT, typename C>
 __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, int p0, int pcnt, const int4* sOpx,
                                             const int4* sOpv, const int32_t* children, const C* Sf, C* sA,
@@ -610,13 +610,20 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, in
   if (ut.g >= ut.G) return;
   for (int p = p0 + ut.g; p < p0 + pcnt; p += ut.G) {
     const int4 ox = sOpx[p];
-    if ((ox.w & 0xffff) == 0) continue;  // a top row
+    const int nch = ox.w & 0xffff;
+    if (nch == 0) continue;  // a top row: its adjoint came from the leaves
     const int4 ov = sOpv[p];
+    const int c1 = children[ox.z];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
       const int c = ut.col[q];
       if (c < ut.ncol) {
-        const C sum = parent_sum<K - 1>(ut.up[q], ut.nw[q], ox, sOpv, children, Sf, sA);
+        C sum = child_terms<K - 1>(ut.up[q], ut.nw[q], c1, Sf, sA);
+        for (int ci = 1; ci < nch; ++ci) {
+          const C t = child_terms<K - 1>(ut.up[q], ut.nw[q], children[ox.z + ci], Sf, sA);
+          sum.x += t.x;
+          sum.y += t.y;
+        }
         if (K == 2)
           sAdj1[ov.z + ut.colnum[q]] = sum;
         else

@@ -167,7 +167,8 @@ bool block_multiplicities(const mbc_block_corr_desc& c, int64_t max_terms, int64
 //   [17] virt_begin [18] n_virt  (backward tiles) level-1 parent records
 //   [19] extra_off   (backward tiles) offset in b_extra of: n_runs, n_dgroups,
 //        rsum_off, then runs (u_slot, b_begin, b_end), d-groups (d_slot, b
-//        mask), the children lists of the ops, and at rsum_off the S-bar row
+//        mask), the children lists of the ops (each child row as its slot << 4
+//        | its first row r0), and at rsum_off the S-bar row
 //        lists: 25 relative pointers over the 24 (flavour, S row) pairs, then
 //        the records (rows and level-1 parents) whose adjoint lands in that row
 //   [15] extra_len   (backward tiles) ints of that extra block

@@ -342,7 +342,9 @@ int64_t emit_tiles(const CorrCtx& X, const std::vector<std::vector<int>>& tiles,
       o.extra->push_back(int32_t(3 + runs.size() + dgs.size() + nchild));  // offset of the S-bar row lists
       o.extra->insert(o.extra->end(), runs.begin(), runs.end());
       o.extra->insert(o.extra->end(), dgs.begin(), dgs.end());
-      for (auto& ch : children) o.extra->insert(o.extra->end(), ch.begin(), ch.end());
+      // children as (row slot << 4 | first row r0), what the parent sums read
+      for (auto& ch : children)
+        for (int ci : ch) o.extra->push_back(int32_t(slot.at(order[size_t(ci)]) << 4) | order[size_t(ci)].t.v[0]);
       int32_t acc = 25;
       for (int q = 0; q < 24; ++q) {
         o.extra->push_back(acc);
