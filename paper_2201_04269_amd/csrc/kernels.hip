@@ -136,7 +136,7 @@ __device__ __forceinline__ C fact_group(int nw, const int (&e)[MC], const C* sV,
 }
 
 template <typename R, int NU, int ND, int MAXS, int QMAX, int NT, bool FACT, int MC>
-__global__ __launch_bounds__(NT) void fwd_kernel(FwdArgs a) {
+__global__ __launch_bounds__(NT, (FACT && NT >= 512 && sizeof(R) == 4) ? 4 : 1) void fwd_kernel(FwdArgs a) {
   using C = typename cx<R>::T;
   constexpr int KMIN = (NU == 1 || ND == 1) ? 1 : 2;
   constexpr int KMAX = NU > ND ? NU : ND;
