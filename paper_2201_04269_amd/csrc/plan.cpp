@@ -145,7 +145,7 @@ struct LdsModel {
   bool backward;  // dS kernel (rows carry a zero element, adjoint rows)
   int csz;
   bool with_w = true;     // forward: the tile's weights are staged (not for dW)
-  bool factored = false;  // dS: the n_src + B weight factors instead of B x n_src weights
+  bool factored = false;  // the n_src + B weight factors instead of B x n_src weights
   int64_t weights(int B, int n_src) const { return factored ? int64_t(n_src) + B : int64_t(B) * n_src; }
   int64_t operator()(int B, int n_src, int64_t row_units, int n_ops, int n_virt, int64_t n_child) const {
     if (!backward) {
@@ -717,7 +717,12 @@ void compile_plan(const IndexSet& s, int precision, PlanHost* out) {
     auto wt = make_tiles(X, budget, dw_keys, dw_model);
     P.b_lds_dw = std::max(P.b_lds_dw, emit_tiles(X, wt, dw_model, wo));
     {
-      auto ftl = make_tiles(X, bbudget, kMaxB, bwdf_model);
+      // the factored tiles serve the factored dS where ds_factored admits it,
+      // else only the factored forward, and are then sized for its LDS
+      // (D_I F32C: 139 tiles of at most 25 KB, five workgroups per CU)
+      const bool for_ds = ds_factored(s.n_u, s.n_d, precision);
+      const LdsModel ffwd_model{false, csz, true, true};
+      auto ftl = for_ds ? make_tiles(X, bbudget, kMaxB, bwdf_model) : make_tiles(X, budget, kMaxB, ffwd_model);
       P.f_lds_ds = std::max(P.f_lds_ds, emit_tiles(X, ftl, bwdf_model, fo2));
     }
     cr[34] = P.f_n_tiles;
