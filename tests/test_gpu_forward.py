@@ -76,6 +76,27 @@ def test_forward_f32c_within_bound(name):
     assert np.all(err <= tol_f32c(A, rs.nu, rs.nd))
 
 
+@pytest.mark.parametrize("name", ["DI_2x2x2x2_su3", "He3_batch"])
+@pytest.mark.parametrize("precision", ["f64", "f32c"])
+def test_factored_and_unfactored_schedules_agree(name, precision):
+    """The exact weights (W = None) take the factored forward; the same
+    weights passed as a user W take the unfactored one. Both must give the
+    oracle's correlator within the precision's bound, and each other."""
+    ods, gen = CASES[name]
+    Su, Sd = gen()
+    rs = O.build_index_set(ods)
+    Cf, plan = run(ods, Su, Sd, precision)
+    assert plan.stats["fwd_factored"] == 1 and plan.stats["rank1"] == 1
+    Cu, _ = run(ods, Su, Sd, precision, W=np.asarray(rs.weights(), dtype=np.complex128))
+    ref, A, _ = oracle(ods, Su, Sd)
+    tol = tol_f64(ref, A, rs.nu, rs.nd) if precision == "f64" else tol_f32c(A, rs.nu, rs.nd)
+    print(name, precision, "factored vs unfactored max |diff|/A",
+          float(np.max(np.abs(Cf - Cu) / np.maximum(A, 1e-300))))
+    assert np.all(np.abs(Cf - ref) <= tol)
+    assert np.all(np.abs(Cu - ref) <= tol)
+    assert np.all(np.abs(Cf - Cu) <= 2 * tol)
+
+
 def test_empty_index_set_gives_zero():
     Su, Sd = synth.iid(3, 2, seed=9)
     C, plan = run([dict(op="DII"), dict(op="DII", snk_spin=1)], Su, Sd, "f64")
