@@ -124,16 +124,23 @@ def host_walk(ods, Su, Sd, W=None, precision=B.F64):
     [dict(op="DI")],
     [dict(op="DI"), dict(op="DII", sign_mode="r2"), dict(op="DII")],
     [dict(op="HE3_I", snk_spin=2, src_spin=2), dict(op="HE3_II", snk_spin=0, src_spin=0, sign_mode="r2")],
-], ids=["proton", "p+n", "DI", "DI+DII", "He3"])
+    [dict(op="neutron", snk_spin=1, src_spin=1)],
+], ids=["proton", "p+n", "DI", "DI+DII", "He3", "neutron"])
 def test_plan_walk_matches_oracle(ods):
+    """W = NULL walks the factored forward (every correlator's exact weights
+    are a sink vector times a source vector: per run, sum over top d columns
+    of (sum_b u[b] Dd) (sum_s v[s] Du)); the same weights passed explicitly
+    walk the forward tiles that stage the weights. Both against the oracle."""
     Su, Sd = synth.iid(2, 1, seed=17)
-    C, st = host_walk(ods, Su, Sd)
     ref_set = O.build_index_set(ods)
     ref = CO.correlator(Su, Sd, ref_set)
     A = CO.sum_abs_terms(Su, Sd, ref_set) if ref_set.nnz < 300000 else None
     scale = A if A is not None else np.abs(ref) + 1.0
-    assert np.all(np.abs(C - ref) <= 1e-12 * np.maximum(scale, 1e-300) + 1e-300), (C, ref)
-    assert st.n_tiles >= 1
+    for W in (None, ref_set.weights()):
+        C, st = host_walk(ods, Su, Sd, W)
+        assert np.all(np.abs(C - ref) <= 1e-12 * np.maximum(scale, 1e-300) + 1e-300), (C, ref, W is None)
+    assert st.rank1 == 1 and st.fwd_factored == 1
+    assert st.n_tiles >= 1 and st.f_n_tiles >= 1
     assert st.exec_flops_per_site >= st.alg_flops_per_site * 0.5
 
 
