@@ -390,24 +390,25 @@ struct CsrTab {
 };
 
 // Leaf adjoint of one top column: sum over the group's sink keys b and the
-// first nw entries (s, oc) of the column's source-key list (nw: the wave's
-// longest list, uniform; padded entries read the zero element) of
+// first NM entries (s, oc) of the column's source-key list of
 // W[b, s] * (other flavour's top minor at b's row slot, column oc).  The u
 // leaves take the run [lo, hi) and the d slots of its keys; the d leaves take
 // the sink keys in the bit mask lo and their u slots.
-template <int MC, bool MASK, typename C>
-__device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
-                                      const C* sR, const int2* sMeta) {
+template <int NM, int MC, bool MASK, typename C>
+__device__ __forceinline__ C leaf_terms(const int (&e)[MC], int lo, int hi, const C* sW, int n_src, const C* sR,
+                                        const int2* sMeta) {
   C sum = cmake<C>(0, 0);
+  int sidx[NM], oc[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    sidx[m] = e[m] & 2047;
+    oc[m] = e[m] >> 11;
+  }
   auto key = [&](int b) {
     const C* wrow = sW + b * n_src;
     const C* orow = sR + (MASK ? sMeta[b].x : sMeta[b].y);
 #pragma unroll
-    for (int m0 = 0; m0 < MC; m0 += 2)
-      if (m0 < nw) {
-#pragma unroll
-        for (int m = m0; m < m0 + 2 && m < MC; ++m) sum = cmac(wrow[e[m] & 2047], orow[e[m] >> 11], sum);
-      }
+    for (int m = 0; m < NM; ++m) sum = cmac(wrow[sidx[m]], orow[oc[m]], sum);
   };
   if constexpr (MASK) {
     for (int mm = lo; mm; mm &= mm - 1) key(__ffs(mm) - 1);
@@ -415,6 +416,22 @@ __device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi
     for (int b = lo; b < hi; ++b) key(b);
   }
   return sum;
+}
+
+// Dispatch on the wave's longest list (nw, uniform), in steps of two entries;
+// the padded entries of shorter lists read the zero element.  (This form
+// keeps all of a key's loads in flight; the factored leaves below use
+// predicated steps instead, where this dispatch was compiled into loops
+// indexing their entry arrays in scratch memory.)
+template <int N, int MC, bool MASK, typename C>
+__device__ __forceinline__ C leaf_sum(int nw, const int (&e)[MC], int lo, int hi, const C* sW, int n_src,
+                                      const C* sR, const int2* sMeta) {
+  if constexpr (N >= MC) {
+    return leaf_terms<MC, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
+  } else {
+    if (nw <= N) return leaf_terms<N, MC, MASK>(e, lo, hi, sW, n_src, sR, sMeta);
+    return leaf_sum<N + 2, MC, MASK>(nw, e, lo, hi, sW, n_src, sR, sMeta);
+  }
 }
 
 // Factored weights W[b, s] = u[b] v[s] (v = sW[0, n_src), u = sW[n_src, n_src + B)).
@@ -581,14 +598,14 @@ __device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o
 // One child row's terms of a parent column: sum over the first nw up entries
 // (superset C' + j: its index in the child row, the parity of j's position,
 // j) of (-1)^pos S[r0, j] A_K(child, C' + j); ce = child slot << 4 | r0.
-template <int KP, typename C>
+template <int KP, bool BOUND, typename C>
 __device__ __forceinline__ C child_terms(const unsigned (&up)[6], int nw, int ce, const C* Sf, const C* sA) {
   const C* srow = Sf + 12 * (ce & 15);
   const C* arow = sA + (ce >> 4);
   C sum = cmake<C>(0, 0);
 #pragma unroll
   for (int m0 = 0; m0 < up_len(KP); m0 += kUpStep) {
-    if (m0 < nw) {  // entries past a lane's count read the zero element
+    if (!BOUND || m0 < nw) {  // entries past a lane's count read the zero element
 #pragma unroll
       for (int m = m0; m < m0 + kUpStep && m < up_len(KP); ++m) {
         const unsigned ent = (up[m >> 1] >> (16 * (m & 1))) & 0xffffu;
@@ -603,7 +620,7 @@ __device__ __forceinline__ C child_terms(const unsigned (&up)[6], int nw, int ce
 // (i) adjoints of the parents of level K-1 (real rows; S rows for K = 2):
 // A_{K-1}(C') = sum over children, over j not in C', of (-1)^pos S[r0, j] A_K(C' + j).
 // The first child (most parents have one) is summed straight-line.
-template <int K, int QMAX, int NT, typename C>
+template <int K, bool BOUND, int QMAX, int NT, typename C>
 __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, int p0, int pcnt, const int4* sOpx,
                                             const int4* sOpv, const int32_t* children, const C* Sf, C* sA,
                                             C* sAdj1) {
@@ -618,9 +635,9 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, in
     for (int q = 0; q < QMAX; ++q) {
       const int c = ut.col[q];
       if (c < ut.ncol) {
-        C sum = child_terms<K - 1>(ut.up[q], ut.nw[q], c1, Sf, sA);
+        C sum = child_terms<K - 1, BOUND>(ut.up[q], ut.nw[q], c1, Sf, sA);
         for (int ci = 1; ci < nch; ++ci) {
-          const C t = child_terms<K - 1>(ut.up[q], ut.nw[q], children[ox.z + ci], Sf, sA);
+          const C t = child_terms<K - 1, BOUND>(ut.up[q], ut.nw[q], children[ox.z + ci], Sf, sA);
           sum.x += t.x;
           sum.y += t.y;
         }
@@ -633,7 +650,7 @@ __device__ __forceinline__ void rev_parents(const UpTab<K - 1, QMAX, NT>& ut, in
   }
 }
 
-template <int K, int NU, int ND, int QMAX, int NT, typename C>
+template <int K, bool BOUND, int NU, int ND, int QMAX, int NT, typename C>
 __device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX, NT>& ru, const RevTabs<ND, QMAX, NT>& rd,
                                            const int32_t* tr, const int4* sOpx, const int4* sOpv,
                                            const int32_t* children, const C* sS, const C* sR, C* sA, C* sAdj1,
@@ -648,16 +665,16 @@ __device__ __forceinline__ void rev_levels(const RevTabs<NU, QMAX, NT>& ru, cons
       if constexpr (K <= NU) {
         const int p0 = (K == 2) ? tr[17] : tr[20 + 2 * (K - 1)];
         const int pc = (K == 2) ? tr[14] : tr[21 + 2 * (K - 1)];
-        rev_parents<K>(ups_of<K - 1>(ru), p0, pc, sOpx, sOpv, children, sS, sA, sAdj1);
+        rev_parents<K, BOUND>(ups_of<K - 1>(ru), p0, pc, sOpx, sOpv, children, sS, sA, sAdj1);
       }
       if constexpr (K <= ND) {
         const int p0 = (K == 2) ? tr[17] + tr[14] : tr[20 + 2 * (7 + K - 1)];
         const int pc = (K == 2) ? tr[18] - tr[14] : tr[21 + 2 * (7 + K - 1)];
-        rev_parents<K>(ups_of<K - 1>(rd), p0, pc, sOpx, sOpv, children, sS + 144, sA, sAdj1);
+        rev_parents<K, BOUND>(ups_of<K - 1>(rd), p0, pc, sOpx, sOpv, children, sS + 144, sA, sAdj1);
       }
     }
     __syncthreads();
-    rev_levels<K - 1, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
+    rev_levels<K - 1, BOUND, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
   }
 }
 
@@ -796,7 +813,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_u + NT * q;
           if (c < cu_tab.ncol) {
-            const C sum = leaf_sum<MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<2, MC, false>(cu_tab.nw[q], cu_tab.e[q], b0, b1, sW, n_src, sR, sMeta);
             sA[us + c] = cmul(gbar, sum);
           }
         }
@@ -807,7 +824,7 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
         for (int q = 0; q < QMAX; ++q) {
           const int c = vt_d + NT * q;
           if (c < cd_tab.ncol) {
-            const C sum = leaf_sum<MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
+            const C sum = leaf_sum<2, MC, true>(cd_tab.nw[q], cd_tab.e[q], mask, 0, sW, n_src, sR, sMeta);
             sA[ds + c] = cmul(gbar, sum);
           }
         }
@@ -817,7 +834,11 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
 
     const int32_t* children = sEx + 3 + 3 * sEx[0] + 2 * sEx[1];
     const int32_t* rsum = sEx + sEx[2];
-    rev_levels<KMAX, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
+    // the wave's superset count bounds the parent sums, except in the
+    // unfactored schedule of the small families, which measured faster
+    // running every padded entry (D_I F32C)
+    constexpr bool kBound = FACT || (NU + ND >= 8);
+    rev_levels<KMAX, kBound, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
 
     // fixed-order accumulation of this tile's S-bar contributions
 #pragma unroll
