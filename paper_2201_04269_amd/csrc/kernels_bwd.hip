@@ -835,9 +835,11 @@ __global__ __launch_bounds__(NT) void ds_kernel(BwdArgs a) {
     const int32_t* children = sEx + 3 + 3 * sEx[0] + 2 * sEx[1];
     const int32_t* rsum = sEx + sEx[2];
     // the wave's superset count bounds the parent sums, except in the
-    // unfactored schedule of the small families, which measured faster
-    // running every padded entry (D_I F32C)
-    constexpr bool kBound = FACT || (NU + ND >= 8);
+    // unfactored FP32-comp schedule of the dinucleons, which measured faster
+    // running every padded entry (D_I F32C 310 vs 333 ms; in FP64, and for
+    // the proton and neutron, the unbounded sums take registers enough to
+    // cost waves per SIMD)
+    constexpr bool kBound = FACT || (NU + ND != 6) || std::is_same<R, double>::value;
     rev_levels<KMAX, kBound, NU, ND, QMAX, NT, C>(ru, rd, tr, sOpx, sOpv, children, sS, sR, sA, sAdj1, sPart);
 
     // fixed-order accumulation of this tile's S-bar contributions
