@@ -295,8 +295,9 @@ struct BinTab {
 __host__ __device__ constexpr int up_len(int k) { return 12 - k; }
 
 // Parent-table entries per uniform bound check: the loads of a step issue
-// together.
-constexpr int kUpStep = 4;
+// together (a level-K parent column has up to 12 - K entries: two steps of
+// six for K <= 5).
+constexpr int kUpStep = 6;
 
 template <int K, int QMAX, int NT>
 struct UpTab {
