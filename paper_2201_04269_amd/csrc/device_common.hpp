@@ -94,6 +94,13 @@ __device__ __forceinline__ float row16_sum(float x) {
   x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x121, 0xf, 0xf, false));
   return x;
 }
+// Sum of the two 16-lane rows of each 32-lane half of the wave, valid in the
+// upper row of the half (lanes 16..31 and 48..63) once every lane holds its
+// row's sum: row_bcast:15 hands lane 15 of rows 0 and 2 to rows 1 and 3
+// (row mask 0b1010; the lower rows keep their own sum).
+__device__ __forceinline__ float upper_row_pair_sum(float x) {
+  return x + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x142, 0xa, 0xf, false));
+}
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const long long v = __builtin_bit_cast(long long, x);
@@ -107,6 +114,12 @@ __device__ __forceinline__ double row16_sum(double x) {
   x += dpp_f64<0x122>(x);
   x += dpp_f64<0x121>(x);
   return x;
+}
+__device__ __forceinline__ double upper_row_pair_sum(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(v & 0xffffffff), 0x142, 0xa, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(v >> 32), 0x142, 0xa, 0xf, false);
+  return x + __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
 // Negates a complex value when `odd` is 1 (flips both sign bits).

@@ -584,13 +584,15 @@ __device__ __forceinline__ void rev_part(const BinTab<K, NT>& bt, int tid, int o
         s1.x = row16_sum(s1.x);
         s1.y = row16_sum(s1.y);
       }
-      if constexpr (L == 32) {  // the two 16-lane rows of a bin (aligned halves of the wave)
-        s0.x += __shfl_xor(s0.x, 16);
-        s0.y += __shfl_xor(s0.y, 16);
-        s1.x += __shfl_xor(s1.x, 16);
-        s1.y += __shfl_xor(s1.y, 16);
+      // 32-lane bins are aligned halves of the wave: the upper 16-lane row
+      // adds the lower row's sum and its first lane writes
+      if constexpr (L == 32) {
+        s0.x = upper_row_pair_sum(s0.x);
+        s0.y = upper_row_pair_sum(s0.y);
+        s1.x = upper_row_pair_sum(s1.x);
+        s1.y = upper_row_pair_sum(s1.y);
       }
-      if (lt % L == 0) {
+      if (lt % L == (L == 32 ? 16 : 0)) {
         sPart[12 * o + lt / L] = s0;
         if (two) sPart[12 * (o + 1) + lt / L] = s1;
       }
