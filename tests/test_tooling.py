@@ -26,6 +26,18 @@ def test_source_hash_is_stable_and_tracks_sources():
     int(h, 16)
 
 
+def test_build_compiles_every_source_and_hashes_its_flags(monkeypatch):
+    """Every C++/HIP source is a unit of the library; the per-source flags
+    (the dS scheduling strategy) name units that exist and enter the hash
+    that ties the committed profiles to the kernels."""
+    on_disk = sorted(n for n in os.listdir(build.CSRC) if n.endswith((".cpp", ".hip")))
+    assert sorted(build.SOURCES) == on_disk
+    assert set(build.SOURCE_FLAGS) <= set(build.SOURCES)
+    h = build.source_hash()
+    monkeypatch.setitem(build.SOURCE_FLAGS, "kernels_ds_5_4.hip", [])
+    assert build.source_hash() != h
+
+
 def test_kernel_names_are_shortened():
     n = "void mbc::(anonymous namespace)::ds_kernel<float, 3, 3, 1, 6, 256>(mbc::(anonymous namespace)::BwdArgs)"
     assert prof_summary._short(n) == "ds_kernel<float, 3, 3, 1, 6, 256>"
