@@ -74,18 +74,16 @@ __device__ __forceinline__ void tile_levels(const FlavTabs<NU, QMAX, NT>& tu, co
 // S-bar partials of a level-K row: bin j collects the columns C that contain
 // j.  Levels K <= 2 have short bins (at most 11 entries): one lane per bin,
 // thread t takes bin t % 12 of row group t / 12 (21 rows side by side).
-// Levels K >= 3: L = 16 lanes per bin, or 32 for levels K >= 4 in
-// workgroups of 384 threads or more; thread t takes bin t / L (t < 12 L) of
-// one row, lane t % L holds entries l, l + L, ...; 32 lanes halve the
-// entries per lane, so the 3He rows' bins (up to 224 entries) take 7
-// registers, while level 3 (at most 55 entries) stays on 16 lanes, where
-// each bin's sum needs one fewer cross-lane step.
+// Levels K >= 3: L = 16 lanes per bin (workgroups of fewer than 384 threads)
+// or 32 (384 threads or more), thread t takes bin t / L (t < 12 L) of one
+// row, lane t % L holds entries l, l + L, ...; 32 lanes halve the entries
+// per lane, so the 3He rows' bins (up to 224 entries) take 7 registers.
 // Level 2 with 384 threads or more: 4 lanes per bin (3 entries each).
 __host__ __device__ constexpr int bin_lanes(int k, int nt) {
-  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 4 : 1) : (nt >= 384 ? (k == 3 ? 16 : 32) : 16));
+  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 4 : 1) : (nt >= 384 ? 32 : 16));
 }
 __host__ __device__ constexpr int bin_regs(int k, int nt) {
-  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 3 : 11) : (nt >= 384 ? (k == 3 ? 4 : (k == 4 ? 6 : 7)) : (k == 3 ? 4 : (k == 4 ? 11 : 14))));
+  return k == 1 ? 1 : (k == 2 ? (nt >= 384 ? 3 : 11) : (nt >= 384 ? (k == 3 ? 2 : (k == 4 ? 6 : 7)) : (k == 3 ? 4 : (k == 4 ? 11 : 14))));
 }
 
 // Sum over the 4 lanes of each quad (every lane receives the quad's sum).
