@@ -217,3 +217,24 @@ def test_mbc_log_writes_one_line_per_handle():
     env["MBC_LOG"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
     assert "[mbc]" not in r.stderr
+
+
+HE3_BATCH = [dict(op="HE3_I", snk_spin=j, src_spin=j) for j in range(4)] + \
+            [dict(op="HE3_II", snk_spin=j, src_spin=j, sign_mode="r2") for j in range(4)]
+
+
+@pytest.mark.parametrize("ods", [[dict(op="DI")], HE3_BATCH], ids=["DI", "He3_batch"])
+def test_bench_plans_fit_the_kernel_instantiations(ods):
+    """mbc_plan_create checks a compiled plan against the kernels' compiled
+    limits (source keys per thread, columns per level, dW keys per tile, the
+    S-bar bins' lanes x registers, source-key lists) before it touches the
+    device: the bench workloads' plans must pass in both precisions (without
+    a device the call then fails at the device lookup, never as unsupported)."""
+    L = B.lib()
+    s = IndexSet(ods)
+    for prec in (B.F64, B.F32C):
+        h = ctypes.c_void_p()
+        st = L.mbc_plan_create(s._h, prec, None, ctypes.byref(h))
+        assert st != B.MBC_ERR_UNSUPPORTED, L.mbc_last_error()
+        if st == B.MBC_OK:
+            L.mbc_plan_destroy(h)
